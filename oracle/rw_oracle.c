@@ -1,0 +1,719 @@
+/*
+ * rw_oracle.c - FP64 CPU reference ("oracle") for the random-walk subsurface
+ * transport through a mixture of K homogeneous media.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the HIP implementation; both sides
+ * implement the same written estimator independently.
+ *
+ * What is computed (paper, Sec. 4.1 "Subsurface Scattering by
+ * Mixtures-of-Media"): the BSSRDF of a K-medium mixture is the w_k-weighted sum
+ * of the per-medium path integrals (second form of eq. sss), and a random walk
+ * realises it by choosing the medium once, before the walk starts, with
+ * probability w_k (same section, last paragraph; Sec. 7 "Results", which also
+ * states that the pdf of that choice cancels the weight).  Each per-medium walk
+ * samples the path-integral contribution of eq. sss: transmittance
+ * T = exp(-sigma_t s) between vertices and the phase function scaled by the
+ * albedo at every scattering vertex.  Under normal incidence the result is the
+ * radial profile R_d(r) = R * P_d(r) of eq. radsss, tallied here as the total
+ * diffuse reflectance R and a histogram of exit radii.  The boundary is a
+ * smooth Fresnel interface (Sec. 8, "Limitations").
+ *
+ * The paper fixes no walk details.  The readings used (written conventions,
+ * identical on the GPU side):
+ *   - pencil beam at r = 0 along +z (z = depth), path weight starts at
+ *     1 - F(0); specular F(0) is not part of R;
+ *   - medium k = first index with u0 < c_k (c = cumulative weights, c_{K-1}=1);
+ *   - free flight s = -ln(u0)/sigma_t;  top hit when uz < 0 and z + s*uz <= 0;
+ *   - boundary: unpolarised Fresnel, total internal reflection when
+ *     n*sin(theta_i) >= 1, reflect when u3 < F (specular, uz -> -uz);
+ *   - collision: W *= alpha (implicit capture), Russian roulette when
+ *     W < rr_weight (survive when u3 < rr_survive, W /= rr_survive);
+ *   - Henyey-Greenstein cos(theta) by inversion of its CDF with u1, azimuth
+ *     phi = 2*pi*u2 measured from the first tangent of the Duff et al. (2017)
+ *     orthonormal frame of the current direction;
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *     counter = (vertex, path, unit, stream tag), one block of four words per
+ *     vertex, word -> ((w >> 9) + 0.5) * 2^-23 in (0, 1);
+ *   - exit radius binned in n_bins log-spaced bins over [r_min, r_max) with an
+ *     underflow slot 0 and an overflow slot n_bins + 1.
+ * The adjoint uses the score-function (likelihood-ratio) estimator of the
+ * path density, evaluated by replaying the same random numbers.
+ *
+ * Everything is FP64.  Threads split the paths of a unit into fixed ranges;
+ * partial sums are merged in range order, so results do not depend on the
+ * thread count.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_K 4
+#define ORC_RANGE 16384 /* paths per task: fixed, so merging is deterministic */
+
+/* ------------------------------------------------------------------------- */
+/* Public structs (mirrored by oracle/oracle.py with ctypes)                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_media;      /* K, 1..4 */
+  int32_t n_bins;       /* radial bins (slots 0 and n_bins+1 are under/overflow) */
+  double n_rel;         /* refractive index of the medium over the outside */
+  double slab_mm;       /* thickness; <= 0 means semi-infinite */
+  double r_min_mm, r_max_mm;
+  double rr_weight;     /* Russian roulette threshold; <= 0 disables it */
+  double rr_survive;    /* survival probability of the roulette */
+  int64_t max_vertices; /* vertex cap per path */
+  int32_t analog;       /* 1: analog absorption, unit weights, no roulette */
+  int32_t order_filter; /* > 0: tally only paths with this many collisions */
+} orc_geometry;
+
+/* per-unit tally layout of orc_forward: 8 doubles */
+enum {
+  T_SUMX = 0,    /* sum of contributions exiting the top surface */
+  T_SUMX2 = 1,   /* sum of their squares */
+  T_SUMT = 2,    /* weight leaving through the bottom of a slab */
+  T_SUMA = 3,    /* absorbed weight */
+  T_SPEC = 4,    /* analog mode: paths specularly reflected at entry */
+  T_CAPPED = 5,  /* paths that hit the vertex cap */
+  T_KILLED = 6,  /* paths ended by roulette */
+  T_NEXIT = 7,   /* number of paths tallied at the top */
+  T_NSLOTS = 8
+};
+
+/* path end kinds (also written to traces) */
+enum {
+  END_NONE = 0,
+  END_EXIT_TOP = 1,
+  END_EXIT_BOTTOM = 2,
+  END_RR_KILLED = 3,
+  END_CAPPED = 4,
+  END_ABSORBED = 5,   /* analog only */
+  END_SPECULAR = 6,   /* analog only */
+  END_NO_BLOCKS = 7   /* injected-word traces that ran out of words */
+};
+
+/* trace event codes */
+enum {
+  EV_START = 0,
+  EV_COLLIDE = 1,
+  EV_REFLECT = 2,
+  EV_EXIT_TOP = 3,
+  EV_EXIT_BOTTOM = 4,
+  EV_RR_KILL = 5,
+  EV_CAP = 6,
+  EV_ABSORB = 7
+};
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 products with the    */
+/* published multipliers, key bumped by the published Weyl constants.         */
+/* ------------------------------------------------------------------------- */
+static void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                          uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* word -> uniform in (0,1): odd multiples of 2^-24, exact in FP32 and FP64 */
+static double u01(uint32_t w) { return ((double)(w >> 9) + 0.5) * 0x1p-23; }
+
+/* ------------------------------------------------------------------------- */
+/* Physics pieces                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Unpolarised Fresnel reflectance for light inside the medium (index n
+ * relative to the outside) hitting the surface with cos(theta_i) = cos_i.
+ * Average of the s and p amplitude-squared coefficients; returns 1 under total
+ * internal reflection (n*sin(theta_i) >= 1). */
+static double fresnel(double cos_i, double n) {
+  double sin_i2 = 1.0 - cos_i * cos_i;
+  if (sin_i2 < 0.0) sin_i2 = 0.0;
+  double sin_t2 = n * n * sin_i2;
+  if (sin_t2 >= 1.0) return 1.0;
+  double cos_t = sqrt(1.0 - sin_t2);
+  double rs = (n * cos_i - cos_t) / (n * cos_i + cos_t);
+  double rp = (cos_i - n * cos_t) / (cos_i + n * cos_t);
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+/* Henyey-Greenstein: cos(theta) by inverting the CDF of
+ * p(mu) = (1 - g^2) / (2 (1 + g^2 - 2 g mu)^{3/2}) at u (textbook form). */
+static double hg_cos(double g, double u) {
+  double mu;
+  if (fabs(g) < 1e-9) {
+    mu = 2.0 * u - 1.0;
+  } else {
+    double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+    mu = (1.0 + g * g - t * t) / (2.0 * g);
+  }
+  if (mu > 1.0) mu = 1.0;
+  if (mu < -1.0) mu = -1.0;
+  return mu;
+}
+
+/* d ln p_HG(mu; g) / d g */
+static double hg_dlog_dg(double g, double mu) {
+  return -2.0 * g / (1.0 - g * g) + 3.0 * (mu - g) / (1.0 + g * g - 2.0 * g * mu);
+}
+
+/* Orthonormal frame (t1, t2, d) of a unit vector d (Duff, Burgess, Christensen,
+ * Hery, Kensler, Liani, Villemin, "Building an Orthonormal Basis, Revisited",
+ * JCGT 6(1), 2017). */
+static void frame(const double d[3], double t1[3], double t2[3]) {
+  double s = copysign(1.0, d[2]);
+  double a = -1.0 / (s + d[2]);
+  double b = d[0] * d[1] * a;
+  t1[0] = 1.0 + s * d[0] * d[0] * a;
+  t1[1] = s * b;
+  t1[2] = -s * d[0];
+  t2[0] = b;
+  t2[1] = s + d[1] * d[1] * a;
+  t2[2] = -d[1];
+}
+
+/* new direction at polar cosine mu from d and azimuth phi (radians) from t1 */
+static void scatter_dir(double d[3], double mu, double phi) {
+  double t1[3], t2[3];
+  frame(d, t1, t2);
+  double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double a = st * cos(phi), b = st * sin(phi);
+  double nd[3];
+  for (int i = 0; i < 3; ++i) nd[i] = a * t1[i] + b * t2[i] + mu * d[i];
+  d[0] = nd[0]; d[1] = nd[1]; d[2] = nd[2];
+}
+
+/* radial slot: 0 underflow, 1..n_bins log bins, n_bins+1 overflow */
+static int bin_slot(double r, const orc_geometry* g) {
+  if (!(r >= g->r_min_mm)) return 0;
+  if (r >= g->r_max_mm) return g->n_bins + 1;
+  double t = log(r / g->r_min_mm) / log(g->r_max_mm / g->r_min_mm);
+  int b = (int)floor(t * g->n_bins);
+  if (b < 0) b = 0;
+  if (b > g->n_bins - 1) b = g->n_bins - 1;
+  return b + 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One path                                                                    */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int K;
+  double sigma_t[ORC_MAX_K], albedo[ORC_MAX_K], g[ORC_MAX_K], w[ORC_MAX_K];
+  double cum[ORC_MAX_K];
+} unit_params;
+
+typedef struct {
+  /* Philox source */
+  uint32_t key[2];
+  uint32_t path, unit, tag;
+  /* injected source (traces): words[v*4 + i], v < n_blocks */
+  const uint32_t* words;
+  int64_t n_blocks;
+} block_source;
+
+typedef struct {
+  int end;
+  int k;
+  int slot;
+  double x;        /* contribution when the path leaves the top (or bottom) */
+  double r;
+  double absorbed;
+  int64_t n_vert;
+  int64_t n_coll;
+  double L;        /* total length of all flight segments */
+  double Sg;       /* sum of d ln p_HG / d g over the scattering vertices */
+} path_result;
+
+/* fetch block v; returns 0 when an injected source has run out */
+static int get_block(const block_source* src, int64_t v, double u[4]) {
+  uint32_t w[4];
+  if (src->words) {
+    if (v >= src->n_blocks) return 0;
+    for (int i = 0; i < 4; ++i) w[i] = src->words[v * 4 + i];
+  } else {
+    uint32_t ctr[4] = {(uint32_t)v, src->path, src->unit, src->tag};
+    philox4x32_10(ctr, src->key, w);
+  }
+  for (int i = 0; i < 4; ++i) u[i] = u01(w[i]);
+  return 1;
+}
+
+static void put_event(double* ev, int64_t max_ev, int64_t idx, int code,
+                      const double p[3], const double d[3], double W) {
+  if (!ev || idx >= max_ev) return;
+  double* e = ev + idx * 8;
+  e[0] = code; e[1] = p[0]; e[2] = p[1]; e[3] = p[2];
+  e[4] = d[0]; e[5] = d[1]; e[6] = d[2]; e[7] = W;
+}
+
+static void walk(const unit_params* up, const orc_geometry* geo,
+                 const block_source* src, path_result* res,
+                 double* events, int64_t max_events) {
+  const double n = geo->n_rel;
+  const double F0 = ((n - 1.0) / (n + 1.0)) * ((n - 1.0) / (n + 1.0));
+  const int slab = geo->slab_mm > 0.0;
+  double u[4];
+  memset(res, 0, sizeof(*res));
+  res->slot = -1;
+
+  /* vertex 0: medium choice (and the analog specular test) */
+  if (!get_block(src, 0, u)) { res->end = END_NO_BLOCKS; return; }
+  int k = up->K - 1;
+  for (int j = 0; j < up->K; ++j) {
+    if (u[0] < up->cum[j]) { k = j; break; }
+  }
+  res->k = k;
+  const double sig = up->sigma_t[k], alb = up->albedo[k], g = up->g[k];
+
+  double p[3] = {0.0, 0.0, 0.0};
+  double d[3] = {0.0, 0.0, 1.0};
+  double W;
+  if (geo->analog) {
+    if (u[1] < F0) {
+      res->end = END_SPECULAR;
+      put_event(events, max_events, 0, EV_START, p, d, 0.0);
+      return;
+    }
+    W = 1.0;
+  } else {
+    W = 1.0 - F0;
+  }
+  put_event(events, max_events, 0, EV_START, p, d, W);
+
+  for (int64_t v = 1;; ++v) {
+    if (v > geo->max_vertices) {
+      res->end = END_CAPPED;
+      put_event(events, max_events, v, EV_CAP, p, d, W);
+      return;
+    }
+    if (!get_block(src, v, u)) { res->end = END_NO_BLOCKS; return; }
+    res->n_vert = v;
+    double s = -log(u[0]) / sig;
+
+    /* boundary crossings along this flight */
+    int hit = 0; /* 1 top, 2 bottom */
+    double db = 0.0;
+    if (d[2] < 0.0 && p[2] + s * d[2] <= 0.0) {
+      hit = 1;
+      db = -p[2] / d[2];
+    } else if (slab && d[2] > 0.0 && p[2] + s * d[2] >= geo->slab_mm) {
+      hit = 2;
+      db = (geo->slab_mm - p[2]) / d[2];
+    }
+
+    if (hit) {
+      res->L += db;
+      p[0] += db * d[0];
+      p[1] += db * d[1];
+      p[2] = (hit == 1) ? 0.0 : geo->slab_mm;
+      double F = fresnel(fabs(d[2]), n);
+      if (u[3] < F) {
+        d[2] = -d[2];
+        put_event(events, max_events, v, EV_REFLECT, p, d, W);
+        continue;
+      }
+      res->x = W;
+      if (hit == 1) {
+        res->end = END_EXIT_TOP;
+        res->r = sqrt(p[0] * p[0] + p[1] * p[1]);
+        res->slot = bin_slot(res->r, geo);
+        put_event(events, max_events, v, EV_EXIT_TOP, p, d, W);
+      } else {
+        res->end = END_EXIT_BOTTOM;
+        put_event(events, max_events, v, EV_EXIT_BOTTOM, p, d, W);
+      }
+      return;
+    }
+
+    /* collision */
+    res->L += s;
+    for (int i = 0; i < 3; ++i) p[i] += s * d[i];
+    res->n_coll += 1;
+    if (geo->analog) {
+      if (!(u[3] < alb)) {
+        res->absorbed += 1.0;
+        res->end = END_ABSORBED;
+        put_event(events, max_events, v, EV_ABSORB, p, d, W);
+        return;
+      }
+    } else {
+      res->absorbed += W * (1.0 - alb);
+      W *= alb;
+      if (geo->rr_weight > 0.0 && W < geo->rr_weight) {
+        if (u[3] < geo->rr_survive) {
+          W /= geo->rr_survive;
+        } else {
+          res->end = END_RR_KILLED;
+          put_event(events, max_events, v, EV_RR_KILL, p, d, 0.0);
+          return;
+        }
+      }
+    }
+    double mu = hg_cos(g, u[1]);
+    res->Sg += hg_dlog_dg(g, mu);
+    scatter_dir(d, mu, 2.0 * M_PI * u[2]);
+    put_event(events, max_events, v, EV_COLLIDE, p, d, W);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Work split                                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_geometry* geo;
+  int K;
+  const double *sigma_t, *albedo, *g, *w;
+  int64_t n_units;
+  const int64_t* paths;
+  uint64_t seed;
+  uint32_t tag;
+  /* adjoint inputs (NULL for the forward) */
+  int adjoint;
+  const double* cot_R;
+  const double* cot_bins;
+  int want_jac;
+  /* task table */
+  int64_t n_tasks;
+  int64_t* task_unit;
+  int64_t* task_begin;
+  int64_t* task_end;
+  double* part;        /* n_tasks * part_len */
+  int64_t part_len;
+  int64_t next_task;
+  pthread_mutex_t lock;
+  int status;
+} job_t;
+
+static int load_unit(const job_t* job, int64_t u, unit_params* up) {
+  int K = job->K;
+  up->K = K;
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    up->sigma_t[k] = job->sigma_t[(int64_t)k * job->n_units + u];
+    up->albedo[k] = job->albedo[(int64_t)k * job->n_units + u];
+    up->g[k] = job->g[(int64_t)k * job->n_units + u];
+    up->w[k] = job->w[(int64_t)k * job->n_units + u];
+    acc += up->w[k];
+    up->cum[k] = acc;
+  }
+  up->cum[K - 1] = 1.0;
+  for (int k = 0; k < K; ++k) {
+    if (!(up->sigma_t[k] > 0.0) || !(up->albedo[k] >= 0.0) || !(up->albedo[k] <= 1.0) ||
+        !(fabs(up->g[k]) < 1.0) || !(up->w[k] >= 0.0))
+      return -1;
+  }
+  if (!(fabs(acc - 1.0) <= 1e-5)) return -1;
+  return 0;
+}
+
+/* partial layout per task:
+ *   forward: [T_NSLOTS] + bins[(nb+2)*2] + vertices(1)
+ *   adjoint: grad[4K] + sumsq[4K] + (jac: jacR[4K] + jacB[(nb+2)*4K])      */
+static void run_task(job_t* job, int64_t t) {
+  const orc_geometry* geo = job->geo;
+  const int nb = geo->n_bins;
+  const int K = job->K;
+  const int P = 4 * K;
+  int64_t u = job->task_unit[t];
+  double* part = job->part + t * job->part_len;
+  unit_params up;
+  if (load_unit(job, u, &up) != 0) {
+    pthread_mutex_lock(&job->lock);
+    job->status |= 1;
+    pthread_mutex_unlock(&job->lock);
+    return;
+  }
+  block_source src;
+  memset(&src, 0, sizeof(src));
+  src.key[0] = (uint32_t)job->seed;
+  src.key[1] = (uint32_t)(job->seed >> 32);
+  src.unit = (uint32_t)u;
+  src.tag = job->tag;
+  double score[4 * ORC_MAX_K];
+  for (int64_t pth = job->task_begin[t]; pth < job->task_end[t]; ++pth) {
+    path_result r;
+    src.path = (uint32_t)pth;
+    walk(&up, geo, &src, &r, NULL, 0);
+    int tallied_top = (r.end == END_EXIT_TOP) &&
+                      (geo->order_filter <= 0 || r.n_coll == geo->order_filter);
+    if (!job->adjoint) {
+      double* tal = part;
+      double* bins = part + T_NSLOTS;
+      double* vert = bins + (int64_t)(nb + 2) * 2;
+      if (tallied_top) {
+        tal[T_SUMX] += r.x;
+        tal[T_SUMX2] += r.x * r.x;
+        tal[T_NEXIT] += 1.0;
+        bins[r.slot * 2 + 0] += r.x;
+        bins[r.slot * 2 + 1] += r.x * r.x;
+      }
+      if (r.end == END_EXIT_BOTTOM) tal[T_SUMT] += r.x;
+      tal[T_SUMA] += r.absorbed;
+      if (r.end == END_SPECULAR) tal[T_SPEC] += 1.0;
+      if (r.end == END_CAPPED) tal[T_CAPPED] += 1.0;
+      if (r.end == END_RR_KILLED) tal[T_KILLED] += 1.0;
+      vert[0] += (double)r.n_vert;
+    } else {
+      if (!tallied_top || r.x == 0.0) continue;
+      for (int j = 0; j < P; ++j) score[j] = 0.0;
+      int k = r.k;
+      score[k] = (double)r.n_coll / up.sigma_t[k] - r.L;
+      score[K + k] = (r.n_coll == 0) ? 0.0 : (double)r.n_coll / up.albedo[k];
+      score[2 * K + k] = r.Sg;
+      for (int j = 0; j < K; ++j) score[3 * K + j] = (j == k ? 1.0 : 0.0) - up.w[j];
+      double cot = job->cot_R ? job->cot_R[u] : 0.0;
+      if (job->cot_bins) cot += job->cot_bins[u * (nb + 2) + r.slot];
+      double* grad = part;
+      double* sumsq = part + P;
+      for (int j = 0; j < P; ++j) {
+        double c = r.x * cot * score[j];
+        grad[j] += c;
+        sumsq[j] += c * c;
+      }
+      if (job->want_jac) {
+        double* jacR = part + 2 * P;
+        double* jacB = jacR + P;
+        for (int j = 0; j < P; ++j) {
+          jacR[j] += r.x * score[j];
+          jacB[(int64_t)r.slot * P + j] += r.x * score[j];
+        }
+      }
+    }
+  }
+}
+
+static void* worker(void* arg) {
+  job_t* job = (job_t*)arg;
+  for (;;) {
+    pthread_mutex_lock(&job->lock);
+    int64_t t = job->next_task++;
+    pthread_mutex_unlock(&job->lock);
+    if (t >= job->n_tasks) break;
+    run_task(job, t);
+  }
+  return NULL;
+}
+
+static int run_job(job_t* job, int n_threads) {
+  int64_t n_tasks = 0;
+  for (int64_t u = 0; u < job->n_units; ++u) {
+    if (job->paths[u] < 0) return -1;
+    n_tasks += (job->paths[u] + ORC_RANGE - 1) / ORC_RANGE;
+  }
+  job->n_tasks = n_tasks;
+  job->task_unit = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_tasks + 1));
+  job->task_begin = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_tasks + 1));
+  job->task_end = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_tasks + 1));
+  job->part = (double*)calloc((size_t)(n_tasks + 1) * (size_t)job->part_len, sizeof(double));
+  if (!job->task_unit || !job->task_begin || !job->task_end || !job->part) {
+    free(job->task_unit); free(job->task_begin); free(job->task_end); free(job->part);
+    return -2;
+  }
+  int64_t t = 0;
+  for (int64_t u = 0; u < job->n_units; ++u) {
+    for (int64_t b = 0; b < job->paths[u]; b += ORC_RANGE) {
+      job->task_unit[t] = u;
+      job->task_begin[t] = b;
+      job->task_end[t] = (b + ORC_RANGE < job->paths[u]) ? b + ORC_RANGE : job->paths[u];
+      ++t;
+    }
+  }
+  job->next_task = 0;
+  job->status = 0;
+  pthread_mutex_init(&job->lock, NULL);
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  pthread_t th[256];
+  int started = 0;
+  for (int i = 1; i < n_threads; ++i) {
+    if (pthread_create(&th[i], NULL, worker, job) != 0) break;
+    started = i;
+  }
+  worker(job);
+  for (int i = 1; i <= started; ++i) pthread_join(th[i], NULL);
+  pthread_mutex_destroy(&job->lock);
+  return job->status ? -3 : 0;
+}
+
+static void free_job(job_t* job) {
+  free(job->task_unit); free(job->task_begin); free(job->task_end); free(job->part);
+}
+
+static int check_geometry(const orc_geometry* g) {
+  if (!g) return -1;
+  if (g->n_media < 1 || g->n_media > ORC_MAX_K) return -1;
+  if (g->n_bins < 1 || g->n_bins > 4096) return -1;
+  if (!(g->r_min_mm > 0.0) || !(g->r_max_mm > g->r_min_mm)) return -1;
+  if (!(g->n_rel > 0.0)) return -1;
+  if (g->max_vertices < 1) return -1;
+  if (!g->analog && g->rr_weight > 0.0 && !(g->rr_survive > 0.0 && g->rr_survive <= 1.0))
+    return -1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exported API                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Forward tallies.  Parameters are SoA [K][n_units].  Outputs (zero-filled
+ * here):  tally[n_units][8] (layout T_*), bins[n_units][n_bins+2][2] (sum x,
+ * sum x^2), vertices[n_units].  Returns 0, -1 bad arguments, -2 no memory,
+ * -3 invalid unit parameters. */
+int orc_forward(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                const double* g, const double* w, int64_t n_units, const int64_t* paths,
+                uint64_t seed, uint32_t tag, int n_threads, double* tally, double* bins,
+                int64_t* vertices) {
+  if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || !paths || n_units < 0 ||
+      !tally || !bins || !vertices)
+    return -1;
+  const int nb = geo->n_bins;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = geo->n_media;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
+  job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.part_len = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
+  int rc = run_job(&job, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(tally, 0, sizeof(double) * (size_t)n_units * T_NSLOTS);
+  memset(bins, 0, sizeof(double) * (size_t)n_units * (size_t)(nb + 2) * 2);
+  for (int64_t u = 0; u < n_units; ++u) vertices[u] = 0;
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    int64_t u = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int i = 0; i < T_NSLOTS; ++i) tally[u * T_NSLOTS + i] += part[i];
+    for (int i = 0; i < (nb + 2) * 2; ++i) bins[u * (nb + 2) * 2 + i] += part[T_NSLOTS + i];
+    vertices[u] += (int64_t)part[T_NSLOTS + (nb + 2) * 2];
+  }
+  free_job(&job);
+  return rc;
+}
+
+/* Score-function gradient of the cotangent-weighted top tallies:
+ *   grad[u][j] = sum over paths of x * (cot_R[u] + cot_bins[u][slot]) * score_j
+ * with score layout [sigma_t(K) | albedo(K) | g(K) | logits(K)] (logits of a
+ * softmax that reproduces w).  grad_sumsq holds the sum of squares of the
+ * per-path terms.  cot_bins may be NULL.  When jac_R / jac_bins are non-NULL
+ * they receive the per-unit Jacobian sums sum x*score_j, for the total and per
+ * slot ([n_units][4K] and [n_units][n_bins+2][4K]).  All sums are raw (not
+ * divided by the path count). */
+int orc_adjoint(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                const double* g, const double* w, int64_t n_units, const int64_t* paths,
+                uint64_t seed, uint32_t tag, int n_threads, const double* cot_R,
+                const double* cot_bins, double* grad, double* grad_sumsq, double* jac_R,
+                double* jac_bins) {
+  if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || !paths || n_units < 0 ||
+      !grad || !grad_sumsq)
+    return -1;
+  if ((jac_R == NULL) != (jac_bins == NULL)) return -1;
+  const int nb = geo->n_bins;
+  const int P = 4 * geo->n_media;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = geo->n_media;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
+  job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.adjoint = 1; job.cot_R = cot_R; job.cot_bins = cot_bins;
+  job.want_jac = jac_R != NULL;
+  job.part_len = 2 * P + (job.want_jac ? P + (int64_t)(nb + 2) * P : 0);
+  int rc = run_job(&job, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(grad, 0, sizeof(double) * (size_t)n_units * P);
+  memset(grad_sumsq, 0, sizeof(double) * (size_t)n_units * P);
+  if (job.want_jac) {
+    memset(jac_R, 0, sizeof(double) * (size_t)n_units * P);
+    memset(jac_bins, 0, sizeof(double) * (size_t)n_units * (size_t)(nb + 2) * P);
+  }
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    int64_t u = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int j = 0; j < P; ++j) {
+      grad[u * P + j] += part[j];
+      grad_sumsq[u * P + j] += part[P + j];
+    }
+    if (job.want_jac) {
+      for (int j = 0; j < P; ++j) jac_R[u * P + j] += part[2 * P + j];
+      for (int i = 0; i < (nb + 2) * P; ++i)
+        jac_bins[u * (int64_t)(nb + 2) * P + i] += part[3 * P + i];
+    }
+  }
+  free_job(&job);
+  return rc;
+}
+
+/* Per-path replay with injected Philox output words (or Philox itself when
+ * words == NULL, then path index p of unit `unit`).  One unit (parameters
+ * sigma_t[K], albedo[K], g[K], w[K]).  words: [n_paths][n_blocks][4].
+ * events: [n_paths][n_blocks][8] = (code, x, y, z, ux, uy, uz, W) per vertex,
+ * zero-filled here; path_out: [n_paths][8] = (end, k, slot, x, r, n_vert,
+ * n_coll, absorbed); path_adj: [n_paths][2] = (L, Sg) or NULL. */
+int orc_trace(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+              const double* g, const double* w, const uint32_t* words, int64_t n_paths,
+              int64_t n_blocks, uint64_t seed, uint32_t unit, uint32_t tag, double* events,
+              double* path_out, double* path_adj) {
+  if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || n_paths < 0 ||
+      n_blocks < 1 || !path_out)
+    return -1;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.K = geo->n_media; job.n_units = 1;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
+  unit_params up;
+  if (load_unit(&job, 0, &up) != 0) return -3;
+  if (events) memset(events, 0, sizeof(double) * (size_t)n_paths * (size_t)n_blocks * 8);
+  for (int64_t p = 0; p < n_paths; ++p) {
+    block_source src;
+    memset(&src, 0, sizeof(src));
+    src.key[0] = (uint32_t)seed;
+    src.key[1] = (uint32_t)(seed >> 32);
+    src.path = (uint32_t)p;
+    src.unit = unit;
+    src.tag = tag;
+    if (words) {
+      src.words = words + p * n_blocks * 4;
+      src.n_blocks = n_blocks;
+    }
+    path_result r;
+    walk(&up, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks);
+    double* o = path_out + p * 8;
+    o[0] = r.end; o[1] = r.k; o[2] = r.slot; o[3] = r.x; o[4] = r.r;
+    o[5] = (double)r.n_vert; o[6] = (double)r.n_coll; o[7] = r.absorbed;
+    if (path_adj) {
+      path_adj[p * 2 + 0] = r.L;
+      path_adj[p * 2 + 1] = r.Sg;
+    }
+  }
+  return 0;
+}
+
+/* Building blocks exported for their own pins. */
+void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+double orc_u01(uint32_t w) { return u01(w); }
+double orc_fresnel(double cos_i, double n) { return fresnel(cos_i, n); }
+double orc_hg_cos(double g, double u) { return hg_cos(g, u); }
+double orc_hg_dlog_dg(double g, double mu) { return hg_dlog_dg(g, mu); }
+void orc_frame(const double* d, double* t1, double* t2) { frame(d, t1, t2); }
+void orc_scatter_dir(double* d, double mu, double phi) { scatter_dir(d, mu, phi); }
+int orc_bin_slot(double r, const orc_geometry* geo) { return bin_slot(r, geo); }

@@ -1,0 +1,338 @@
+"""Checks that pin the FP64 oracle's random walk to things other than itself.
+
+Each ``check_*`` returns (ok: bool, detail: str) so that the same battery runs
+at full size in test_oracle_transport.py and at small size against copies of
+the oracle with planted mistakes in test_oracle_mutations.py.
+
+What pins what:
+  plane albedo     - total R against Chandrasekhar's 1 - H(1) sqrt(1-alpha)
+  second moment    - sum x^2 / N against R(alpha^2) (x = alpha^n_coll without
+                     roulette, so E[x^2](alpha) = R(alpha^2)), SE from R(alpha^4)
+  single scatter   - order-1 tallies (total and per annulus) against the 1-D
+                     quadrature for any g and Fresnel index
+  energy           - slab without roulette: R + T + A = 1 - F(0) per path
+  analog/weighted  - two different estimators of the same R agree
+  Beer-Lambert     - purely absorbing slab: T = exp(-sigma_t d), R = 0
+  mixture          - R_mix = sum_k w_k R(alpha_k) (paper Sec. 4.1, eq. sss)
+  special case     - w = (1, 0, 0) reproduces the one-medium walk bit for bit
+  scale invariance - sigma_t -> c sigma_t on the same random numbers leaves R
+                     unchanged and divides every exit radius by c (eq. separability)
+  trace invariants - reflection law, straight flights, exponential first flight,
+                     Henyey-Greenstein scattering cosines, uniform azimuth
+  adjoint          - closed-form dR/dalpha, dR/dsigma_t = 0, mixture gradients,
+                     and common-random-number central differences of the forward
+  brute force      - a deterministic grid of injected words averages to the
+                     single-scattering closed form
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import integrate, stats
+
+from oracle import closed_forms as cf
+from oracle import oracle as O
+from tests._stats import accept_histogram, histogram_z, mean_se
+
+
+def _r(ok, detail):
+    return bool(ok), detail
+
+
+def check_plane_albedo(alphas=(0.5, 0.7, 0.9, 0.99), paths=1 << 18, seed=1, k=3.0, rel=None):
+    alphas = np.asarray(alphas, np.float64)
+    n = alphas.size
+    geo = O.Geometry(n_media=1, n_rel=1.0)
+    tal, _, _ = O.forward(geo, np.ones(n), alphas, np.zeros(n), np.ones(n), paths, seed)
+    m, se = mean_se(tal[:, 0], tal[:, 1], paths)
+    ref = np.array([cf.R_plane(a) for a in alphas])
+    z = (m - ref) / se
+    ok = np.all(np.abs(z) <= k)
+    if rel is not None:
+        ok = ok and np.all(np.abs(m - ref) <= rel * ref)
+    return _r(ok, f"z={np.round(z, 2)} rel={np.round((m - ref) / ref, 5)}")
+
+
+def check_second_moment(alpha=0.8, paths=1 << 18, seed=2, k=3.0):
+    # without roulette the walk only ends at the surface and path lengths are
+    # heavy-tailed; a path still inside after 4096 vertices carries
+    # x <= alpha^4095, which is 0 in FP64 for alpha <= 0.8, so the cap (which
+    # scores 0) does not bias E[x^2]
+    geo = O.Geometry(n_media=1, n_rel=1.0, rr_weight=0.0, max_vertices=4096)
+    tal, _, _ = O.forward(geo, [1.0], [alpha], [0.0], [1.0], paths, seed)
+    m2 = tal[0, 1] / paths
+    ref = cf.R_plane(alpha * alpha)
+    se = math.sqrt(max(cf.R_plane(alpha ** 4) - ref * ref, 0.0) / paths)
+    z = (m2 - ref) / se
+    return _r(abs(z) <= k, f"E[x^2] z={z:.2f}")
+
+
+def check_single_scatter(g=0.5, n=1.4, sigma_t=2.0, alpha=0.9, paths=1 << 18, seed=3, k=3.0,
+                         n_bins=64):
+    geo = O.Geometry(n_media=1, n_rel=n, order_filter=1, n_bins=n_bins)
+    tal, bins, _ = O.forward(geo, [sigma_t], [alpha], [g], [1.0], paths, seed)
+    m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+    ref = cf.R1_total(alpha, g, n)
+    z = (m - ref) / se
+    slots = cf.R1_slots(alpha, g, n, sigma_t, n_bins, geo.r_min_mm, geo.r_max_mm)
+    bm, bse = mean_se(bins[0, :, 0], bins[0, :, 1], paths)
+    hits = bins[0, :, 0] ** 2 / np.maximum(bins[0, :, 1], 1e-300)  # effective hit count
+    zb = histogram_z(bm, bse, slots, 0.0, mask=hits >= 30)
+    okh, chi2, lim = accept_histogram(zb)
+    return _r(abs(z) <= k and okh, f"total z={z:.2f}; bins chi2={chi2:.1f}/{lim:.1f} "
+              f"n={zb.size} max|z|={np.max(np.abs(zb)) if zb.size else 0:.2f}")
+
+
+def check_energy_exact(paths=1 << 14, seed=4):
+    n = 1.4
+    geo = O.Geometry(n_media=1, n_rel=n, slab_mm=2.0, rr_weight=0.0)
+    tal, _, _ = O.forward(geo, [1.5], [0.9], [0.8], [1.0], paths, seed)
+    F0 = ((n - 1) / (n + 1)) ** 2
+    tot = (tal[0, 0] + tal[0, 2] + tal[0, 3]) / paths
+    capped = tal[0, 5]
+    return _r(abs(tot - (1 - F0)) < 1e-10 and capped == 0, f"R+T+A={tot!r} vs {1 - F0!r}")
+
+
+def check_analog_vs_weighted(paths=1 << 18, seed=5, k=3.0):
+    n = 1.4
+    base = dict(n_media=1, n_rel=n, slab_mm=3.0)
+    args = ([2.0], [0.95], [0.6], [1.0], paths)
+    ta, _, _ = O.forward(O.Geometry(analog=True, **base), *args, seed)
+    tw, _, _ = O.forward(O.Geometry(**base), *args, seed + 100)
+    counts = ta[0, 0] + ta[0, 2] + ta[0, 3] + ta[0, 4] + ta[0, 5]
+    pa = ta[0, 0] / paths
+    sa = math.sqrt(pa * (1 - pa) / paths)
+    mw, sw = mean_se(tw[0, 0], tw[0, 1], paths)
+    z = (pa - mw) / math.hypot(sa, sw)
+    pt = ta[0, 2] / paths
+    mt = tw[0, 2] / paths
+    return _r(abs(z) <= k and counts == paths and abs(pt - mt) < 5 * math.sqrt(pt / paths),
+              f"R analog={pa:.5f} weighted={mw:.5f} z={z:.2f}; T {pt:.5f}/{mt:.5f}; counts={counts}")
+
+
+def check_beer_lambert(paths=1 << 18, seed=6, k=3.0):
+    geo = O.Geometry(n_media=1, n_rel=1.0, slab_mm=1.0)
+    tal, _, _ = O.forward(geo, [1.3], [0.0], [0.0], [1.0], paths, seed)
+    p = cf.beer_lambert(1.3, 1.0)
+    T = tal[0, 2] / paths
+    z = (T - p) / math.sqrt(p * (1 - p) / paths)
+    return _r(abs(z) <= k and tal[0, 0] == 0.0, f"T={T:.5f} vs {p:.5f} z={z:.2f} R={tal[0, 0]}")
+
+
+def check_mixture_linearity(paths=1 << 18, seed=7, k=3.0):
+    al = np.array([[0.6], [0.9], [0.99]])
+    w = np.array([[0.2], [0.5], [0.3]])
+    geo = O.Geometry(n_media=3, n_rel=1.0)
+    tal, _, _ = O.forward(geo, [[1.0], [3.0], [0.5]], al, np.zeros((3, 1)), w, paths, seed)
+    m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+    ref = sum(w[i, 0] * cf.R_plane(al[i, 0]) for i in range(3))
+    z = (m - ref) / se
+    return _r(abs(z) <= k, f"R_mix={m:.5f} vs {ref:.5f} z={z:.2f}")
+
+
+def check_single_medium_special_case(paths=1 << 14, seed=8):
+    one = O.Geometry(n_media=1, n_rel=1.4)
+    three = O.Geometry(n_media=3, n_rel=1.4)
+    t1, b1, v1 = O.forward(one, [2.0], [0.9], [0.7], [1.0], paths, seed)
+    t3, b3, v3 = O.forward(three, [[2.0], [5.0], [0.3]], [[0.9], [0.5], [0.99]],
+                           [[0.7], [0.1], [0.2]], [[1.0], [0.0], [0.0]], paths, seed)
+    ok = np.array_equal(t1, t3) and np.array_equal(b1, b3) and np.array_equal(v1, v3)
+    return _r(ok, "K=3 with w=(1,0,0) vs K=1")
+
+
+def check_scale_invariance(paths=1 << 14, seed=9, c=3.7):
+    geo = O.Geometry(n_media=1, n_rel=1.4)
+    ta, _, _ = O.forward(geo, [1.0], [0.95], [0.6], [1.0], paths, seed)
+    tb, _, _ = O.forward(geo, [c], [0.95], [0.6], [1.0], paths, seed)
+    okR = abs(ta[0, 0] - tb[0, 0]) <= 1e-9 * abs(ta[0, 0])
+    _, oa, _ = O.trace(geo, [1.0], [0.95], [0.6], [1.0], n_paths=512, n_blocks=4096, seed=seed)
+    _, ob, _ = O.trace(geo, [c], [0.95], [0.6], [1.0], n_paths=512, n_blocks=4096, seed=seed)
+    top = (oa[:, 0] == O.END_EXIT_TOP) & (ob[:, 0] == O.END_EXIT_TOP)
+    okr = np.allclose(oa[top, 4], ob[top, 4] * c, rtol=1e-9, atol=1e-12) and top.sum() > 100
+    return _r(okR and okr, f"R {ta[0, 0]!r} vs {tb[0, 0]!r}; radii scale ok={okr}")
+
+
+def check_trace_invariants(n_paths=4000, seed=10, g=0.6, n=1.4, sigma_t=2.5, alpha=0.95):
+    geo = O.Geometry(n_media=1, n_rel=n)
+    ev, out, _ = O.trace(geo, [sigma_t], [alpha], [g], [1.0], n_paths=n_paths, n_blocks=2048,
+                         seed=seed)
+    nv = out[:, 5].astype(np.int64)
+    vidx = np.arange(1, ev.shape[1])[None, :]
+    live = vidx <= nv[:, None]                      # [paths, vertices-1] pairs (v-1, v)
+    prev, cur = ev[:, :-1][live], ev[:, 1:][live]
+    code = cur[:, 0].astype(int)
+    fails = []
+    dpos = cur[:, 1:4] - prev[:, 1:4]
+    cross = np.linalg.norm(np.cross(dpos, prev[:, 4:7]), axis=1)
+    if np.any(cross > 1e-9 * np.maximum(1.0, np.linalg.norm(dpos, axis=1))):
+        fails.append("flight not along direction")
+    if np.any(np.einsum("ij,ij->i", dpos, prev[:, 4:7]) < -1e-12):
+        fails.append("flight backwards")
+    bnd = (code == O.EV_REFLECT) | (code == O.EV_EXIT_TOP)
+    if np.any(cur[bnd, 3] != 0.0):
+        fails.append("boundary event off the surface")
+    refl = code == O.EV_REFLECT
+    if not (np.array_equal(cur[refl, 4], prev[refl, 4]) and np.array_equal(cur[refl, 5], prev[refl, 5])
+            and np.array_equal(cur[refl, 6], -prev[refl, 6])):
+        fails.append("reflection law")
+    if not np.array_equal(cur[refl, 7], prev[refl, 7]):
+        fails.append("weight changed at reflection")
+    col = code == O.EV_COLLIDE
+    if np.any(np.abs(np.linalg.norm(cur[col, 4:7], axis=1) - 1.0) > 1e-12):
+        fails.append("direction not unit")
+    ratio = cur[col, 7] / prev[col, 7]
+    okw = (np.abs(ratio - alpha) < 1e-12 * alpha) | (
+        np.abs(ratio - alpha / geo.rr_survive) < 1e-9 * alpha / geo.rr_survive)
+    if not np.all(okw):
+        fails.append("weight update")
+    cosines = np.einsum("ij,ij->i", cur[col, 4:7], prev[col, 4:7])
+    first = ev[:, 1][ev[:, 1, 0] == O.EV_COLLIDE]   # first vertex, entered along +z
+    first_depth = first[:, 3]
+    first_phi = np.arctan2(first[:, 5], first[:, 4])
+    exits = out[:, 0] == O.END_EXIT_TOP
+    last = ev[np.arange(n_paths), nv][exits]
+    if np.any(np.abs(out[exits, 4] - np.hypot(last[:, 1], last[:, 2]))
+              > 1e-12 * np.maximum(1.0, out[exits, 4])):
+        fails.append("exit radius")
+    if not np.array_equal(last[:, 7], out[exits, 3]):
+        fails.append("exit weight")
+    # first flight from the surface along +z: depth ~ Exp(sigma_t)
+    ks_depth = stats.kstest(first_depth, lambda z: 1.0 - np.exp(-sigma_t * np.asarray(z))).pvalue
+    # scattering cosines ~ HG(g): CDF by integrating the closed-form density
+    grid = np.linspace(-1, 1, 400001)
+    cdf_grid = integrate.cumulative_trapezoid(cf.hg_pdf(grid, g), grid, initial=0.0)
+    ks_cos = stats.kstest(cosines[:20000], lambda m: np.interp(m, grid, cdf_grid)).pvalue
+    ks_phi = stats.kstest(first_phi, "uniform", args=(-math.pi, 2 * math.pi)).pvalue
+    n_reflect = int(refl.sum())
+    ok = not fails and ks_depth > 1e-4 and ks_cos > 1e-4 and ks_phi > 1e-4 and n_reflect > 0
+    return _r(ok, f"fails={fails[:4]} ks depth={ks_depth:.3g} cos={ks_cos:.3g} "
+              f"phi={ks_phi:.3g} reflections={n_reflect}")
+
+
+def check_brute_force_single_scatter(m=48, alpha=0.7, g=0.0):
+    """Deterministic grid over (first flight u0, scattering u1, azimuth u2, second
+    flight u0'), index-matched: the grid mean of the order-1 tally converges to
+    alpha (1 - ln 2)/2 (g = 0).  The words encode the grid points exactly."""
+    geo = O.Geometry(n_media=1, n_rel=1.0, rr_weight=0.0, order_filter=0)
+    pts = (np.arange(m) + 0.5) / m
+
+    def word(u):  # the word whose uniform is the grid point rounded to 2^-23
+        return (np.floor(u * (1 << 23)).astype(np.uint64) << 9).astype(np.uint32)
+
+    a, b, c = np.meshgrid(pts, pts, pts, indexing="ij")
+    n = a.size
+    words = np.zeros((n, 3, 4), np.uint32)
+    words[:, 0, 0] = word(np.full(n, 0.5))
+    words[:, 1, 0] = word(a.ravel())
+    words[:, 1, 1] = word(b.ravel())
+    words[:, 1, 2] = word(np.full(n, 0.25))
+    words[:, 2, 0] = word(c.ravel())
+    words[:, 2, 3] = word(np.full(n, 0.5))
+    _, out, _ = O.trace(geo, [1.0], [alpha], [g], [1.0], words=words)
+    order1 = (out[:, 0] == O.END_EXIT_TOP) & (out[:, 6] == 1)
+    est = float(np.sum(out[order1, 3])) / n
+    ref = cf.R1_total(alpha, g, 1.0)
+    return _r(abs(est - ref) < 0.02 * ref, f"grid mean {est:.6f} vs {ref:.6f}")
+
+
+def check_adjoint_plane(alphas=(0.6, 0.9), paths=1 << 18, seed=11, k=3.0):
+    alphas = np.asarray(alphas, np.float64)
+    n = alphas.size
+    geo = O.Geometry(n_media=1, n_rel=1.0)
+    grad, sq = O.adjoint(geo, np.full(n, 2.0), alphas, np.zeros(n), np.ones(n), paths, seed,
+                         cot_R=np.ones(n))
+    ga, sa = mean_se(grad[:, 1], sq[:, 1], paths)
+    gs, ss = mean_se(grad[:, 0], sq[:, 0], paths)
+    gl, _ = mean_se(grad[:, 3], sq[:, 3], paths)
+    ref = np.array([cf.dR_plane_dalpha(a) for a in alphas])
+    za = (ga - ref) / sa
+    zs = gs / ss
+    ok = np.all(np.abs(za) <= k) and np.all(np.abs(zs) <= k) and np.all(np.abs(gl) < 1e-12)
+    return _r(ok, f"dR/dalpha z={np.round(za, 2)}; dR/dsigma z={np.round(zs, 2)}")
+
+
+def check_adjoint_mixture(paths=1 << 18, seed=12, k=3.0):
+    al = np.array([0.6, 0.9, 0.99])
+    w = np.array([0.2, 0.5, 0.3])
+    geo = O.Geometry(n_media=3, n_rel=1.0)
+    grad, sq = O.adjoint(geo, np.array([1.0, 3.0, 0.5]), al, np.zeros(3), w, paths, seed,
+                         cot_R=[1.0])
+    g, se = mean_se(grad[0], sq[0], paths)
+    Rk = np.array([cf.R_plane(a) for a in al])
+    Rmix = float(w @ Rk)
+    ref_l = w * (Rk - Rmix)
+    ref_a = w * np.array([cf.dR_plane_dalpha(a) for a in al])
+    z = np.concatenate([(g[9:12] - ref_l) / se[9:12], (g[3:6] - ref_a) / se[3:6], g[0:3] / se[0:3]])
+    return _r(np.all(np.abs(z) <= k), f"z={np.round(z, 2)}")
+
+
+def check_adjoint_vs_crn_fd(paths=1 << 15, reps=8, seed=13, k=3.5):
+    """VJP with random cotangents against central differences of the cotangent-weighted
+    forward tallies on common random numbers, with replica means for the SE."""
+    geo = O.Geometry(n_media=3, n_rel=1.4, n_bins=32, r_min_mm=1e-2, r_max_mm=20.0)
+    sig = np.array([1.0, 4.0, 0.5])
+    alb = np.array([0.9, 0.6, 0.97])
+    gg = np.array([0.5, 0.2, 0.8])
+    logits = np.array([0.3, -0.4, 0.0])
+    rng = np.random.default_rng(seed)
+    cotB = rng.standard_normal(geo.n_bins + 2)
+    cotR = 1.0
+
+    def weights(l):
+        e = np.exp(l - l.max())
+        return e / e.sum()
+
+    def J(s, a, g_, l, sd):
+        tal, bins, _ = O.forward(geo, s, a, g_, weights(l), paths, sd)
+        return (cotR * tal[0, 0] + bins[0, :, 0] @ cotB) / paths
+
+    P = 12
+    adj = np.zeros((reps, P))
+    fd = np.zeros((reps, P))
+    for r in range(reps):
+        sd = seed * 1000 + r
+        grad, _ = O.adjoint(geo, sig, alb, gg, weights(logits), paths, sd, cot_R=[cotR],
+                            cot_bins=cotB[None, :])
+        adj[r] = grad[0] / paths
+        for j in range(P):
+            s, a, g_, l = sig.copy(), alb.copy(), gg.copy(), logits.copy()
+            grp, i = divmod(j, 3)
+            if grp == 0:
+                h = 1e-3 * s[i]
+                s[i] += h; Jp = J(s, a, g_, l, sd); s[i] -= 2 * h; Jm = J(s, a, g_, l, sd)
+            elif grp == 1:
+                h = 1e-3 * a[i]
+                a[i] += h; Jp = J(s, a, g_, l, sd); a[i] -= 2 * h; Jm = J(s, a, g_, l, sd)
+            elif grp == 2:
+                h = 1e-3
+                g_[i] += h; Jp = J(s, a, g_, l, sd); g_[i] -= 2 * h; Jm = J(s, a, g_, l, sd)
+            else:
+                # a logit step moves the medium-choice thresholds, so only paths
+                # whose u0 lies within ~h*w of a threshold change; a larger step keeps
+                # the difference from resting on a handful of paths (the mixture is
+                # smooth in the logits, so the O(h^2) error stays far below the SE)
+                h = 1e-2
+                l[i] += h; Jp = J(s, a, g_, l, sd); l[i] -= 2 * h; Jm = J(s, a, g_, l, sd)
+            fd[r, j] = (Jp - Jm) / (2 * h)
+    ma, sa = adj.mean(0), adj.std(0, ddof=1) / math.sqrt(reps)
+    mf, sf = fd.mean(0), fd.std(0, ddof=1) / math.sqrt(reps)
+    z = (ma - mf) / np.sqrt(sa ** 2 + sf ** 2 + 1e-30)
+    return _r(np.all(np.abs(z) <= k), f"z={np.round(z, 2)}")
+
+
+BATTERY_SMALL = [
+    ("plane", lambda: check_plane_albedo(alphas=(0.5, 0.9), paths=1 << 16, k=4.0)),
+    ("second_moment", lambda: check_second_moment(paths=1 << 16, k=4.0)),
+    ("single_scatter", lambda: check_single_scatter(paths=1 << 16, k=4.0, n_bins=32)),
+    ("energy", lambda: check_energy_exact(paths=1 << 12)),
+    ("analog", lambda: check_analog_vs_weighted(paths=1 << 16, k=4.0)),
+    ("beer", lambda: check_beer_lambert(paths=1 << 16, k=4.0)),
+    ("mixture", lambda: check_mixture_linearity(paths=1 << 16, k=4.0)),
+    ("special", lambda: check_single_medium_special_case(paths=1 << 12)),
+    ("scale", lambda: check_scale_invariance(paths=1 << 12)),
+    ("trace", lambda: check_trace_invariants(n_paths=1500)),
+    ("brute", lambda: check_brute_force_single_scatter(m=32)),
+    ("adj_plane", lambda: check_adjoint_plane(paths=1 << 16, k=4.0)),
+    ("adj_mixture", lambda: check_adjoint_mixture(paths=1 << 16, k=4.0)),
+]

@@ -1,0 +1,90 @@
+"""Pins of the closed forms themselves (CPU only).
+
+The closed forms in oracle/closed_forms.py pin the oracle; here they are pinned
+against textbook values, identities and each other (two independent
+computations of Chandrasekhar's H-function, its moments, a tabulated value,
+numerical differentiation, and an elementary integral)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import closed_forms as cf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("w", [0.3, 0.5, 0.9, 0.99, 0.999])
+def test_H_two_independent_forms_agree(w):
+    for mu in (0.05, 0.3, 1.0):
+        assert abs(cf.H_iterative(mu, w) - cf.H_explicit(mu, w)) < 1e-10
+
+
+@pytest.mark.parametrize("w", [0.5, 0.9, 1.0])
+def test_H_zeroth_moment_identity(w):
+    m0, _ = integrate.quad(lambda m: cf.H_explicit(m, w), 0.0, 1.0, epsabs=1e-12)
+    assert abs(m0 - cf.H_moment0(w)) < 1e-9
+
+
+def test_H_conservative_table_value_and_first_moment():
+    with open(os.path.join(GOLDEN, "chandrasekhar_h.json")) as f:
+        gold = json.load(f)
+    H1 = cf.H_explicit(1.0, 1.0)
+    assert abs(H1 - gold["H_at_1"]) < 0.5 * 10.0 ** (-gold["H_at_1_digits"])
+    m1, _ = integrate.quad(lambda m: m * cf.H_explicit(m, 1.0), 0.0, 1.0, epsabs=1e-12)
+    assert abs(m1 - gold["moment1"]) < 1e-8
+
+
+@pytest.mark.parametrize("a", [0.5, 0.7, 0.9, 0.99])
+def test_dR_dalpha_matches_numerical_derivative(a):
+    h = 1e-5
+    fd = (cf.R_plane(a + h) - cf.R_plane(a - h)) / (2 * h)
+    assert abs(cf.dR_plane_dalpha(a) - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_plane_albedo_limits():
+    # alpha -> 0: no scattering, nothing comes back; alpha -> 1: everything does
+    assert abs(cf.R_plane(1e-9)) < 1e-8
+    assert abs(cf.R_plane(1.0 - 1e-12) - 1.0) < 1e-5
+
+
+def test_single_scatter_isotropic_index_matched_is_elementary():
+    # alpha * int_0^1 mu / (2 (1 + mu)) dmu = alpha (1 - ln 2) / 2
+    for a in (0.3, 1.0):
+        assert abs(cf.R1_total(a, 0.0, 1.0) - a * (1.0 - math.log(2.0)) / 2.0) < 1e-12
+
+
+@pytest.mark.parametrize("g,n", [(0.0, 1.0), (0.5, 1.4), (0.9, 1.4)])
+def test_single_scatter_annuli_sum_to_total(g, n):
+    slots = cf.R1_slots(0.8, g, n, 2.0, 64, 1e-3, 50.0)
+    assert abs(slots.sum() - cf.R1_total(0.8, g, n)) < 1e-9
+
+
+def test_single_scatter_annulus_scales_with_sigma_t():
+    # eq. separability: the profile rescales with 1/sigma_t
+    a = cf.R1_annulus(0.9, 0.3, 1.4, 1.0, 0.2, 0.5)
+    b = cf.R1_annulus(0.9, 0.3, 1.4, 4.0, 0.05, 0.125)
+    assert abs(a - b) < 1e-12
+
+
+def test_fresnel_hecht_limits():
+    assert cf.fresnel_hecht(1.0, 1.4) == pytest.approx((0.4 / 2.4) ** 2, abs=1e-15)
+    assert cf.fresnel_hecht(0.3, 1.0) == 0.0
+    crit = math.sqrt(1.0 - 1.0 / 1.4 ** 2)
+    assert cf.fresnel_hecht(crit * 0.999, 1.4) == 1.0
+    assert cf.fresnel_hecht(crit * 1.001, 1.4) < 1.0
+
+
+def test_golden_files_regenerate():
+    with open(os.path.join(GOLDEN, "plane_albedo_16.json")) as f:
+        plane = json.load(f)
+    for a, R, d in zip(plane["alpha"], plane["R"], plane["dR_dalpha"]):
+        assert abs(cf.R_plane(a) - R) < 1e-12
+        assert abs(cf.dR_plane_dalpha(a) - d) < 1e-9
+    with open(os.path.join(GOLDEN, "single_scatter.json")) as f:
+        ss = json.load(f)
+    for c in ss["cases"]:
+        assert abs(cf.R1_total(1.0, c["g"], c["n"]) - c["R1"]) < 1e-12

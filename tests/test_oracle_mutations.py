@@ -1,0 +1,95 @@
+"""Planted mistakes in a copy of the oracle must be caught by its pins (CPU only).
+
+Each case edits one line of oracle/rw_oracle.c the way a plausible slip would
+(a dropped term, a wrong sign or index, a transposed operand), builds the copy
+in a temporary directory and runs the pin battery of tests/oracle_pins.py
+against it in a subprocess.  The unmodified source must pass the same battery.
+Nothing here touches the GPU or the product path."""
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = [
+    ("philox_transposed_products", "uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;"),
+    ("philox_wrong_multiplier", "uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;",
+     "uint64_t p1 = (uint64_t)M0 * (uint64_t)c2;"),
+    ("philox_nine_rounds", "round < 10", "round < 9"),
+    ("u01_wrong_shift", "((double)(w >> 9) + 0.5) * 0x1p-23", "((double)(w >> 8) + 0.5) * 0x1p-23"),
+    ("fresnel_p_amplitude", "double rp = (cos_i - n * cos_t) / (cos_i + n * cos_t);",
+     "double rp = (n * cos_i - cos_t) / (n * cos_i + cos_t);"),
+    ("fresnel_refracted_cosine", "double cos_t = sqrt(1.0 - sin_t2);",
+     "double cos_t = sqrt(1.0 - sin_i2);"),
+    ("hg_orientation", "(1.0 - g + 2.0 * g * u)", "(1.0 + g - 2.0 * g * u)"),
+    ("hg_score_dropped_term", "return -2.0 * g / (1.0 - g * g) + 3.0 * (mu - g)",
+     "return 3.0 * (mu - g)"),
+    ("frame_sign", "t2[2] = -d[1];", "t2[2] = d[1];"),
+    ("azimuth_sin_cos", "b = st * sin(phi);", "b = st * cos(phi);"),
+    ("free_flight_scale", "double s = -log(u[0]) / sig;", "double s = -log(u[0]) * sig;"),
+    ("boundary_distance_sign", "db = -p[2] / d[2];", "db = p[2] / d[2];"),
+    ("no_absorption", "W *= alb;", "W *= 1.0;"),
+    ("absorbed_after_update", "res->absorbed += W * (1.0 - alb);\n      W *= alb;",
+     "W *= alb;\n      res->absorbed += W * (1.0 - alb);"),
+    ("roulette_weight", "W /= geo->rr_survive;", "W *= geo->rr_survive;"),
+    ("medium_choice_uncumulated", "if (u[0] < up->cum[j])", "if (u[0] < up->w[j])"),
+    ("entry_fresnel_dropped", "W = 1.0 - F0;", "W = 1.0;"),
+    ("bin_log_origin", "log(r / g->r_min_mm)", "log(r)"),
+    ("exit_radius_component", "sqrt(p[0] * p[0] + p[1] * p[1])", "sqrt(p[0] * p[0] + p[2] * p[2])"),
+    ("reflect_wrong_component", "d[2] = -d[2];", "d[0] = -d[0];"),
+    ("scatter_sign", "scatter_dir(d, mu, 2.0 * M_PI * u[2]);", "scatter_dir(d, -mu, 2.0 * M_PI * u[2]);"),
+    ("score_sigma_sign", "score[k] = (double)r.n_coll / up.sigma_t[k] - r.L;",
+     "score[k] = (double)r.n_coll / up.sigma_t[k] + r.L;"),
+    ("score_alpha_inverted", "(double)r.n_coll / up.albedo[k]", "(double)r.n_coll * up.albedo[k]"),
+    ("score_logit_no_baseline", "(j == k ? 1.0 : 0.0) - up.w[j]", "(j == k ? 1.0 : 0.0)"),
+    ("boundary_segment_not_counted", "      res->L += db;\n", ""),
+    ("hg_score_not_accumulated", "res->Sg += hg_dlog_dg(g, mu);", "res->Sg = hg_dlog_dg(g, mu);"),
+]
+
+
+@pytest.fixture(scope="module")
+def rr_exe(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        return None
+    exe = str(tmp_path_factory.mktemp("rrm") / "rr_ref")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, os.path.join(ROOT, "tests", "rocrand_philox_ref.cpp")],
+                          cwd=str(tmp_path_factory.getbasetemp()))
+    return exe
+
+
+def _run(lib, rr, threads=None):
+    cmd = [sys.executable, "-m", "tests.mutation_runner", lib] + ([rr] if rr else [])
+    env = dict(os.environ)
+    if threads:
+        env["ORC_THREADS"] = str(threads)
+    try:
+        p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=240, env=env)
+    except subprocess.TimeoutExpired:
+        return None, "timeout"
+    return p.returncode, (p.stdout + p.stderr).strip()[-400:]
+
+
+def test_unmodified_oracle_passes_battery(tmp_path, rr_exe):
+    lib = O.compile_source(O.source_text(), str(tmp_path / "liborc_ok.so"))
+    rc, out = _run(lib, rr_exe)
+    assert rc == 0, out
+
+
+def test_planted_mistakes_are_caught(tmp_path, rr_exe):
+    src = O.source_text()
+    libs = []
+    for name, old, new in MUTATIONS:
+        assert src.count(old) == 1, f"mutation site for {name} not unique"
+        libs.append((name, O.compile_source(src.replace(old, new), str(tmp_path / f"liborc_{name}.so"))))
+    workers = max(1, min(8, (os.cpu_count() or 2) // 2))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda nl: (nl[0],) + _run(nl[1], rr_exe, threads=2), libs))
+    survivors = [(name, out) for name, rc, out in results if rc == 0]
+    assert not survivors, f"planted mistakes not caught: {survivors}"
