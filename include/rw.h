@@ -1,0 +1,224 @@
+/*
+ * rw.h - C ABI of the MI355X (gfx950) random-walk subsurface transport through
+ * a mixture of K homogeneous media.
+ *
+ * The operation (paper Sec. 4.1, "Subsurface Scattering by Mixtures-of-Media"):
+ * the BSSRDF of a mixture is the w_k-weighted sum of the per-medium path
+ * integrals (second form of eq. sss); a random walk realises it by choosing
+ * the medium k with probability w_k once, before the walk starts (same
+ * section, and Sec. 7 "Results": the choice pdf cancels the weight).  Under
+ * normal incidence the BSSRDF is radial, R_d(r) = R * P_d(r) (eq. radsss),
+ * so each (parameter set, wavelength) "unit" yields the total diffuse
+ * reflectance R and a radial histogram.  The per-wavelength parameters are
+ * theta(lambda) = {alpha_k, g_k, sigma_t_k, w_k} (Sec. 5.1, eq.
+ * decoder_output); the boundary is a smooth Fresnel interface (Sec. 8,
+ * "Limitations").
+ *
+ * Walk conventions (the paper fixes none; identical in the FP64 oracle):
+ *   z is depth, the medium fills z >= 0 (and z <= slab_mm for a slab); the
+ *   beam enters at r = 0 along +z with weight 1 - F(0), F(0) = ((n-1)/(n+1))^2
+ *   (the specular part is not in R).  Per path, Philox4x32-10 (Salmon et al.,
+ *   SC'11) with key = seed and counter = (vertex, path, unit, stream tag)
+ *   gives one block of four words per vertex; word w -> ((w >> 9) + 0.5) 2^-23.
+ *   Vertex 0: medium = first k with u0 < cumulative weight.  Vertex v >= 1:
+ *   flight s = -ln(u0)/sigma_t; when it crosses the surface the photon moves
+ *   there and reflects (uz -> -uz) with the unpolarised Fresnel probability
+ *   (u3 < F, total internal reflection when n sin(theta_i) >= 1), else
+ *   leaves and its weight is tallied at r = hypot(x, y); otherwise it
+ *   collides: W *= alpha, Russian roulette when W < rr_weight (survive when
+ *   u3 < rr_survive, W /= rr_survive), Henyey-Greenstein cosine from u1 and
+ *   azimuth 2 pi u2 measured from the first tangent of the Duff et al. (2017)
+ *   frame of the current direction.  One loop iteration is one "vertex".
+ *   Radial slots: 0 for r < r_min, 1..n_bins for log-spaced bins over
+ *   [r_min, r_max), n_bins + 1 for r >= r_max.
+ *
+ * All entry points are asynchronous on the given HIP stream (passed as
+ * void*, i.e. a hipStream_t; NULL is the null stream) and return once the
+ * work is enqueued.  Host-side argument checks return RW_E_INVALID before
+ * anything is enqueued.  Per-unit parameter checks run on the device and set
+ * bits in flags[0] (RW_FLAG_*); rw_check() synchronises and reports them.
+ * Device pointers are caller-owned; the library never allocates caller-visible
+ * memory.  A context owns its workspace, tuned launch shapes and captured
+ * graphs; one context per stream, not thread-safe.
+ */
+#ifndef RW_H
+#define RW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RW_OK = 0,
+  RW_E_INVALID = 1,     /* bad argument (null pointer, size, geometry) */
+  RW_E_HIP = 2,         /* a HIP runtime call failed */
+  RW_E_NOMEM = 3,       /* workspace allocation failed */
+  RW_E_UNSUPPORTED = 4, /* valid but not supported (e.g. K > 4) */
+  RW_E_DEVICE_FLAG = 5  /* a device-side check raised a flag (rw_check) */
+} rw_status;
+
+/* device flag bits written to flags[0] */
+#define RW_FLAG_BAD_PARAMS 1   /* a unit had sigma_t <= 0, alpha not in [0,1], |g| >= 1,
+                                  a negative weight, weights not summing to 1 (+-1e-5)
+                                  or a NaN; that unit is left with zero tallies */
+#define RW_FLAG_VERTEX_CAP 2   /* some path hit max_vertices; it scored 0 */
+
+typedef struct rw_context rw_context;
+
+/* Create a context on HIP device `hip_device` (allocates its small workspace).
+ * *out is set to NULL on failure. */
+rw_status rw_create(rw_context** out, int hip_device);
+/* Release a context and everything it owns; NULL is accepted. */
+rw_status rw_destroy(rw_context* ctx);
+/* Message of the last non-OK status returned on this context ("" if none). */
+const char* rw_last_error(const rw_context* ctx);
+/* Static name of a status code. */
+const char* rw_status_string(rw_status s);
+
+/* Geometry and estimator constants, copied by value into kernel arguments. */
+typedef struct {
+  int32_t n_media;      /* K, 1..4 */
+  int32_t n_bins;       /* radial bins, 1..4096 (plus under/overflow slots) */
+  float n_rel;          /* refractive index of the medium over the outside, > 0;
+                           1 = index-matched */
+  float slab_mm;        /* <= 0: semi-infinite; > 0: slab of this thickness (T tallied) */
+  float r_min_mm;       /* > 0, first bin edge */
+  float r_max_mm;       /* > r_min_mm, last bin edge */
+  float rr_weight;      /* roulette threshold (<= 0 disables roulette) */
+  float rr_survive;     /* roulette survival probability, (0, 1] */
+  int64_t max_vertices; /* per-path vertex cap, 1..2^31 */
+} rw_geometry;
+
+/* Media parameters: DEVICE pointers, SoA [K][n_units] FP32, caller-owned,
+ * unit = set * n_wl + wavelength index (the wavelength list of the paper's
+ * per-wavelength parameters; the walk itself depends on lambda only through
+ * the parameters). */
+typedef struct {
+  const float* sigma_t;       /* extinction, mm^-1, > 0 */
+  const float* albedo;        /* single-scattering albedo, [0, 1] */
+  const float* g;             /* Henyey-Greenstein anisotropy, (-1, 1) */
+  const float* weight;        /* mixture weights (sum 1 per unit), or logits */
+  int32_t weights_are_logits; /* 1: weight holds logits, w = softmax over K */
+  int64_t n_sets;             /* parameter sets */
+  int64_t n_wl;               /* wavelengths per set */
+  const float* wavelength_nm; /* [n_wl] labels, may be NULL; not read by the walk */
+  int64_t k_stride;           /* elements between media k and k+1 in each array;
+                                 0 means n_sets * n_wl (a sub-range of a larger SoA
+                                 array passes the full array's unit count) */
+} rw_media;
+
+/* Raw FP64 sums, DEVICE pointers, caller-owned.  The library overwrites them
+ * (it clears them first), so a tally holds exactly one call's result. */
+typedef struct {
+  double* R;          /* [n_units][4]: sum x, sum x^2 (top exits), sum T (bottom
+                         exits of a slab), sum A (absorbed weight) */
+  double* bins;       /* [n_units][n_bins + 2][2]: per slot sum x, sum x^2 */
+  int64_t* vertices;  /* [n_units]: exact vertex counts */
+  int32_t* flags;     /* [1]: RW_FLAG_* bits (cleared by each call) */
+} rw_tally;
+
+/* Forward walk, plain form: one launch over a static grid of
+ * (unit, chunk of paths); every unit runs `paths_per_unit` paths (1..2^31).
+ * Results are deterministic: each chunk's sums are reduced in chunk order. */
+rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                     int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
+
+/* Batched persistent form of the forward walk: a persistent grid pulls
+ * (unit, chunk) work items from a device queue, long-path units first, with
+ * chunk sizes balanced by estimated path length.  `paths_per_unit` is a
+ * DEVICE int32 array [n_units] (uneven counts allowed, 0 allowed) or NULL, in
+ * which case every unit runs `paths_uniform` paths.  The estimates equal
+ * rw_forward's for the same seed (same random numbers per path); sums are
+ * reduced in chunk order, so tallies are deterministic. */
+typedef struct {
+  int32_t use_graph;            /* capture the launch sequence in a hipGraph and replay it */
+  int32_t autotune;             /* time candidate launch shapes on first use, cache them */
+  int32_t deterministic_reduce; /* 1: per-chunk partials reduced in order (default);
+                                   0: device atomics (no workspace) */
+  int64_t unit_begin, unit_end; /* resume window [begin, end) of units; end <= 0: all.
+                                   Units outside the window are left untouched. */
+} rw_batch_opts;
+
+rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                           const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                           rw_tally* out, const rw_batch_opts* opts, void* stream);
+
+/* Adjoint by path replay (not in the paper, which fits through look-up
+ * tables, Sec. 4.2): re-runs the forward walk on the same random numbers
+ * (same seed, same path counts) and returns the score-function gradient
+ *   grad[u][j] = sum over paths leaving the top of
+ *                x * (cot_R[u] + cot_bins[u][slot]) * score_j
+ * with the score of the path density: for the chosen medium k,
+ *   sigma_t_k: n_coll / sigma_t_k - L   (L = total flight length),
+ *   alpha_k:   n_coll / alpha_k,
+ *   g_k:       sum over scatterings of d ln p_HG(mu) / d g,
+ *   logit_j:   [k == j] - w_j          (w = softmax of the logits),
+ * i.e. the gradient of sum_u (cot_R[u] * R_sum[u] + sum_s cot_bins[u][s] * bins[u][s][0]).
+ * Output layout grad[n_units][4K] = (sigma_t[K], alpha[K], g[K], logit[K]);
+ * raw sums (divide by the path count for the gradient of the means).
+ * cot_R: DEVICE float [n_units] or NULL (zero); cot_bins: DEVICE float
+ * [n_units][n_bins + 2] or NULL (zero).  grad_sumsq (DEVICE double
+ * [n_units][4K] or NULL) receives the sums of squares of the per-path terms.
+ * vertices (DEVICE int64 [n_units] or NULL) receives the replayed vertex
+ * counts; flags (DEVICE int32 [1], required) as for the forward.
+ * rw_adjoint uses the plain static grid; rw_batch_adjoint the persistent
+ * queue with the same options as rw_batch_forward. */
+rw_status rw_adjoint(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                     int64_t paths_per_unit, uint64_t seed, const float* cot_R,
+                     const float* cot_bins, double* grad, double* grad_sumsq, int64_t* vertices,
+                     int32_t* flags, void* stream);
+
+rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                           const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                           const float* cot_R, const float* cot_bins, double* grad,
+                           double* grad_sumsq, int64_t* vertices, int32_t* flags,
+                           const rw_batch_opts* opts, void* stream);
+
+/* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
+ * path count N (DEVICE int32 paths_per_unit [n_units], or NULL and
+ * paths_uniform):
+ *   R_mean = sum x / N,  R_se = sqrt((sum x^2 - (sum x)^2 / N) / (N (N - 1))),
+ *   Rr[b]  = bins sum / (N * pi (r_{b+1}^2 - r_b^2))  [mm^-2], b = 0..n_bins-1,
+ *   Rr_se  likewise from the per-slot sums of squares,
+ *   Pd[b]  = Rr[b] / R_mean (0 when R_mean = 0).
+ * Outputs are DEVICE double arrays: R_mean, R_se [n_units]; Rr, Rr_se, Pd
+ * [n_units][n_bins] (any of them may be NULL).  Units with N = 0 give zeros. */
+rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
+                      const int32_t* paths_per_unit, int64_t paths_uniform, const rw_tally* tally,
+                      double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,
+                      void* stream);
+
+/* Synchronise `stream`, read flags[0] into *out_flags (may be NULL) and
+ * return RW_E_DEVICE_FLAG when it is nonzero. */
+rw_status rw_check(rw_context* ctx, const int32_t* flags, int32_t* out_flags, void* stream);
+
+/* Per-path replay for tests: runs n_paths paths of ONE unit (media with
+ * n_sets = n_wl = 1) with the random words taken from `words` (DEVICE uint32
+ * [n_paths][n_blocks][4], block v of path p) or, when words is NULL, from
+ * Philox with counter (v, p, unit_index, 0).  Writes per vertex
+ * events[p][v][8] = (code, x, y, z, ux, uy, uz, W) with code 0 start,
+ * 1 collision, 2 reflection, 3 top exit, 4 bottom exit, 5 roulette kill,
+ * 6 vertex cap (state after the vertex; zero-filled beyond the path end), and
+ * path_out[p][8] = (end, k, slot, x, r, n_vert, n_coll, absorbed) with end 1
+ * top exit, 2 bottom exit, 3 roulette kill, 4 cap, 7 out of words;
+ * path_adj[p][2] = (L, sum d ln p_HG / d g) or NULL.  All DEVICE float. */
+rw_status rw_debug_trace(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                         const uint32_t* words, int64_t n_paths, int64_t n_blocks, uint64_t seed,
+                         uint32_t unit_index, float* events, float* path_out, float* path_adj,
+                         void* stream);
+
+/* Philox4x32-10 blocks for tests: out[i][0..3] = Philox(ctr[i], key); DEVICE
+ * uint32 arrays [n][4]. */
+rw_status rw_debug_philox(rw_context* ctx, const uint32_t* ctr, uint64_t key, int64_t n,
+                          uint32_t* out, void* stream);
+
+/* Library version string. */
+const char* rw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RW_H */

@@ -92,7 +92,7 @@ enum {
   END_CAPPED = 4,
   END_ABSORBED = 5,   /* analog only */
   END_SPECULAR = 6,   /* analog only */
-  END_NO_BLOCKS = 7   /* injected-word traces that ran out of words */
+  END_NO_BLOCKS = 7   /* traces that ran out of blocks */
 };
 
 /* trace event codes */
@@ -226,9 +226,9 @@ typedef struct {
   /* Philox source */
   uint32_t key[2];
   uint32_t path, unit, tag;
-  /* injected source (traces): words[v*4 + i], v < n_blocks */
+  /* injected source (traces): words[v*4 + i] */
   const uint32_t* words;
-  int64_t n_blocks;
+  int64_t n_blocks; /* blocks available to the path (either source) */
 } block_source;
 
 typedef struct {
@@ -247,8 +247,8 @@ typedef struct {
 /* fetch block v; returns 0 when an injected source has run out */
 static int get_block(const block_source* src, int64_t v, double u[4]) {
   uint32_t w[4];
+  if (v >= src->n_blocks) return 0;
   if (src->words) {
-    if (v >= src->n_blocks) return 0;
     for (int i = 0; i < 4; ++i) w[i] = src->words[v * 4 + i];
   } else {
     uint32_t ctr[4] = {(uint32_t)v, src->path, src->unit, src->tag};
@@ -449,6 +449,7 @@ static void run_task(job_t* job, int64_t t) {
   src.key[1] = (uint32_t)(job->seed >> 32);
   src.unit = (uint32_t)u;
   src.tag = job->tag;
+  src.n_blocks = INT64_MAX;
   double score[4 * ORC_MAX_K];
   for (int64_t pth = job->task_begin[t]; pth < job->task_end[t]; ++pth) {
     path_result r;
@@ -662,7 +663,8 @@ int orc_adjoint(const orc_geometry* geo, const double* sigma_t, const double* al
 }
 
 /* Per-path replay with injected Philox output words (or Philox itself when
- * words == NULL, then path index p of unit `unit`).  One unit (parameters
+ * words == NULL, then path index p of unit `unit`); either way a path draws
+ * at most n_blocks blocks and ends "out of blocks" after that.  One unit (parameters
  * sigma_t[K], albedo[K], g[K], w[K]).  words: [n_paths][n_blocks][4].
  * events: [n_paths][n_blocks][8] = (code, x, y, z, ux, uy, uz, W) per vertex,
  * zero-filled here; path_out: [n_paths][8] = (end, k, slot, x, r, n_vert,
@@ -689,10 +691,8 @@ int orc_trace(const orc_geometry* geo, const double* sigma_t, const double* albe
     src.path = (uint32_t)p;
     src.unit = unit;
     src.tag = tag;
-    if (words) {
-      src.words = words + p * n_blocks * 4;
-      src.n_blocks = n_blocks;
-    }
+    src.n_blocks = n_blocks;
+    if (words) src.words = words + p * n_blocks * 4;
     path_result r;
     walk(&up, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks);
     double* o = path_out + p * 8;

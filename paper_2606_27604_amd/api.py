@@ -1,0 +1,116 @@
+"""Convenience layer over the C-ABI binding: allocate outputs, call the entry
+points, return tensors.  Every numerical step runs in the HIP library.
+
+The per-wavelength parameter layout of the paper is
+theta(lambda) = {alpha_k, g_k, sigma_t_k, w_k}_{k=1..K} (Sec. 5.1, eq.
+decoder_output); ``media_from_theta`` converts a tensor [S, L, K, 4] in that
+order to the library's SoA layout.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import rw
+from .rw import Context, Geometry, Media, Tally
+
+
+@dataclass
+class ForwardResult:
+    tally: Tally
+    R: torch.Tensor        # [n_units] mean total diffuse reflectance
+    R_se: torch.Tensor     # [n_units]
+    Rr: torch.Tensor       # [n_units, n_bins] radial density, mm^-2
+    Rr_se: torch.Tensor
+    Pd: torch.Tensor       # [n_units, n_bins] normalised profile Rr / R
+    vertices: torch.Tensor  # [n_units] int64
+
+
+def media_from_theta(theta: torch.Tensor, weights_are_logits: bool = False) -> Media:
+    """theta: float32 [S, L, K, 4] with (alpha, g, sigma_t, w) per medium."""
+    S, L, K, four = theta.shape
+    assert four == 4
+    soa = theta.permute(3, 2, 0, 1).reshape(4, K, S * L).contiguous().float()
+    return Media(soa[2].contiguous(), soa[0].contiguous(), soa[1].contiguous(),
+                 soa[3].contiguous(), S, L, weights_are_logits)
+
+
+def finalize(ctx: Context, geom: Geometry, tally: Tally, n_units: int, paths_uniform: int,
+             paths_per_unit=None, stream=None) -> ForwardResult:
+    dev = tally.R.device
+    nb = geom.n_bins
+    R = torch.empty(n_units, dtype=torch.float64, device=dev)
+    R_se = torch.empty_like(R)
+    Rr = torch.empty((n_units, nb), dtype=torch.float64, device=dev)
+    Rr_se = torch.empty_like(Rr)
+    Pd = torch.empty_like(Rr)
+    rw.rw_finalize(ctx, geom, n_units, paths_per_unit, paths_uniform, tally, R, R_se, Rr, Rr_se, Pd,
+                   stream=stream)
+    return ForwardResult(tally, R, R_se, Rr, Rr_se, Pd, tally.vertices)
+
+
+def forward(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, batched: bool = True,
+            paths_per_unit=None, use_graph: bool = True, autotune: bool = False,
+            stream=None) -> ForwardResult:
+    """Forward walk + finalize.  batched=False uses the plain static launch."""
+    tally = Tally(media.n_units, geom.n_bins, device=media.sigma_t.device)
+    if batched:
+        rw.rw_batch_forward(ctx, media, geom, paths_per_unit, paths, seed, tally,
+                            use_graph=use_graph, autotune=autotune, stream=stream)
+    else:
+        rw.rw_forward(ctx, media, geom, paths, seed, tally, stream=stream)
+    return finalize(ctx, geom, tally, media.n_units, paths, paths_per_unit, stream=stream)
+
+
+def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, cot_R=None,
+            cot_bins=None, batched: bool = True, paths_per_unit=None, use_graph: bool = True,
+            stream=None):
+    """Gradient sums (raw, see rw_adjoint).  Returns (grad, grad_sumsq, vertices, flags)."""
+    dev = media.sigma_t.device
+    n, P = media.n_units, 4 * geom.n_media
+    grad = torch.empty((n, P), dtype=torch.float64, device=dev)
+    sumsq = torch.empty_like(grad)
+    vert = torch.empty(n, dtype=torch.int64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    if batched:
+        rw.rw_batch_adjoint(ctx, media, geom, paths_per_unit, paths, seed, cot_R, cot_bins, grad,
+                            sumsq, vert, flags, use_graph=use_graph, stream=stream)
+    else:
+        rw.rw_adjoint(ctx, media, geom, paths, seed, cot_R, cot_bins, grad, sumsq, vert, flags,
+                      stream=stream)
+    return grad, sumsq, vert, flags
+
+
+class RWReflectance(torch.autograd.Function):
+    """Differentiable mixture-of-media reflectance.
+
+    forward(sigma_t, albedo, g, logits [K, n_units] float32 on the GPU) ->
+    (R [n_units], bins [n_units, n_bins + 2]) as per-path means (bins not per
+    area).  backward replays the same random numbers (same seed) in the
+    adjoint kernel and returns d/d(sigma_t, albedo, g, logits); the weights are
+    w = softmax(logits) over the K media.
+    """
+
+    @staticmethod
+    def forward(fctx, sigma_t, albedo, g, logits, ctx, geom, paths, seed, n_sets, n_wl):
+        media = Media(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
+                      logits.contiguous(), n_sets, n_wl, weights_are_logits=True)
+        tally = Tally(media.n_units, geom.n_bins, device=sigma_t.device)
+        rw.rw_batch_forward(ctx, media, geom, None, paths, seed, tally)
+        fctx.save_for_backward(sigma_t, albedo, g, logits)
+        fctx.meta = (ctx, geom, paths, seed, n_sets, n_wl)
+        return tally.R[:, 0] / paths, tally.bins[:, :, 0] / paths
+
+    @staticmethod
+    def backward(fctx, gR, gB):
+        sigma_t, albedo, g, logits = fctx.saved_tensors
+        ctx, geom, paths, seed, n_sets, n_wl = fctx.meta
+        media = Media(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
+                      logits.contiguous(), n_sets, n_wl, weights_are_logits=True)
+        cot_R = None if gR is None else (gR / paths).float().contiguous()
+        cot_B = None if gB is None else (gB / paths).float().contiguous()
+        grad, _, _, _ = adjoint(ctx, media, geom, paths, seed, cot_R, cot_B)
+        K = geom.n_media
+        gr = grad.t().reshape(4, K, -1).float()
+        return gr[0], gr[1], gr[2], gr[3], None, None, None, None, None, None

@@ -1,0 +1,302 @@
+// Device-side pieces of the random walk (gfx950, FP32 path arithmetic).
+//
+// The walk realises the paper's mixture-of-media BSSRDF (Sec. 4.1, second form
+// of eq. sss): one medium is chosen per path with probability w_k, then the
+// path samples the homogeneous path-integral contribution (transmittance
+// exp(-sigma_t s), albedo-weighted Henyey-Greenstein scattering) under a smooth
+// Fresnel surface (Sec. 8) for a normally incident beam (eq. radsss).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rw_internal.hpp"
+
+namespace rw {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round is two
+// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs; the key
+// schedule is wave-uniform and lives in scalar registers.
+// ---------------------------------------------------------------------------
+struct PhiloxKey {
+  uint32_t k0[10], k1[10];
+};
+
+__device__ __forceinline__ PhiloxKey philox_schedule(uint32_t k0, uint32_t k1) {
+  PhiloxKey s;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    s.k0[r] = k0 + uint32_t(r) * 0x9E3779B9u;
+    s.k1[r] = k1 + uint32_t(r) * 0xBB67AE85u;
+  }
+  return s;
+}
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        const PhiloxKey& ks) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ ks.k0[r];
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ ks.k1[r];
+    c1 = uint32_t(p1);
+    c3 = uint32_t(p0);
+    c0 = n0;
+    c2 = n2;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// word -> uniform ((w >> 9) + 0.5) * 2^-23 in (0, 1): the mantissa trick gives
+// 1 + m 2^-23 exactly, and the subtraction is exact (Sterbenz).
+__device__ __forceinline__ float u01(uint32_t w) {
+  return __uint_as_float(0x3f800000u | (w >> 9)) - (1.0f - 0x1p-24f);
+}
+
+// ---------------------------------------------------------------------------
+// Per-medium constants of the chosen medium (selected per lane at path start).
+// ---------------------------------------------------------------------------
+struct Medium {
+  float flight;  // ln(2) / sigma_t: s = -log2(u) * flight
+  float inv_sig; // 1 / sigma_t (adjoint)
+  float alb;     // albedo
+  float g;
+  float hq;             // 2 (1 - g)^2, Henyey-Greenstein inversion
+  float gq;             // 3 / (1 - g^2)^2, for the g score (adjoint)
+  float gc;             // -2 g / (1 - g^2): per-scattering constant of the g score
+};
+
+__device__ __forceinline__ Medium make_medium(float sigma_t, float alb, float g) {
+  Medium m;
+  m.inv_sig = 1.0f / sigma_t;
+  m.flight = 0.69314718055994531f * m.inv_sig;
+  m.alb = alb;
+  m.g = g;
+  m.hq = 2.0f * (1.0f - g) * (1.0f - g);
+  const float omg2 = 1.0f - g * g;
+  m.gq = 3.0f / (omg2 * omg2);
+  m.gc = -2.0f * g / omg2;
+  return m;
+}
+
+// Henyey-Greenstein cos(theta) from u, by inverting its CDF.  The textbook
+// inversion mu = (1 + g^2 - tau^2) / (2g), tau = (1 - g^2) / (1 + g t),
+// t = 2u - 1, cancels badly in FP32 for g near 1; factoring tau^2 - (1-g)^2
+// gives the equivalent
+//   1 - mu = 2 (1 - g)^2 (1 - u) (1 + g u) / (1 + g t)^2,
+// a product of positive terms (accurate to a few ulp for every g and u, exact
+// isotropic limit).  Also returns (1 + g t)^2, which equals
+// (1 - g^2)^2 / (1 + g^2 - 2 g mu) and feeds the g score without a division.
+__device__ __forceinline__ float hg_cos(const Medium& m, float u, float& den, float& sin_t) {
+  const float b = fmaf(m.g, fmaf(2.0f, u, -1.0f), 1.0f);
+  den = b * b;
+  const float omm = fminf(m.hq * (1.0f - u) * fmaf(m.g, u, 1.0f) * __builtin_amdgcn_rcpf(den), 2.0f);
+  // sin(theta) from (1 - mu)(1 + mu): no cancellation near mu = 1
+  sin_t = __builtin_amdgcn_sqrtf(omm * (2.0f - omm));
+  return 1.0f - omm;
+}
+
+// New direction at polar cosine mu (sin_t = sin(theta)) about (ux, uy, uz)
+// and azimuth 2*pi*u2 measured from the first tangent of the Duff et al.
+// (JCGT 2017) frame: t1 = (1 + s ux^2 a, s ux uy a, -s ux),
+// t2 = (ux uy a, s + uy^2 a, -uy) with s = sign(uz), a = -1/(s + uz).
+// Renormalised in FP32.
+__device__ __forceinline__ void scatter(float& ux, float& uy, float& uz, float mu, float st,
+                                        float u2) {
+  const float cp = __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
+  const float sp = __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
+  const float s = copysignf(1.0f, uz);
+  const float a = -__builtin_amdgcn_rcpf(s + uz);
+  const float b = ux * uy * a;
+  const float p = st * cp, q = st * sp;
+  const float t1x = fmaf(s * ux * ux, a, 1.0f), t1y = s * b, t1z = -s * ux;
+  const float t2x = b, t2y = fmaf(uy * uy, a, s), t2z = -uy;
+  float nx = fmaf(p, t1x, fmaf(q, t2x, mu * ux));
+  float ny = fmaf(p, t1y, fmaf(q, t2y, mu * uy));
+  float nz = fmaf(p, t1z, fmaf(q, t2z, mu * uz));
+  const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+  ux = nx * inv;
+  uy = ny * inv;
+  uz = nz * inv;
+}
+
+// Unpolarised Fresnel reflectance for light inside the medium (index n
+// relative to the outside) at cos(theta_i) = ci; 1 under total internal
+// reflection.  Mean of the s and p amplitude-squared coefficients.
+__device__ __forceinline__ float fresnel(float ci, float n, float n2) {
+  const float st2 = n2 * fmaf(-ci, ci, 1.0f);
+  if (st2 >= 1.0f) return 1.0f;
+  const float ct = __builtin_amdgcn_sqrtf(1.0f - st2);
+  const float nci = n * ci, nct = n * ct;
+  const float rs = (nci - ct) * __builtin_amdgcn_rcpf(nci + ct);
+  const float rp = (ci - nct) * __builtin_amdgcn_rcpf(ci + nct);
+  return 0.5f * fmaf(rs, rs, rp * rp);
+}
+
+// Radial slot of an exit point: 0 below r_min, 1..n_bins, n_bins+1 at/above r_max.
+__device__ __forceinline__ int radial_slot(float x, float y, const WalkGeom& geo) {
+  const float r = __builtin_amdgcn_sqrtf(fmaf(x, x, y * y));
+  if (!(r >= geo.r_min)) return 0;
+  if (r >= geo.r_max) return geo.n_bins + 1;
+  const float t = (__builtin_amdgcn_logf(r) - geo.log2_rmin) * geo.bin_scale;
+  int b = int(t);
+  b = b < 0 ? 0 : (b > geo.n_bins - 1 ? geo.n_bins - 1 : b);
+  return b + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Unit parameters (wave-uniform) and their device-side validation.
+// ---------------------------------------------------------------------------
+template <int K>
+struct UnitParams {
+  float sigma_t[K], alb[K], g[K], w[K], cum[K];
+  bool ok;
+};
+
+template <int K>
+__device__ __forceinline__ UnitParams<K> load_unit(const WalkArgs& a, int64_t u) {
+  UnitParams<K> p;
+  const int64_t n = a.k_stride;
+  float wsum = 0.0f, wmax = -3.0e38f;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    p.sigma_t[k] = a.sigma_t[k * n + u];
+    p.alb[k] = a.albedo[k * n + u];
+    p.g[k] = a.g[k * n + u];
+    p.w[k] = a.weight[k * n + u];
+    ok = ok && (p.sigma_t[k] > 0.0f) && (p.sigma_t[k] < 3.0e38f) && (p.alb[k] >= 0.0f) &&
+         (p.alb[k] <= 1.0f) && (fabsf(p.g[k]) < 1.0f);
+    wmax = fmaxf(wmax, p.w[k]);
+  }
+  if (a.weights_are_logits) {
+    ok = ok && (wmax < 3.0e38f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ok = ok && (p.w[k] == p.w[k]) && (p.w[k] < 3.0e38f) && (p.w[k] > -3.0e38f);
+      p.w[k] = __expf(p.w[k] - wmax);
+      wsum += p.w[k];
+    }
+    const float inv = 1.0f / wsum;
+#pragma unroll
+    for (int k = 0; k < K; ++k) p.w[k] *= inv;
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ok = ok && (p.w[k] >= 0.0f);
+      wsum += p.w[k];
+    }
+    ok = ok && (fabsf(wsum - 1.0f) <= 1e-5f);
+  }
+  float c = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    c += p.w[k];
+    p.cum[k] = c;
+  }
+  p.cum[K - 1] = 1.0f;
+  p.ok = ok;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Path state and the two steps of the walk.
+// ---------------------------------------------------------------------------
+struct Path {
+  float x, y, z, ux, uy, uz, W, A;
+  Medium m;
+  int k;
+  // adjoint bookkeeping: collisions, D = sum over flights of (1/sigma_t - s)
+  // for collisions and (-s) for boundary-terminated flights, which equals
+  // n_coll / sigma_t - L without the cancellation of accumulating L; and the
+  // part of the g score that depends on the sampled cosines
+  uint32_t ncoll;
+  float D, Sg;
+};
+
+enum VertexEvent : int {
+  EV_START = 0,
+  EV_COLLIDE = 1,
+  EV_REFLECT = 2,
+  EV_EXIT_TOP = 3,
+  EV_EXIT_BOTTOM = 4,
+  EV_RR_KILL = 5,
+  EV_CAP = 6
+};
+
+// vertex 0: choose the medium from u0 (first k with u0 < cumulative weight)
+template <int K>
+__device__ __forceinline__ void start_path(Path& p, uint4 w, const UnitParams<K>& up,
+                                           const WalkGeom& geo) {
+  const float u0 = u01(w.x);
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) k += (u0 >= up.cum[j]) ? 1 : 0;
+  float s = up.sigma_t[0], a = up.alb[0], g = up.g[0];
+#pragma unroll
+  for (int j = 1; j < K; ++j) {
+    s = (k == j) ? up.sigma_t[j] : s;
+    a = (k == j) ? up.alb[j] : a;
+    g = (k == j) ? up.g[j] : g;
+  }
+  p.k = k;
+  p.m = make_medium(s, a, g);
+  p.x = 0.0f; p.y = 0.0f; p.z = 0.0f;
+  p.ux = 0.0f; p.uy = 0.0f; p.uz = 1.0f;
+  p.W = geo.entry_weight;
+  p.A = 0.0f;
+  p.ncoll = 0;
+  p.D = 0.0f;
+  p.Sg = 0.0f;
+}
+
+// vertex v >= 1: flight, then boundary interaction or collision.  Returns the
+// vertex event.  ADJ adds the score bookkeeping (collisions, flight length,
+// g score).
+template <bool ADJ>
+__device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo) {
+  const float s = -__builtin_amdgcn_logf(u01(w.x)) * p.m.flight;
+  const float zn = fmaf(s, p.uz, p.z);
+  const bool top = (p.uz < 0.0f) && (zn <= 0.0f);
+  const bool bottom = geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
+  if (top || bottom) {
+    const float db = (top ? -p.z : (geo.slab_mm - p.z)) * __builtin_amdgcn_rcpf(p.uz);
+    p.x = fmaf(db, p.ux, p.x);
+    p.y = fmaf(db, p.uy, p.y);
+    p.z = top ? 0.0f : geo.slab_mm;
+    if (ADJ) p.D -= db;
+    if (!geo.index_matched) {
+      const float F = fresnel(fabsf(p.uz), geo.n_rel, geo.n_rel2);
+      if (u01(w.w) < F) {
+        p.uz = -p.uz;
+        return EV_REFLECT;
+      }
+    }
+    return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
+  }
+  p.x = fmaf(s, p.ux, p.x);
+  p.y = fmaf(s, p.uy, p.y);
+  p.z = zn;
+  if (ADJ) {
+    p.D += p.m.inv_sig - s;
+    p.ncoll += 1;
+  }
+  p.A = fmaf(p.W, 1.0f - p.m.alb, p.A);
+  p.W *= p.m.alb;
+  if (p.W < geo.rr_weight) {
+    if (u01(w.w) < geo.rr_survive) {
+      p.W *= geo.rr_boost;
+    } else {
+      return EV_RR_KILL;
+    }
+  }
+  float den, st;
+  const float mu = hg_cos(p.m, u01(w.y), den, st);
+  if (ADJ) p.Sg = fmaf((mu - p.m.g) * den, p.m.gq, p.Sg);
+  scatter(p.ux, p.uy, p.uz, mu, st, u01(w.z));
+  return EV_COLLIDE;
+}
+
+}  // namespace rw

@@ -1,0 +1,772 @@
+// Host runtime of the C ABI declared in include/rw.h.
+//
+// Responsibilities: argument validation (before anything is enqueued), the
+// context's device workspace (per-item partial sums, the persistent queue
+// counter), launch shapes (plain static grid, or a persistent grid sized from
+// the device's compute-unit count and the kernel's occupancy), the autotuner
+// that picks the chunk size and workgroup shape by timing candidates with HIP
+// events, and hipGraph replay of the batched launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rw.h"
+#include "rw_internal.hpp"
+
+using namespace rw;
+
+namespace {
+
+struct TuneCfg {
+  int chunk = 4096;        // paths per work item (multiple of 64)
+  int waves_per_wg = 4;    // workgroup = waves_per_wg wavefronts
+  int wgs_per_cu = 0;      // persistent grid: workgroups per CU (0: occupancy limit)
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;
+  std::vector<const void*> funcs;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+};
+
+}  // namespace
+
+struct rw_context {
+  int device = -1;          // -1: validation-only context (no device)
+  int n_cu = 0;
+  std::string last_error;
+  double* partial = nullptr;
+  size_t partial_bytes = 0;
+  uint32_t* queue = nullptr;
+  std::map<std::string, TuneCfg> tune;
+  std::map<std::string, GraphEntry> graphs;
+  bool tune_cache_loaded = false;
+};
+
+namespace {
+
+rw_status fail(rw_context* ctx, rw_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return st;
+}
+
+bool fault_injected(const char* what) {
+  const char* e = std::getenv("RW_FAULT_INJECT");
+  return e && std::strcmp(e, what) == 0;
+}
+
+#define RW_HIP(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, RW_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+rw_status check_geom(rw_context* ctx, const rw_geometry* g) {
+  if (!g) return fail(ctx, RW_E_INVALID, "geometry is NULL");
+  if (g->n_media < 1) return fail(ctx, RW_E_INVALID, "n_media must be >= 1 (got %d)", g->n_media);
+  if (g->n_media > kMaxMedia)
+    return fail(ctx, RW_E_UNSUPPORTED, "n_media %d > %d is not supported", g->n_media, kMaxMedia);
+  if (g->n_bins < 1 || g->n_bins > 4096)
+    return fail(ctx, RW_E_INVALID, "n_bins must be in [1, 4096] (got %d)", g->n_bins);
+  if (!(g->n_rel > 0.0f) || !std::isfinite(g->n_rel))
+    return fail(ctx, RW_E_INVALID, "n_rel must be finite and > 0");
+  if (!(g->r_min_mm > 0.0f) || !std::isfinite(g->r_max_mm) || !(g->r_max_mm > g->r_min_mm))
+    return fail(ctx, RW_E_INVALID, "need 0 < r_min_mm < r_max_mm < inf");
+  if (!std::isfinite(g->slab_mm)) return fail(ctx, RW_E_INVALID, "slab_mm must be finite");
+  if (!std::isfinite(g->rr_weight)) return fail(ctx, RW_E_INVALID, "rr_weight must be finite");
+  if (g->rr_weight > 0.0f && !(g->rr_survive > 0.0f && g->rr_survive <= 1.0f))
+    return fail(ctx, RW_E_INVALID, "rr_survive must be in (0, 1]");
+  if (g->max_vertices < 1 || g->max_vertices > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "max_vertices must be in [1, 2^31]");
+  return RW_OK;
+}
+
+WalkGeom make_geom(const rw_geometry* g) {
+  WalkGeom w{};
+  w.n_bins = g->n_bins;
+  w.index_matched = g->n_rel == 1.0f;
+  w.slab = g->slab_mm > 0.0f;
+  w.n_rel = g->n_rel;
+  w.n_rel2 = g->n_rel * g->n_rel;
+  const double n = g->n_rel;
+  const double F0 = ((n - 1.0) / (n + 1.0)) * ((n - 1.0) / (n + 1.0));
+  w.entry_weight = float(1.0 - F0);
+  w.slab_mm = g->slab_mm > 0.0f ? g->slab_mm : 0.0f;
+  w.r_min = g->r_min_mm;
+  w.r_max = g->r_max_mm;
+  w.log2_rmin = float(std::log2(double(g->r_min_mm)));
+  w.bin_scale = float(double(g->n_bins) / std::log2(double(g->r_max_mm) / double(g->r_min_mm)));
+  w.rr_weight = g->rr_weight > 0.0f ? g->rr_weight : 0.0f;
+  w.rr_survive = g->rr_weight > 0.0f ? g->rr_survive : 1.0f;
+  w.rr_boost = float(1.0 / double(w.rr_survive));
+  w.max_vertices = uint32_t(std::min<int64_t>(g->max_vertices, int64_t(0xFFFFFFFFu)));
+  return w;
+}
+
+rw_status check_media(rw_context* ctx, const rw_media* m, int64_t* n_units) {
+  if (!m) return fail(ctx, RW_E_INVALID, "media is NULL");
+  if (!m->sigma_t || !m->albedo || !m->g || !m->weight)
+    return fail(ctx, RW_E_INVALID, "a media parameter pointer is NULL");
+  if (m->n_sets < 0 || m->n_wl < 0) return fail(ctx, RW_E_INVALID, "n_sets and n_wl must be >= 0");
+  if (m->n_wl > 0 && m->n_sets > (int64_t(1) << 40) / m->n_wl)
+    return fail(ctx, RW_E_INVALID, "too many units");
+  *n_units = m->n_sets * m->n_wl;
+  if (*n_units > (int64_t(1) << 32))
+    return fail(ctx, RW_E_UNSUPPORTED, "more than 2^32 units per call");
+  if (m->k_stride != 0 && m->k_stride < *n_units)
+    return fail(ctx, RW_E_INVALID, "k_stride (%lld) < n_units (%lld)", (long long)m->k_stride,
+                (long long)*n_units);
+  return RW_OK;
+}
+
+rw_status need_device(rw_context* ctx) {
+  if (ctx->device < 0)
+    return fail(ctx, RW_E_UNSUPPORTED, "validation-only context (created with hip_device = -1)");
+  RW_HIP(ctx, hipSetDevice(ctx->device));
+  return RW_OK;
+}
+
+rw_status ensure_partial(rw_context* ctx, size_t bytes) {
+  if (bytes <= ctx->partial_bytes) return RW_OK;
+  if (fault_injected("alloc")) return fail(ctx, RW_E_NOMEM, "injected allocation failure");
+  if (ctx->partial) {
+    // the old buffer may still be read by queued work
+    RW_HIP(ctx, hipDeviceSynchronize());
+    RW_HIP(ctx, hipFree(ctx->partial));
+    ctx->partial = nullptr;
+    ctx->partial_bytes = 0;
+  }
+  size_t want = std::max(bytes, size_t(1) << 20);
+  if (hipMalloc(&ctx->partial, want) != hipSuccess) {
+    ctx->partial = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, RW_E_NOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  ctx->partial_bytes = want;
+  return RW_OK;
+}
+
+// Work description shared by the four walk entry points.
+struct Plan {
+  WalkArgs a{};
+  int K = 0;
+  bool adjoint = false;
+  TuneCfg cfg;
+  int64_t n_window = 0;
+};
+
+int round_up(int64_t v, int64_t m) { return int((v + m - 1) / m * m); }
+
+rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_geometry* geom,
+                     int64_t n_units, const int32_t* paths, int64_t paths_uniform, uint64_t seed,
+                     int64_t ub, int64_t ue, bool adjoint, const TuneCfg& cfg) {
+  WalkArgs& a = P.a;
+  a.sigma_t = media->sigma_t;
+  a.albedo = media->albedo;
+  a.g = media->g;
+  a.weight = media->weight;
+  a.weights_are_logits = media->weights_are_logits ? 1 : 0;
+  a.n_units_total = n_units;
+  a.k_stride = media->k_stride ? media->k_stride : n_units;
+  a.geo = make_geom(geom);
+  a.key0 = uint32_t(seed);
+  a.key1 = uint32_t(seed >> 32);
+  a.tag = kForwardTag;
+  P.K = geom->n_media;
+  P.adjoint = adjoint;
+  P.cfg = cfg;
+  P.n_window = ue - ub;
+  // chunk: at most the configured size, and no larger than the (rounded) path count
+  int chunk = cfg.chunk;
+  if (paths_uniform > 0 && paths_uniform < chunk) chunk = std::max(64, round_up(paths_uniform, 64));
+  WorkMap& m = a.map;
+  m.n_units = ue - ub;
+  m.unit_begin = ub;
+  m.paths_uniform = paths_uniform;
+  m.paths = paths;
+  m.chunk = chunk;
+  m.chunks_per_unit = paths_uniform > 0 ? int((paths_uniform + chunk - 1) / chunk) : 0;
+  m.n_items = m.n_units * int64_t(m.chunks_per_unit);
+  m.order = nullptr;
+  m.queue = nullptr;
+  a.lds_doubles_per_wave = adjoint ? 8 * P.K : (geom->n_bins + 2) * 2;
+  a.part_len = adjoint ? adjoint_part_len(P.K) : forward_part_len(geom->n_bins);
+  return RW_OK;
+}
+
+int occupancy_wgs(const Plan& P, int waves_per_wg) {
+  int blocks = 0;
+  const int lds = walk_lds_bytes(P.a, waves_per_wg);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel_ptr(P.K, P.adjoint),
+                                                   waves_per_wg * kWave, lds) != hipSuccess ||
+      blocks < 1) {
+    (void)hipGetLastError();
+    blocks = 1;
+  }
+  return blocks;
+}
+
+// Enqueue the launch sequence of a plan (no graph).
+rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, double* grad,
+                  double* grad_sumsq, int64_t* adj_vertices, int32_t* flags, hipStream_t s) {
+  WalkArgs& a = P.a;
+  if (fault_injected("launch")) return fail(ctx, RW_E_HIP, "injected launch failure");
+  RW_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(flags), 1, 0u, s));
+  a.flags = flags;
+  if (P.n_window <= 0) return RW_OK;
+  const int64_t nd = (a.geo.n_bins + 2) * 2;
+  if (!P.adjoint) {
+    a.R = out->R;
+    a.bins = out->bins;
+    a.vertices = out->vertices;
+    const int64_t ub = a.map.unit_begin;
+    if (a.map.n_items == 0 || a.atomic) {
+      RW_HIP(ctx, launch_fill_f64(a.R + ub * 4, P.n_window * 4, 0.0, s));
+      RW_HIP(ctx, launch_fill_f64(a.bins + ub * nd, P.n_window * nd, 0.0, s));
+      RW_HIP(ctx, launch_fill_i64(a.vertices + ub, P.n_window, s));
+      if (a.map.n_items == 0) return RW_OK;
+    }
+  } else {
+    a.vertices = adj_vertices;
+    if (a.map.n_items == 0) {
+      const int64_t ub = a.map.unit_begin;
+      RW_HIP(ctx, launch_fill_f64(grad + ub * 4 * P.K, P.n_window * 4 * P.K, 0.0, s));
+      if (grad_sumsq)
+        RW_HIP(ctx, launch_fill_f64(grad_sumsq + ub * 4 * P.K, P.n_window * 4 * P.K, 0.0, s));
+      if (adj_vertices) RW_HIP(ctx, launch_fill_i64(adj_vertices + ub, P.n_window, s));
+      return RW_OK;
+    }
+  }
+  const int wpw = P.cfg.waves_per_wg;
+  int64_t grid;
+  if (persistent) {
+    a.map.queue = ctx->queue;
+    RW_HIP(ctx, launch_fill_u32(ctx->queue, 1, 0u, s));
+    const int per_cu = P.cfg.wgs_per_cu > 0 ? P.cfg.wgs_per_cu : occupancy_wgs(P, wpw);
+    grid = int64_t(ctx->n_cu) * per_cu;
+    grid = std::min<int64_t>(grid, (a.map.n_items + wpw - 1) / wpw);
+  } else {
+    a.map.queue = nullptr;
+    grid = (a.map.n_items + wpw - 1) / wpw;
+  }
+  if (grid > 0x7FFFFFFF) return fail(ctx, RW_E_UNSUPPORTED, "grid too large");
+  RW_HIP(ctx, launch_walk(a, P.K, P.adjoint, wpw, int(grid), s));
+  if (P.adjoint) {
+    RW_HIP(ctx, launch_reduce_adjoint(a, P.K, grad, grad_sumsq, s));
+  } else if (!a.direct && !a.atomic) {
+    RW_HIP(ctx, launch_reduce_forward(a, s));
+  }
+  return RW_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------
+std::string tune_key(const Plan& P, bool persistent, int64_t paths_uniform) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "gfx950 K%d %s %s nb%d p%lld", P.K, P.adjoint ? "adj" : "fwd",
+                persistent ? "persistent" : "static", P.a.geo.n_bins,
+                (long long)std::min<int64_t>(paths_uniform, 1 << 16));
+  return buf;
+}
+
+void load_tune_cache(rw_context* ctx) {
+  if (ctx->tune_cache_loaded) return;
+  ctx->tune_cache_loaded = true;
+  const char* path = std::getenv("RW_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* bar = std::strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    TuneCfg c;
+    if (std::sscanf(bar + 1, "%d %d %d", &c.chunk, &c.waves_per_wg, &c.wgs_per_cu) == 3 &&
+        c.chunk >= 64 && c.chunk % 64 == 0 && (c.waves_per_wg == 1 || c.waves_per_wg == 2 ||
+                                               c.waves_per_wg == 4))
+      ctx->tune[line] = c;
+  }
+  std::fclose(f);
+}
+
+void save_tune_cache(rw_context* ctx) {
+  const char* path = std::getenv("RW_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : ctx->tune)
+    std::fprintf(f, "%s|%d %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.waves_per_wg,
+                 kv.second.wgs_per_cu);
+  std::fclose(f);
+}
+
+// Time candidate shapes on a sample window of units (the real call overwrites
+// every output of its window afterwards).
+rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, double* grad,
+                   double* grad_sumsq, int64_t* adj_vertices, int32_t* flags, hipStream_t s,
+                   TuneCfg* best) {
+  const int64_t paths = base.a.map.paths_uniform;
+  // sample: enough units for ~2^22 paths, at most the window
+  int64_t n_sample = std::max<int64_t>(1, (int64_t(1) << 22) / std::max<int64_t>(paths, 1));
+  n_sample = std::max<int64_t>(n_sample, 2 * ctx->n_cu);
+  n_sample = std::min<int64_t>(n_sample, base.n_window);
+  const int chunks[] = {1024, 2048, 4096, 8192};
+  const int wpws[] = {1, 2, 4};
+  hipEvent_t e0, e1;
+  RW_HIP(ctx, hipEventCreate(&e0));
+  RW_HIP(ctx, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  *best = base.cfg;
+  for (int chunk : chunks) {
+    for (int wpw : wpws) {
+      Plan P = base;
+      P.cfg.chunk = chunk;
+      P.cfg.waves_per_wg = wpw;
+      P.cfg.wgs_per_cu = 0;
+      P.n_window = n_sample;
+      WorkMap& m = P.a.map;
+      m.n_units = n_sample;
+      int c = chunk;
+      if (paths > 0 && paths < c) c = std::max(64, round_up(paths, 64));
+      m.chunk = c;
+      m.chunks_per_unit = int((paths + c - 1) / c);
+      m.n_items = m.n_units * int64_t(m.chunks_per_unit);
+      P.a.direct = (!P.adjoint && m.chunks_per_unit == 1 && !P.a.atomic) ? 1 : 0;
+      if (!P.a.direct && !P.a.atomic) {
+        rw_status st = ensure_partial(ctx, size_t(m.n_items) * P.a.part_len * sizeof(double));
+        if (st != RW_OK) continue;
+        P.a.partial = ctx->partial;
+      }
+      float ms_sum = 0.0f;
+      bool ok = true;
+      for (int rep = 0; rep < 3 && ok; ++rep) {
+        if (hipEventRecord(e0, s) != hipSuccess) { ok = false; break; }
+        if (enqueue(ctx, P, persistent, out, grad, grad_sumsq, adj_vertices, flags, s) != RW_OK) {
+          ok = false;
+          break;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          ok = false;
+          break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_sum += ms;  // first repetition warms up
+      }
+      if (ok && ms_sum < best_ms) {
+        best_ms = ms_sum;
+        *best = P.cfg;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return RW_OK;
+}
+
+// ---- graphs ---------------------------------------------------------------
+// The batched sequence is built as an explicit graph of kernel nodes (no memset
+// nodes): fill flags -> fill queue -> [fill outputs] -> walk -> [reduce].
+// Topology is keyed by the kernels and launch shapes; each call updates the
+// kernel arguments of the instantiated graph and launches it.
+struct NodeSpec {
+  const void* func;
+  dim3 grid, block;
+  unsigned lds;
+  std::vector<std::vector<char>> args;  // argument bytes in order
+};
+
+template <class T>
+std::vector<char> arg_bytes(const T& v) {
+  std::vector<char> b(sizeof(T));
+  std::memcpy(b.data(), &v, sizeof(T));
+  return b;
+}
+
+rw_status graph_launch(rw_context* ctx, const std::string& key, std::vector<NodeSpec>& specs,
+                       hipStream_t s) {
+  auto it = ctx->graphs.find(key);
+  std::vector<std::vector<void*>> ptrs(specs.size());
+  for (size_t i = 0; i < specs.size(); ++i)
+    for (auto& a : specs[i].args) ptrs[i].push_back(a.data());
+  if (it == ctx->graphs.end()) {
+    GraphEntry ge;
+    RW_HIP(ctx, hipGraphCreate(&ge.graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (size_t i = 0; i < specs.size(); ++i) {
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(specs[i].func);
+      kp.gridDim = specs[i].grid;
+      kp.blockDim = specs[i].block;
+      kp.sharedMemBytes = specs[i].lds;
+      kp.kernelParams = ptrs[i].data();
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      RW_HIP(ctx, hipGraphAddKernelNode(&node, ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+      ge.nodes.push_back(node);
+      ge.funcs.push_back(specs[i].func);
+      prev = node;
+    }
+    RW_HIP(ctx, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+    RW_HIP(ctx, hipEventCreateWithFlags(&ge.done, hipEventDisableTiming));
+    it = ctx->graphs.emplace(key, ge).first;
+  } else {
+    GraphEntry& ge = it->second;
+    // arguments of an instantiated graph may still be read by a queued launch
+    if (ge.launched) RW_HIP(ctx, hipEventSynchronize(ge.done));
+    for (size_t i = 0; i < specs.size(); ++i) {
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(specs[i].func);
+      kp.gridDim = specs[i].grid;
+      kp.blockDim = specs[i].block;
+      kp.sharedMemBytes = specs[i].lds;
+      kp.kernelParams = ptrs[i].data();
+      kp.extra = nullptr;
+      RW_HIP(ctx, hipGraphExecKernelNodeSetParams(ge.exec, ge.nodes[i], &kp));
+    }
+  }
+  GraphEntry& ge = it->second;
+  RW_HIP(ctx, hipGraphLaunch(ge.exec, s));
+  RW_HIP(ctx, hipEventRecord(ge.done, s));
+  ge.launched = true;
+  return RW_OK;
+}
+
+rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, double* grad_sumsq,
+                        int64_t* adj_vertices, int32_t* flags, hipStream_t s) {
+  WalkArgs& a = P.a;
+  a.flags = flags;
+  if (P.adjoint) {
+    a.vertices = adj_vertices;
+  } else {
+    a.R = out->R;
+    a.bins = out->bins;
+    a.vertices = out->vertices;
+  }
+  if (P.n_window <= 0 || a.map.n_items == 0 || a.atomic)
+    return enqueue(ctx, P, true, out, grad, grad_sumsq, adj_vertices, flags, s);
+  const int wpw = P.cfg.waves_per_wg;
+  a.map.queue = ctx->queue;
+  const int per_cu = P.cfg.wgs_per_cu > 0 ? P.cfg.wgs_per_cu : occupancy_wgs(P, wpw);
+  int64_t grid = std::min<int64_t>(int64_t(ctx->n_cu) * per_cu, (a.map.n_items + wpw - 1) / wpw);
+  std::vector<NodeSpec> specs;
+  uint32_t* flags_u = reinterpret_cast<uint32_t*>(flags);
+  const int64_t one = 1;
+  const uint32_t zero = 0;
+  specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
+                   {arg_bytes(flags_u), arg_bytes(one), arg_bytes(zero)}});
+  specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
+                   {arg_bytes(ctx->queue), arg_bytes(one), arg_bytes(zero)}});
+  specs.push_back({walk_kernel_ptr(P.K, P.adjoint), dim3(unsigned(grid)), dim3(wpw * kWave),
+                   unsigned(walk_lds_bytes(a, wpw)), {arg_bytes(a)}});
+  if (P.adjoint) {
+    specs.push_back({reduce_adjoint_kernel_ptr(P.K), dim3(unsigned((a.map.n_units + 255) / 256)),
+                     dim3(256), 0, {arg_bytes(a), arg_bytes(grad), arg_bytes(grad_sumsq)}});
+  } else if (!a.direct) {
+    specs.push_back({reduce_forward_kernel_ptr(), dim3(unsigned(a.map.n_units)), dim3(256), 0,
+                     {arg_bytes(a)}});
+  }
+  char key[200];
+  std::snprintf(key, sizeof(key), "K%d adj%d direct%d grid%lld wpw%d lds%d units%lld nodes%zu",
+                P.K, int(P.adjoint), a.direct, (long long)grid, wpw, walk_lds_bytes(a, wpw),
+                (long long)a.map.n_units, specs.size());
+  return graph_launch(ctx, key, specs, s);
+}
+
+// ---- shared body of the four walk entry points -----------------------------
+rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                   const int32_t* paths, int64_t paths_uniform, uint64_t seed, rw_tally* out,
+                   const float* cot_R, const float* cot_bins, double* grad, double* grad_sumsq,
+                   int64_t* adj_vertices, int32_t* flags, const rw_batch_opts* opts, bool batched,
+                   bool adjoint, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  int64_t n_units = 0;
+  st = check_media(ctx, media, &n_units);
+  if (st != RW_OK) return st;
+  if (paths_uniform < 0 || paths_uniform > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "path count must be in [0, 2^31] (got %lld)",
+                (long long)paths_uniform);
+  if (paths && paths_uniform <= 0 && n_units > 0)
+    return fail(ctx, RW_E_INVALID,
+                "with a per-unit path array, paths_uniform must give the largest count (> 0)");
+  if (!adjoint) {
+    if (!out || !out->R || !out->bins || !out->vertices || !out->flags)
+      return fail(ctx, RW_E_INVALID, "tally pointers must be non-NULL");
+    flags = out->flags;
+  } else {
+    if (!grad) return fail(ctx, RW_E_INVALID, "grad is NULL");
+    if (!flags) return fail(ctx, RW_E_INVALID, "flags is NULL");
+  }
+  int64_t ub = 0, ue = n_units;
+  bool use_graph = false, tune = false, deterministic = true;
+  if (opts) {
+    use_graph = opts->use_graph != 0;
+    tune = opts->autotune != 0;
+    deterministic = opts->deterministic_reduce != 0;
+    if (opts->unit_end > 0 || opts->unit_begin != 0) {
+      ub = opts->unit_begin;
+      ue = opts->unit_end > 0 ? opts->unit_end : n_units;
+      if (ub < 0 || ue > n_units || ub > ue)
+        return fail(ctx, RW_E_INVALID, "unit window [%lld, %lld) outside [0, %lld)", (long long)ub,
+                    (long long)ue, (long long)n_units);
+    }
+  }
+  if (adjoint && !deterministic)
+    return fail(ctx, RW_E_UNSUPPORTED, "the adjoint always reduces per item (deterministic)");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  Plan P;
+  TuneCfg cfg;
+  std::string key;
+  if (batched) {
+    load_tune_cache(ctx);
+    // a tune-key probe plan (shape only)
+    build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
+    key = tune_key(P, true, paths_uniform);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) cfg = it->second;
+  }
+  build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
+  P.a.atomic = (!adjoint && !deterministic) ? 1 : 0;
+  P.a.direct = (!adjoint && !P.a.atomic && P.a.map.chunks_per_unit == 1) ? 1 : 0;
+  if (adjoint) {
+    P.a.cot_R = cot_R;
+    P.a.cot_bins = cot_bins;
+  }
+  if (batched && tune && ctx->tune.find(key) == ctx->tune.end() && P.a.map.n_items > 0 &&
+      P.n_window > 0) {
+    TuneCfg best;
+    st = autotune(ctx, P, true, out, grad, grad_sumsq, adj_vertices, flags, s, &best);
+    if (st != RW_OK) return st;
+    ctx->tune[key] = best;
+    save_tune_cache(ctx);
+    build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, best);
+    P.a.atomic = (!adjoint && !deterministic) ? 1 : 0;
+    P.a.direct = (!adjoint && !P.a.atomic && P.a.map.chunks_per_unit == 1) ? 1 : 0;
+    if (adjoint) {
+      P.a.cot_R = cot_R;
+      P.a.cot_bins = cot_bins;
+    }
+  }
+  if (!P.a.direct && !P.a.atomic && P.a.map.n_items > 0) {
+    st = ensure_partial(ctx, size_t(P.a.map.n_items) * P.a.part_len * sizeof(double));
+    if (st != RW_OK) return st;
+    P.a.partial = ctx->partial;
+  }
+  if (batched && use_graph)
+    return enqueue_graph(ctx, P, out, grad, grad_sumsq, adj_vertices, flags, s);
+  return enqueue(ctx, P, batched, out, grad, grad_sumsq, adj_vertices, flags, s);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* rw_version(void) { return "rwmc-gfx950 1.0"; }
+
+const char* rw_status_string(rw_status s) {
+  switch (s) {
+    case RW_OK: return "RW_OK";
+    case RW_E_INVALID: return "RW_E_INVALID";
+    case RW_E_HIP: return "RW_E_HIP";
+    case RW_E_NOMEM: return "RW_E_NOMEM";
+    case RW_E_UNSUPPORTED: return "RW_E_UNSUPPORTED";
+    case RW_E_DEVICE_FLAG: return "RW_E_DEVICE_FLAG";
+  }
+  return "RW_E_UNKNOWN";
+}
+
+rw_status rw_create(rw_context** out, int hip_device) {
+  if (!out) return RW_E_INVALID;
+  *out = nullptr;
+  rw_context* ctx = new (std::nothrow) rw_context();
+  if (!ctx) return RW_E_NOMEM;
+  if (hip_device < 0) {  // validation-only context
+    *out = ctx;
+    return RW_OK;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) {
+    (void)hipGetLastError();
+    delete ctx;
+    return RW_E_HIP;
+  }
+  ctx->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete ctx;
+    return RW_E_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+    delete ctx;
+    return RW_E_HIP;
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->queue, 256) != hipSuccess) {
+    delete ctx;
+    return RW_E_NOMEM;
+  }
+  *out = ctx;
+  return RW_OK;
+}
+
+rw_status rw_destroy(rw_context* ctx) {
+  if (!ctx) return RW_OK;
+  if (ctx->device >= 0) {
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& kv : ctx->graphs) {
+      if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+      if (kv.second.done) hipEventDestroy(kv.second.done);
+    }
+    if (ctx->partial) hipFree(ctx->partial);
+    if (ctx->queue) hipFree(ctx->queue);
+  }
+  delete ctx;
+  return RW_OK;
+}
+
+const char* rw_last_error(const rw_context* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                     int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream) {
+  return run_walk(ctx, media, geom, nullptr, paths_per_unit, seed, out, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, false, false, stream);
+}
+
+rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                           const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                           rw_tally* out, const rw_batch_opts* opts, void* stream) {
+  rw_batch_opts def{1, 0, 1, 0, 0};
+  return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, out, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false, stream);
+}
+
+rw_status rw_adjoint(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                     int64_t paths_per_unit, uint64_t seed, const float* cot_R,
+                     const float* cot_bins, double* grad, double* grad_sumsq, int64_t* vertices,
+                     int32_t* flags, void* stream) {
+  return run_walk(ctx, media, geom, nullptr, paths_per_unit, seed, nullptr, cot_R, cot_bins, grad,
+                  grad_sumsq, vertices, flags, nullptr, false, true, stream);
+}
+
+rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                           const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                           const float* cot_R, const float* cot_bins, double* grad,
+                           double* grad_sumsq, int64_t* vertices, int32_t* flags,
+                           const rw_batch_opts* opts, void* stream) {
+  rw_batch_opts def{1, 0, 1, 0, 0};
+  return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, nullptr, cot_R, cot_bins,
+                  grad, grad_sumsq, vertices, flags, opts ? opts : &def, true, true, stream);
+}
+
+rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
+                      const int32_t* paths_per_unit, int64_t paths_uniform, const rw_tally* tally,
+                      double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,
+                      void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  if (n_units < 0) return fail(ctx, RW_E_INVALID, "n_units must be >= 0");
+  if (!tally || !tally->R || !tally->bins)
+    return fail(ctx, RW_E_INVALID, "tally R and bins must be non-NULL");
+  if (!paths_per_unit && paths_uniform < 0)
+    return fail(ctx, RW_E_INVALID, "paths_uniform must be >= 0");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  RW_HIP(ctx, launch_finalize(make_geom(geom), n_units, paths_per_unit, paths_uniform, tally->R,
+                              tally->bins, R_mean, R_se, Rr, Rr_se, Pd,
+                              reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+rw_status rw_check(rw_context* ctx, const int32_t* flags, int32_t* out_flags, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  if (!flags) return fail(ctx, RW_E_INVALID, "flags is NULL");
+  rw_status st = need_device(ctx);
+  if (st != RW_OK) return st;
+  int32_t h = 0;
+  RW_HIP(ctx, hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  RW_HIP(ctx, hipMemcpy(&h, flags, sizeof(h), hipMemcpyDeviceToHost));
+  if (out_flags) *out_flags = h;
+  if (h) return fail(ctx, RW_E_DEVICE_FLAG, "device flags 0x%x", unsigned(h));
+  return RW_OK;
+}
+
+rw_status rw_debug_trace(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                         const uint32_t* words, int64_t n_paths, int64_t n_blocks, uint64_t seed,
+                         uint32_t unit_index, float* events, float* path_out, float* path_adj,
+                         void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  int64_t n_units = 0;
+  st = check_media(ctx, media, &n_units);
+  if (st != RW_OK) return st;
+  if (n_units != 1) return fail(ctx, RW_E_INVALID, "rw_debug_trace takes exactly one unit");
+  if (n_paths < 0 || n_paths > (int64_t(1) << 24) || n_blocks < 1 || n_blocks > (int64_t(1) << 24))
+    return fail(ctx, RW_E_INVALID, "n_paths in [0, 2^24] and n_blocks in [1, 2^24] required");
+  if (!path_out) return fail(ctx, RW_E_INVALID, "path_out is NULL");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  if (n_paths == 0) return RW_OK;
+  WalkArgs a{};
+  a.sigma_t = media->sigma_t;
+  a.albedo = media->albedo;
+  a.g = media->g;
+  a.weight = media->weight;
+  a.weights_are_logits = media->weights_are_logits ? 1 : 0;
+  a.n_units_total = 1;
+  a.k_stride = media->k_stride ? media->k_stride : 1;
+  a.geo = make_geom(geom);
+  a.key0 = uint32_t(seed);
+  a.key1 = uint32_t(seed >> 32);
+  a.tag = kForwardTag;
+  RW_HIP(ctx, launch_trace(a, geom->n_media, words, n_paths, n_blocks, unit_index, events,
+                           path_out, path_adj, reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+rw_status rw_debug_philox(rw_context* ctx, const uint32_t* ctr, uint64_t key, int64_t n,
+                          uint32_t* out, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  if (!ctr || !out || n < 0) return fail(ctx, RW_E_INVALID, "bad arguments");
+  rw_status st = need_device(ctx);
+  if (st != RW_OK) return st;
+  RW_HIP(ctx, launch_philox(ctr, uint32_t(key), uint32_t(key >> 32), n, out,
+                            reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+}  // extern "C"
