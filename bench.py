@@ -1,0 +1,369 @@
+"""Benchmark of the mixture-of-media random walk on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3] [--micro]
+
+One step is one pass of the whole path over the 81-wavelength three-medium
+workload (81 wavelengths 380-780 nm, per-medium sigma_t log-uniform in
+[0.1, 100] mm^-1, alpha uniform in [0.30, 0.999], g uniform in [0, 0.95],
+Dirichlet(1,1,1) weights, Fresnel boundary n = 1.4, 2^20 paths per
+wavelength, 256 log bins over [1e-3, 50] mm):
+    rw_batch_forward (persistent, graph replay) -> rw_finalize ->
+    rw_batch_adjoint (path replay with cotangents v_R = 1, v_bins ~ N(0, 1)).
+Each step uses a fresh seed.  The metric is path vertices per second over the
+forward and the adjoint (exact int64 vertex counts from the device), with the
+plain static-grid launches (rw_forward + rw_adjoint) timed on the same seeds
+for the batched/plain ratio at identical statistical error (same random
+numbers, same estimates).
+
+Extra fields: the batched sweep of 65,536 three-medium sets x 16 wavelengths
+at 4,096 paths (one persistent launch) and its per-set plain launches timed on
+a subset of sets; the roofline of the dominant kernel (ALU-bound: VALU issue
+slots per vertex x vertices / measured kernel time, against the issue peak of
+256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+Prints one JSON line.  Inputs are synthetic (seeded); nothing is read from
+outside the repository.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC path vertices/s, fwd & adjoint, batched vs plain, at matched stat. error"
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction
+# occupies a SIMD for 4 cycles at full rate)
+N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+ISSUE_PEAK = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ  # lane-slots / s
+
+# Algorithmic work of one vertex, in VALU lane-slots (an op's issue cost in
+# full-rate cycles): one Philox4x32-10 block = 10 rounds x (2 32x32->64
+# products + 2 three-input XORs); ~60 FP32 add/mul/FMA/compare/select;
+# 7 transcendentals (log, rcp, sqrt, sin, cos, rsq, rcp).  32x32->64 integer
+# products and transcendentals issue at quarter rate on CDNA (4 slots).
+ALG_FP32_PER_VERTEX = 60
+ALG_TRANS_PER_VERTEX = 7
+ALG_MAD64_PER_VERTEX = 20
+ALG_XOR_PER_VERTEX = 20
+QUARTER = 4.0
+
+
+def alg_slots_per_vertex(mad_cost=QUARTER, trans_cost=QUARTER) -> float:
+    return (ALG_MAD64_PER_VERTEX * mad_cost + ALG_XOR_PER_VERTEX + ALG_FP32_PER_VERTEX +
+            ALG_TRANS_PER_VERTEX * trans_cost)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_27604_amd", "csrc")
+    for name in ("rw_device.hpp", "rw_internal.hpp", "rw_kernels.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_name: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
+    used only while the kernel sources still hash to the measured version."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel_name)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def micro(args):
+    import ctypes
+
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2606_27604_amd", "librw_micro.so"))
+    lib.rw_micro_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.rw_micro_run.restype = ctypes.c_float
+    names = ["fma_f32", "mad_u64_u32", "xor3_b32", "log_f32", "sin_f32", "rcp_f32", "sqrt_f32",
+             "rsq_f32", "mul_hi_u32", "philox_block"]
+    grid, iters = N_CU * 16, 4096
+    out = torch.zeros(grid * 256, dtype=torch.int32, device="cuda")
+    res = {}
+    for op, name in enumerate(names):
+        lib.rw_micro_run(op, grid, 64, ctypes.c_void_p(out.data_ptr()))  # warm-up
+        ms = min(lib.rw_micro_run(op, grid, iters, ctypes.c_void_p(out.data_ptr())) for _ in range(3))
+        per = 1 if name == "philox_block" else (16 if name == "mad_u64_u32" else 8)
+        rate = grid * 256.0 * iters * per / (ms * 1e-3)
+        res[name] = rate
+    fma = res["fma_f32"]
+    rep = {k: {"lane_ops_per_s": v, "issue_cost_vs_fma": fma / v} for k, v in res.items()}
+    rep["issue_peak_lane_slots_per_s"] = ISSUE_PEAK
+    rep["fma_fraction_of_issue_peak"] = fma / ISSUE_PEAK
+    print(json.dumps(rep, indent=1))
+
+
+def cpu_baseline(wl, seed, max_seconds=30.0):
+    """The FP64 oracle on the host on a bounded sample of the same workload: all
+    81 wavelengths at fewer paths (forward + adjoint)."""
+    from oracle import oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))  # the host share of one GPU
+    paths = 1 << 13
+    geo = O.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins)
+    total_v, total_t = 0, 0.0
+    rng = np.random.default_rng(99)
+    cot_B = rng.standard_normal((wl.n_units, wl.n_bins + 2))
+    while True:
+        t0 = time.perf_counter()
+        _, _, vert = O.forward(geo, wl.sigma_t, wl.albedo, wl.g, wl.weight, paths, seed,
+                               n_threads=cores)
+        O.adjoint(geo, wl.sigma_t, wl.albedo, wl.g, wl.weight, paths, seed,
+                  cot_R=np.ones(wl.n_units), cot_bins=cot_B, n_threads=cores)
+        dt = time.perf_counter() - t0
+        total_v, total_t = 2 * int(vert.sum()), dt
+        if dt > 4.0 or paths >= (1 << 17) or dt * 2 > max_seconds:
+            break
+        paths *= 2
+    return {"value": total_v / total_t, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "sample": f"81 wavelengths x {paths} paths (forward + adjoint), FP64, "
+                      f"{total_v} vertices in {total_t:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--c3-sets", type=int, default=65536)
+    ap.add_argument("--c3-plain-sets", type=int, default=512)
+    ap.add_argument("--micro", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run an elementwise copy of 256 MiB in / 256 MiB out (reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the walk shards by unit with no communication, and "
+              "this build runs on a single MI355X; --gpus above 1 is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_27604_amd import api, rw, workloads
+
+    if args.micro:
+        micro(args)
+        return
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    ctx = rw.Context(0)
+    stream = torch.cuda.current_stream()
+    wl = workloads.config2()
+    media = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_sets, wl.n_wl)
+    geom = rw.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins, r_min_mm=wl.r_min_mm,
+                       r_max_mm=wl.r_max_mm)
+    n, P = wl.n_units, wl.paths_per_unit
+    rng = np.random.default_rng(2024)
+    cot_R = torch.ones(n, dtype=torch.float32, device="cuda")
+    cot_B = torch.from_numpy(rng.standard_normal((n, wl.n_bins + 2)).astype(np.float32)).cuda()
+    tally = rw.Tally(n, wl.n_bins)
+    R_mean = torch.empty(n, dtype=torch.float64, device="cuda")
+    R_se, Rr, Rr_se, Pd = (torch.empty_like(R_mean), torch.empty((n, wl.n_bins), dtype=torch.float64,
+                                                                  device="cuda"), None, None)
+    Rr_se = torch.empty_like(Rr)
+    Pd = torch.empty_like(Rr)
+    grad = torch.empty((n, 12), dtype=torch.float64, device="cuda")
+    sumsq = torch.empty_like(grad)
+    avert = torch.empty(n, dtype=torch.int64, device="cuda")
+    aflags = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def step(seed, batched, ev=None):
+        if ev:
+            ev[0].record(stream)
+        if batched:
+            rw.rw_batch_forward(ctx, media, geom, None, P, seed, tally, autotune=args.autotune,
+                                stream=stream)
+        else:
+            rw.rw_forward(ctx, media, geom, P, seed, tally, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        rw.rw_finalize(ctx, geom, n, None, P, tally, R_mean, R_se, Rr, Rr_se, Pd, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        if batched:
+            rw.rw_batch_adjoint(ctx, media, geom, None, P, seed, cot_R, cot_B, grad, sumsq, avert,
+                                aflags, autotune=args.autotune, stream=stream)
+        else:
+            rw.rw_adjoint(ctx, media, geom, P, seed, cot_R, cot_B, grad, sumsq, avert, aflags,
+                          stream=stream)
+        if ev:
+            ev[3].record(stream)
+
+    def run(batched, seed0):
+        for i in range(args.warmup):
+            step(seed0 + 1000 + i, batched)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        verts = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(seed0 + i, batched, evs[i])
+            verts.append((tally.vertices, avert))
+            # vertex counts of this step (device int64), summed without a sync
+            verts[-1] = (tally.vertices.sum(), avert.sum())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
+        fin_ms = [e[1].elapsed_time(e[2]) for e in evs]
+        adj_ms = [e[2].elapsed_time(e[3]) for e in evs]
+        vf = [int(a.item()) for a, _ in verts]
+        va = [int(b.item()) for _, b in verts]
+        return dict(wall=wall, fwd_ms=fwd_ms, fin_ms=fin_ms, adj_ms=adj_ms, vf=vf, va=va)
+
+    bat = run(True, 1)
+    flags = rw.rw_check(ctx, tally.flags) | rw.rw_check(ctx, aflags)
+    plain = None if args.no_plain else run(False, 1)
+
+    total_v = sum(bat["vf"]) + sum(bat["va"])
+    value = total_v / bat["wall"]
+    ms_per_step = 1e3 * bat["wall"] / args.steps
+    fwd_avg = float(np.mean(bat["fwd_ms"]))
+    adj_avg = float(np.mean(bat["adj_ms"]))
+    vf_avg = float(np.mean(bat["vf"]))
+    va_avg = float(np.mean(bat["va"]))
+    slots = alg_slots_per_vertex()
+    if adj_avg >= fwd_avg:
+        dom, dom_ms, dom_v = "walk_kernel<3, adjoint>", adj_avg, va_avg
+    else:
+        dom, dom_ms, dom_v = "walk_kernel<3, forward>", fwd_avg, vf_avg
+    achieved = slots * dom_v / (dom_ms * 1e-3) / 1e12
+    peak = ISSUE_PEAK / 1e12
+    traffic = load_traffic(dom)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded parameter draws; no dataset or trained weights)",
+        "config": {"workload": "mixture3-81wl: 81 wavelengths x 2^20 paths, K=3, n=1.4, "
+                               "256 log bins [1e-3, 50] mm; step = batched forward + finalize + "
+                               "batched adjoint (path replay), fresh seed per step",
+                   "units": n, "paths_per_unit": P, "parallelism": "single GPU"},
+        "forward_ms": fwd_avg,
+        "adjoint_ms": adj_avg,
+        "finalize_ms": float(np.mean(bat["fin_ms"])),
+        "forward_vertices_per_s": vf_avg / (fwd_avg * 1e-3),
+        "adjoint_vertices_per_s": va_avg / (adj_avg * 1e-3),
+        "vertices_per_step": vf_avg + va_avg,
+        "spectra_per_s": wl.n_sets * args.steps / bat["wall"],
+        "device_flags": flags,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                     "frac": achieved / peak, "traffic": traffic, "kernel": dom,
+                     "slots_per_vertex": slots,
+                     "note": "VALU lane-slots (issue-cost weighted algorithmic ops) per second"},
+    }
+    if plain is not None:
+        pv = sum(plain["vf"]) + sum(plain["va"])
+        out["plain"] = {"ms_per_step": 1e3 * plain["wall"] / args.steps,
+                        "vertices_per_s": pv / plain["wall"],
+                        "forward_ms": float(np.mean(plain["fwd_ms"])),
+                        "adjoint_ms": float(np.mean(plain["adj_ms"]))}
+        out["batched_over_plain_speedup"] = plain["wall"] / bat["wall"]
+        out["matched_statistical_error"] = (plain["vf"] == bat["vf"])
+    del tally, grad, sumsq
+    torch.cuda.empty_cache()
+
+    if not args.no_c3:
+        out["batched_sweep"] = c3(ctx, rw, api, workloads, torch, args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, seed=5)
+    print(json.dumps(out), flush=True)
+
+
+def c3(ctx, rw, api, workloads, torch, args):
+    """65,536 sets x 16 wavelengths x 4,096 paths: one persistent launch, and
+    per-set plain launches timed on a subset of sets (same seeds, same estimates)."""
+    wl = workloads.config3(n_sets=args.c3_sets)
+    media = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_sets, wl.n_wl)
+    geom = rw.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins)
+    n, P = wl.n_units, wl.paths_per_unit
+    tally = rw.Tally(n, wl.n_bins)
+    s = torch.cuda.current_stream()
+    rw.rw_batch_forward(ctx, media, geom, None, P, 7, tally, stream=s)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    rw.rw_batch_forward(ctx, media, geom, None, P, 7, tally, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    full_ms = e0.elapsed_time(e1)
+    full_v = int(tally.vertices.sum().item())
+    res = {"workload": f"batched-{wl.n_sets}x16: K=3, n=1.4, 4096 paths per unit",
+           "units": n, "batched_ms": full_ms, "batched_vertices_per_s": full_v / (full_ms * 1e-3),
+           "spectra_per_s": wl.n_sets / (full_ms * 1e-3)}
+    # like for like on a subset: per-set plain launches vs one batched launch
+    S = min(args.c3_plain_sets, wl.n_sets)
+    U = S * wl.n_wl
+    sub_media = media.unit_range(0, U)
+    sub_tally_b = rw.Tally(U, wl.n_bins)
+    sub_tally_p = rw.Tally(U, wl.n_bins)
+    rw.rw_batch_forward(ctx, sub_media, geom, None, P, 7, sub_tally_b, stream=s)
+    torch.cuda.synchronize()
+    e0.record(s)
+    rw.rw_batch_forward(ctx, sub_media, geom, None, P, 7, sub_tally_b, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sub_b_ms = e0.elapsed_time(e1)
+    per_set = [(media.unit_range(i * wl.n_wl, wl.n_wl), sub_tally_p.view(i * wl.n_wl, wl.n_wl))
+               for i in range(S)]
+    for m_i, t_i in per_set[:8]:
+        rw.rw_forward(ctx, m_i, geom, P, 7, t_i, stream=s)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for m_i, t_i in per_set:
+        rw.rw_forward(ctx, m_i, geom, P, 7, t_i, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sub_p_ms = e0.elapsed_time(e1)
+    same = bool(torch.equal(sub_tally_b.vertices, sub_tally_p.vertices) and
+                torch.allclose(sub_tally_b.R, sub_tally_p.R, rtol=1e-12, atol=0))
+    res.update({"subset_sets": S, "subset_batched_ms": sub_b_ms, "subset_per_set_plain_ms": sub_p_ms,
+                "per_set_over_batched_time": sub_p_ms / sub_b_ms,
+                "same_estimates_as_batched": same})
+    return res
+
+
+if __name__ == "__main__":
+    main()

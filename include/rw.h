@@ -18,7 +18,7 @@
  *   z is depth, the medium fills z >= 0 (and z <= slab_mm for a slab); the
  *   beam enters at r = 0 along +z with weight 1 - F(0), F(0) = ((n-1)/(n+1))^2
  *   (the specular part is not in R).  Per path, Philox4x32-10 (Salmon et al.,
- *   SC'11) with key = seed and counter = (vertex, path, unit, stream tag)
+ *   SC'11) with key = seed and counter = (vertex, path, stream tag, unit)
  *   gives one block of four words per vertex; word w -> ((w >> 9) + 0.5) 2^-23.
  *   Vertex 0: medium = first k with u0 < cumulative weight.  Vertex v >= 1:
  *   flight s = -ln(u0)/sigma_t; when it crosses the surface the photon moves
@@ -120,23 +120,26 @@ typedef struct {
 } rw_tally;
 
 /* Forward walk, plain form: one launch over a static grid of
- * (unit, chunk of paths); every unit runs `paths_per_unit` paths (1..2^31).
- * Results are deterministic: each chunk's sums are reduced in chunk order. */
+ * (unit, chunk of paths) work items, one item per wavefront; every unit runs
+ * `paths_per_unit` paths (0..2^31).  Sums are exact (per path, 32-bit fixed
+ * point; per unit, 64-bit integer sums, converted to FP64 at the end), so
+ * results are bit-identical for the same seed whatever the launch shape or
+ * scheduling.  A call with more than one work item per unit uses a device
+ * workspace of (n_bins + 2) * 16 + 40 bytes per work item (4096 paths). */
 rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                      int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
 
 /* Batched persistent form of the forward walk: a persistent grid pulls
- * (unit, chunk) work items from a device queue, long-path units first, with
- * chunk sizes balanced by estimated path length.  `paths_per_unit` is a
- * DEVICE int32 array [n_units] (uneven counts allowed, 0 allowed) or NULL, in
- * which case every unit runs `paths_uniform` paths.  The estimates equal
- * rw_forward's for the same seed (same random numbers per path); sums are
- * reduced in chunk order, so tallies are deterministic. */
+ * (unit, chunk) work items from a device queue, units with the longest
+ * estimated paths first, and wavefronts move on to further items without
+ * waiting for an item's slowest path.  `paths_per_unit` is a DEVICE int32
+ * array [n_units] (uneven counts allowed, 0 allowed; entries above
+ * paths_uniform are clamped to it) or NULL, in which case every unit runs
+ * `paths_uniform` paths.  Same random numbers per path as rw_forward, hence
+ * bit-identical tallies for the same seed and path counts. */
 typedef struct {
-  int32_t use_graph;            /* capture the launch sequence in a hipGraph and replay it */
+  int32_t use_graph;            /* build the launch sequence as a hipGraph and replay it */
   int32_t autotune;             /* time candidate launch shapes on first use, cache them */
-  int32_t deterministic_reduce; /* 1: per-chunk partials reduced in order (default);
-                                   0: device atomics (no workspace) */
   int64_t unit_begin, unit_end; /* resume window [begin, end) of units; end <= 0: all.
                                    Units outside the window are left untouched. */
 } rw_batch_opts;
@@ -157,7 +160,10 @@ rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geom
  *   logit_j:   [k == j] - w_j          (w = softmax of the logits),
  * i.e. the gradient of sum_u (cot_R[u] * R_sum[u] + sum_s cot_bins[u][s] * bins[u][s][0]).
  * Output layout grad[n_units][4K] = (sigma_t[K], alpha[K], g[K], logit[K]);
- * raw sums (divide by the path count for the gradient of the means).
+ * raw sums (divide by the path count for the gradient of the means), summed
+ * in FP64: the same seed gives the same per-path terms whatever the launch
+ * shape, and the sums agree to FP64 rounding (their order follows the
+ * schedule, so they are reproducible to rounding, not bitwise).
  * cot_R: DEVICE float [n_units] or NULL (zero); cot_bins: DEVICE float
  * [n_units][n_bins + 2] or NULL (zero).  grad_sumsq (DEVICE double
  * [n_units][4K] or NULL) receives the sums of squares of the per-path terms.
@@ -197,7 +203,7 @@ rw_status rw_check(rw_context* ctx, const int32_t* flags, int32_t* out_flags, vo
 /* Per-path replay for tests: runs n_paths paths of ONE unit (media with
  * n_sets = n_wl = 1) with the random words taken from `words` (DEVICE uint32
  * [n_paths][n_blocks][4], block v of path p) or, when words is NULL, from
- * Philox with counter (v, p, unit_index, 0).  Writes per vertex
+ * Philox with counter (v, p, 0, unit_index).  Writes per vertex
  * events[p][v][8] = (code, x, y, z, ux, uy, uz, W) with code 0 start,
  * 1 collision, 2 reflection, 3 top exit, 4 bottom exit, 5 roulette kill,
  * 6 vertex cap (state after the vertex; zero-filled beyond the path end), and

@@ -248,7 +248,8 @@ def adjoint(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, cot_R=None, 
 
 
 def trace(geo: Geometry, sigma_t, albedo, g, w, words=None, n_paths: int | None = None,
-          n_blocks: int = 64, seed: int = 0, unit: int = 0, tag: int = 0):
+          n_blocks: int = 64, seed: int = 0, unit: int = 0, tag: int = 0,
+          with_events: bool = True):
     """Per-path replay of one unit.  words: uint32 [n_paths, n_blocks, 4] or None
     (Philox).  Returns (events [n_paths, n_blocks, 8], path_out [n_paths, 8],
     path_adj [n_paths, 2])."""
@@ -259,13 +260,13 @@ def trace(geo: Geometry, sigma_t, albedo, g, w, words=None, n_paths: int | None 
         words = np.ascontiguousarray(np.asarray(words, dtype=np.uint32))
         n_paths, n_blocks = words.shape[0], words.shape[1]
     assert n_paths is not None
-    ev = np.zeros((n_paths, n_blocks, 8))
+    ev = np.zeros((n_paths, n_blocks, 8)) if with_events else None
     out = np.zeros((n_paths, 8))
     adj = np.zeros((n_paths, 2))
     cg = geo.c()
     rc = lib().orc_trace(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(ww),
                          _u32ptr(words) if words is not None else None, n_paths, n_blocks, seed,
-                         unit, tag, _dptr(ev), _dptr(out), _dptr(adj))
+                         unit, tag, _dptr(ev) if ev is not None else None, _dptr(out), _dptr(adj))
     if rc != 0:
         raise ValueError(f"orc_trace failed with code {rc}")
     return ev, out, adj

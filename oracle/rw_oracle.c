@@ -34,7 +34,7 @@
  *     phi = 2*pi*u2 measured from the first tangent of the Duff et al. (2017)
  *     orthonormal frame of the current direction;
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
- *     counter = (vertex, path, unit, stream tag), one block of four words per
+ *     counter = (vertex, path, stream tag, unit), one block of four words per
  *     vertex, word -> ((w >> 9) + 0.5) * 2^-23 in (0, 1);
  *   - exit radius binned in n_bins log-spaced bins over [r_min, r_max) with an
  *     underflow slot 0 and an overflow slot n_bins + 1.
@@ -251,7 +251,7 @@ static int get_block(const block_source* src, int64_t v, double u[4]) {
   if (src->words) {
     for (int i = 0; i < 4; ++i) w[i] = src->words[v * 4 + i];
   } else {
-    uint32_t ctr[4] = {(uint32_t)v, src->path, src->unit, src->tag};
+    uint32_t ctr[4] = {(uint32_t)v, src->path, src->tag, src->unit};
     philox4x32_10(ctr, src->key, w);
   }
   for (int i = 0; i < 4; ++i) u[i] = u01(w[i]);

@@ -17,8 +17,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librw.so")
+MICRO_LIB = os.path.join(PKG, "librw_micro.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["rw_kernels.hip", "rw_runtime.hip"]
+MICRO_SOURCES = ["rw_micro.hip"]
 HEADERS = ["rw_device.hpp", "rw_internal.hpp"]
 
 HIPCC_FLAGS = [
@@ -29,6 +31,9 @@ HIPCC_FLAGS = [
     "-Wall",
     "-Wno-unused-result",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # tally atomics come from one or two lanes at a time: plain atomics, not
+    # the compiler's lane-serialising reduction loop around each of them
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
@@ -40,23 +45,30 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link librw.so (always rebuilds)."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def _link(sources, lib, verbose):
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
         cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True, cwd=BUILD_DIR, stderr=subprocess.PIPE if not verbose else None)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=BUILD_DIR)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link librw.so and the micro-benchmark library
+    librw_micro.so (always rebuilds)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    _link(SOURCES, LIB, verbose)
+    _link(MICRO_SOURCES, MICRO_LIB, verbose)
     return LIB
 
 

@@ -16,35 +16,36 @@ namespace rw {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round is two
-// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs; the key
-// schedule is wave-uniform and lives in scalar registers.
+// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs.  The
+// key schedule k + r * (0x9E3779B9, 0xBB67AE85) is wave-uniform; it is
+// recomputed with scalar adds inside every call (the empty asm makes the base
+// key opaque, so the compiler cannot hoist the ten round keys out of the walk
+// loop, where they would occupy twenty scalar registers and spill).
 // ---------------------------------------------------------------------------
 struct PhiloxKey {
-  uint32_t k0[10], k1[10];
+  uint32_t k0, k1;
 };
 
 __device__ __forceinline__ PhiloxKey philox_schedule(uint32_t k0, uint32_t k1) {
-  PhiloxKey s;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    s.k0[r] = k0 + uint32_t(r) * 0x9E3779B9u;
-    s.k1[r] = k1 + uint32_t(r) * 0xBB67AE85u;
-  }
-  return s;
+  return PhiloxKey{k0, k1};
 }
 
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        const PhiloxKey& ks) {
+                                        const PhiloxKey& key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
     const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
-    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ ks.k0[r];
-    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ ks.k1[r];
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
     c1 = uint32_t(p1);
     c3 = uint32_t(p0);
     c0 = n0;
     c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
   }
   return make_uint4(c0, c1, c2, c3);
 }
@@ -135,9 +136,9 @@ __device__ __forceinline__ float fresnel(float ci, float n, float n2) {
   return 0.5f * fmaf(rs, rs, rp * rp);
 }
 
-// Radial slot of an exit point: 0 below r_min, 1..n_bins, n_bins+1 at/above r_max.
-__device__ __forceinline__ int radial_slot(float x, float y, const WalkGeom& geo) {
-  const float r = __builtin_amdgcn_sqrtf(fmaf(x, x, y * y));
+// Radial slot of an exit radius: 0 below r_min, 1..n_bins, n_bins+1 at/above r_max.
+template <class G>
+__device__ __forceinline__ int radial_slot_r(float r, const G& geo) {
   if (!(r >= geo.r_min)) return 0;
   if (r >= geo.r_max) return geo.n_bins + 1;
   const float t = (__builtin_amdgcn_logf(r) - geo.log2_rmin) * geo.bin_scale;
@@ -145,6 +146,47 @@ __device__ __forceinline__ int radial_slot(float x, float y, const WalkGeom& geo
   b = b < 0 ? 0 : (b > geo.n_bins - 1 ? geo.n_bins - 1 : b);
   return b + 1;
 }
+
+__device__ __forceinline__ float exit_radius(float x, float y) {
+  return __builtin_amdgcn_sqrtf(fmaf(x, x, y * y));
+}
+
+template <class G>
+__device__ __forceinline__ int radial_slot(float x, float y, const G& geo) {
+  return radial_slot_r(exit_radius(x, y), geo);
+}
+
+// The same value, held in a vector register.  The walk loop needs more
+// wave-uniform constants than fit in scalar registers next to its control
+// state; constants it reads as VALU operands cost nothing in vector registers,
+// whereas spilled scalars are re-read with one v_readlane per use.
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+// The constants the vertex step reads, in vector registers; the rest of the
+// geometry is read from LDS where it is needed (cold constants, below).
+__device__ __forceinline__ WalkGeom step_geom_in_vgprs(const WalkGeom& g) {
+  WalkGeom r = g;
+  r.n_rel = in_vgpr(g.n_rel);
+  r.n_rel2 = in_vgpr(g.n_rel2);
+  r.slab_mm = in_vgpr(g.slab_mm);
+  r.rr_weight = in_vgpr(g.rr_weight);
+  r.rr_survive = in_vgpr(g.rr_survive);
+  r.rr_boost = in_vgpr(g.rr_boost);
+  r.max_vertices = in_vgpr(g.max_vertices);
+  return r;
+}
+
+// Constants needed only when a path starts or a batch of ends is tallied;
+// the walk kernel keeps them in LDS (two 16-byte words).
+struct ColdConst {
+  float r_min, r_max, log2_rmin, bin_scale;
+  int32_t n_bins;
+  float entry_weight, fix_scale, fix_cap;
+};
 
 // ---------------------------------------------------------------------------
 // Unit parameters (wave-uniform) and their device-side validation.
@@ -226,6 +268,20 @@ enum VertexEvent : int {
   EV_CAP = 6
 };
 
+// vertex 0 after the medium k has been chosen: pencil beam entering at the
+// origin along +z with the transmitted weight 1 - F(0)
+__device__ __forceinline__ void init_path(Path& p, int k, const Medium& m, float entry_weight) {
+  p.k = k;
+  p.m = m;
+  p.x = 0.0f; p.y = 0.0f; p.z = 0.0f;
+  p.ux = 0.0f; p.uy = 0.0f; p.uz = 1.0f;
+  p.W = entry_weight;
+  p.A = 0.0f;
+  p.ncoll = 0;
+  p.D = 0.0f;
+  p.Sg = 0.0f;
+}
+
 // vertex 0: choose the medium from u0 (first k with u0 < cumulative weight)
 template <int K>
 __device__ __forceinline__ void start_path(Path& p, uint4 w, const UnitParams<K>& up,
@@ -241,15 +297,46 @@ __device__ __forceinline__ void start_path(Path& p, uint4 w, const UnitParams<K>
     a = (k == j) ? up.alb[j] : a;
     g = (k == j) ? up.g[j] : g;
   }
-  p.k = k;
-  p.m = make_medium(s, a, g);
-  p.x = 0.0f; p.y = 0.0f; p.z = 0.0f;
-  p.ux = 0.0f; p.uy = 0.0f; p.uz = 1.0f;
-  p.W = geo.entry_weight;
-  p.A = 0.0f;
-  p.ncoll = 0;
-  p.D = 0.0f;
-  p.Sg = 0.0f;
+  init_path(p, k, make_medium(s, a, g), geo.entry_weight);
+}
+
+// The walk kernel keeps the current unit's media in LDS rather than in scalar
+// registers (which the vertex loop needs for its own constants): per medium
+// the eight floats {flight, alb, g, hq, inv_sig, gq, gc, 0}, then the
+// cumulative weights.
+template <int K>
+__device__ __forceinline__ void stage_unit(const UnitParams<K>& up, float* tab, int lane) {
+  if (lane < K) {
+    float s = up.sigma_t[0], a = up.alb[0], g = up.g[0], c = up.cum[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j) {
+      s = (lane == j) ? up.sigma_t[j] : s;
+      a = (lane == j) ? up.alb[j] : a;
+      g = (lane == j) ? up.g[j] : g;
+      c = (lane == j) ? up.cum[j] : c;
+    }
+    const Medium m = make_medium(s, a, g);
+    float4* e = reinterpret_cast<float4*>(tab + lane * kMediumFloats);
+    e[0] = make_float4(m.flight, m.alb, m.g, m.hq);
+    e[1] = make_float4(m.inv_sig, m.gq, m.gc, 0.0f);
+    tab[kMediumFloats * kMaxMedia + lane] = c;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <int K>
+__device__ __forceinline__ void start_path_lds(Path& p, uint4 w, const float* tab,
+                                               float entry_weight) {
+  const float u0 = u01(w.x);
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) k += (u0 >= tab[kMediumFloats * kMaxMedia + j]) ? 1 : 0;
+  const float4* e = reinterpret_cast<const float4*>(tab + k * kMediumFloats);
+  const float4 e0 = e[0], e1 = e[1];
+  Medium m;
+  m.flight = e0.x; m.alb = e0.y; m.g = e0.z; m.hq = e0.w;
+  m.inv_sig = e1.x; m.gq = e1.y; m.gc = e1.z;
+  init_path(p, k, m, entry_weight);
 }
 
 // vertex v >= 1: flight, then boundary interaction or collision.  Returns the

@@ -10,6 +10,10 @@ namespace rw {
 constexpr int kMaxMedia = 4;
 constexpr int kWave = 64;
 constexpr uint32_t kForwardTag = 0;  // Philox stream tag shared by forward and adjoint replay
+// LDS table of the walk kernel's current unit: per medium 8 floats, then the
+// cumulative medium weights
+constexpr int kMediumFloats = 8;
+constexpr int kMediaTableFloats = kMediumFloats * kMaxMedia + kMaxMedia;
 
 // Geometry and estimator constants, in the form the kernels use.
 struct WalkGeom {
@@ -26,9 +30,9 @@ struct WalkGeom {
   uint32_t max_vertices;
 };
 
-// How work items map to (unit, path range).  Item i covers unit
-// unit_begin + i / chunks_per_unit and its chunk i % chunks_per_unit; a unit
-// with fewer paths than the bound leaves its trailing items empty.
+// How work items map to (unit, path range).  Item i covers local unit
+// i / chunks_per_unit and its chunk i % chunks_per_unit; a unit with fewer
+// paths than the bound leaves its trailing items empty.
 struct WorkMap {
   int64_t n_units;             // units covered: [unit_begin, unit_begin + n_units)
   int64_t unit_begin;
@@ -37,12 +41,13 @@ struct WorkMap {
   const int32_t* paths;        // device [n_units_total] or nullptr
   int32_t chunk;               // paths per item
   int32_t chunks_per_unit;     // ceil(paths_uniform / chunk)
-  const int32_t* order;        // optional device [n_items] processing order
+  const int32_t* unit_order;   // optional device [n_units]: processing order of the local
+                               // units (longest estimated paths first)
   uint32_t* queue;             // persistent schedule: device counter (nullptr = static grid)
 };
 
 struct WalkArgs {
-  // media, SoA [K][n_units_total]
+  // media, SoA [K][k_stride]
   const float* sigma_t;
   const float* albedo;
   const float* g;
@@ -53,40 +58,61 @@ struct WalkArgs {
   WalkGeom geo;
   WorkMap map;
   uint32_t key0, key1, tag;
-  // forward outputs: per-item partials (deterministic) or direct/atomic outputs
-  double* partial;             // [n_items][part_len] (reduce mode) or nullptr
-  int32_t part_len;
-  int32_t direct;              // 1: one item per unit, write outputs directly
-  int32_t atomic;              // 1: accumulate into zero-filled outputs with device atomics
-  double* R;                   // [n_units_total][4]
-  double* bins;                // [n_units_total][n_bins+2][2]
-  int64_t* vertices;           // [n_units_total]
+  // forward: exact fixed-point sums (64-bit counters of 32-bit per-path
+  // values), one set per slot.  A slot is the work item that opened a wave's
+  // visit of a unit (the visit takes further items of the same unit until the
+  // wave moves to another unit), so no two waves share one; the reduce kernel
+  // sums a unit's slots and converts them to FP64.  When every unit is a single
+  // item (direct), the slot is the unit and the slots are the caller's tally
+  // buffers, converted in place.
+  float fix_scale32;           // 2^s: one unit of weight = 2^s counts
+  float fix_cap;               // per-path values are clamped below x_max (never reached)
+  int32_t direct;
+  int64_t* tb;                 // [slot][n_bins+2][2]
+  int64_t* tc;                 // [slot][4]: T at 2, A at 3
+  int64_t* tv;                 // [slot] vertices
+  double* out_R;               // [n_units_total][4]
+  double* out_bins;            // [n_units_total][n_bins+2][2]
+  int64_t* out_vertices;       // [n_units_total]
   int32_t* flags;
-  // adjoint inputs
+  // adjoint: FP64 sums [slot][K][8] and vertex counts [slot], slot = work item
+  double* adj;
+  int64_t* adj_vertices;
   const float* cot_R;          // [n_units_total] or nullptr
   const float* cot_bins;       // [n_units_total][n_bins+2] or nullptr
-  int32_t lds_doubles_per_wave;
+  // per-wave LDS accumulators (8-byte words)
+  int32_t acc_words;
+  int32_t lds_words_per_wave;
 };
 
-// forward partial layout: [0..3] R sums, [4] vertices, [5..] bins (n_bins+2)*2
-inline int forward_part_len(int n_bins) { return 5 + (n_bins + 2) * 2; }
-// adjoint partial layout: [K][8] = (C, Q, Ss, Ss2, Sa, Sa2, Sg, Sg2), then vertices
-inline int adjoint_part_len(int K) { return K * 8 + 1; }
+// per-wave LDS of the walk kernel (8-byte words): accumulators (forward:
+// (x, x^2) per slot + T, A, vertices; adjoint: K media x 8 FP64 sums +
+// vertices), the media table, the cold constants, the exit ring (kExitRing
+// records of 16 bytes forward, 32 bytes adjoint; a power of two, >= 64)
+constexpr int kExitRing = 64;
+constexpr int kMediaTableWords = (kMediaTableFloats + 1) / 2;
+constexpr int kColdConstWords = 4;  // 32 bytes after the media table
+inline int forward_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
+inline int adjoint_acc_words(int K) { return 8 * K + 2; }
+inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {
+  return acc_words + kMediaTableWords + kColdConstWords + kExitRing * (adjoint ? 4 : 2);
+}
 
 // launchers (rw_kernels.hip); all asynchronous on `stream`
 hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg, int grid_wgs,
                        hipStream_t stream);
-hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
-hipError_t launch_fill_i64(int64_t* p, int64_t n, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
-hipError_t launch_reduce_forward(const WalkArgs& a, hipStream_t stream);
-hipError_t launch_reduce_adjoint(const WalkArgs& a, int K, double* grad, double* grad_sumsq,
-                                 hipStream_t stream);
-const void* walk_kernel_ptr(int K, bool adjoint);
-const void* fill_u32_kernel_ptr();
-const void* reduce_forward_kernel_ptr();
-const void* reduce_adjoint_kernel_ptr(int K);
-int walk_lds_bytes(const WalkArgs& a, int waves_per_wg);
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, hipStream_t stream);
+// forward: sum each unit's int64 fixed-point slots -> FP64 outputs, R sums from the bins
+constexpr int kConvertThreads = 256;
+// convert kernels loop over units with a grid stride
+inline unsigned convert_blocks(int64_t n_units) {
+  return unsigned(n_units < (int64_t(1) << 20) ? n_units : (int64_t(1) << 20));
+}
+hipError_t launch_convert_forward(const WalkArgs& a, hipStream_t stream);
+// adjoint: FP64 sums -> gradients (and sums of squares), logits from the weights
+hipError_t launch_convert_adjoint(const WalkArgs& a, int K, double* grad, double* grad_sumsq,
+                                  int64_t* vertices_out, hipStream_t stream);
 hipError_t launch_finalize(const WalkGeom& geo, int64_t n_units, const int32_t* paths,
                            int64_t paths_uniform, const double* R, const double* bins,
                            double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,
@@ -96,5 +122,22 @@ hipError_t launch_trace(const WalkArgs& a, int K, const uint32_t* words, int64_t
                         float* path_adj, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
                          hipStream_t stream);
+
+// longest-first unit order for the persistent schedule: bucket[n_units] and
+// unit_order[n_units] int32, hist[kOrderBuckets] uint32 (cleared by the caller)
+constexpr int kOrderBuckets = 64;
+hipError_t launch_unit_order(const WalkArgs& a, int K, int32_t* bucket, uint32_t* hist,
+                             int32_t* unit_order, hipStream_t stream);
+
+// kernel entry points, for graph nodes
+const void* walk_kernel_ptr(int K, bool adjoint);
+const void* fill_u32_kernel_ptr();
+const void* fill_u64_kernel_ptr();
+const void* unit_cost_kernel_ptr(int K);
+const void* order_scan_kernel_ptr();
+const void* order_scatter_kernel_ptr();
+const void* convert_forward_kernel_ptr();
+const void* convert_adjoint_kernel_ptr(int K);
+int walk_lds_bytes(const WalkArgs& a, int waves_per_wg);
 
 }  // namespace rw

@@ -1,15 +1,20 @@
 // HIP kernels of the random walk for gfx950 and their launchers.
 //
-// Work decomposition: a work item is (unit, chunk of consecutive path indices)
-// and is processed by ONE wavefront.  Lanes regenerate: a lane whose path
-// ended takes the next path index of the chunk (ballot + mbcnt, no atomics),
-// so a wave stays full until its chunk runs dry.  Each loop iteration draws one
-// Philox block per lane and processes one vertex.  Tallies: per-lane FP64
-// registers for the totals, a per-wave FP64 histogram in LDS (ds_add_f64) for
-// the radial slots; at the end of an item the wave writes its partial sums to
-// the item's slot of a workspace (or straight to the outputs when a unit is a
-// single item), and a reduction kernel sums the slots of each unit in item
-// order, so results do not depend on scheduling.
+// Work decomposition.  A work item is (unit, chunk of consecutive path
+// indices).  A wavefront takes items one after another (a static grid takes
+// one item per wave; the persistent grid pulls items from a device queue in
+// longest-first unit order) and its lanes regenerate: a lane whose path ended
+// takes the next path index, from the current item or, once that is used up,
+// from the next item, so lanes never wait for the slowest path of an item.
+// Each loop iteration draws one Philox block per lane and processes one
+// vertex.
+//
+// Tallies.  The forward sums are exact integers (32-bit fixed point per
+// path, 64-bit counters), so they are bit-identical whatever the schedule,
+// the launch shape or the order of atomics; the adjoint sums are FP64.  The
+// wave's current unit accumulates in LDS (flushed to global memory with
+// atomics when the wave moves to another unit); paths of an earlier unit
+// still in flight add straight to global memory.
 #include <hip/hip_runtime.h>
 
 #include "../../include/rw.h"
@@ -18,18 +23,15 @@
 
 namespace rw {
 
+using u64 = unsigned long long;
+
+// vertex count above which a path counts as long (priority boost)
+constexpr uint32_t kLongPath = 256;
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
 }
 
 // item -> (local unit, first path, end path); pb >= pe for an empty item
@@ -47,277 +49,550 @@ __device__ __forceinline__ void map_item(const WorkMap& m, int64_t item, int64_t
   if (pe > n) pe = n;
 }
 
-// number of non-empty items of a unit
-__device__ __forceinline__ int64_t unit_items(const WorkMap& m, int64_t ul) {
-  int64_t n = m.paths_uniform;
-  if (m.paths != nullptr) {
-    const int64_t q = m.paths[m.unit_begin + ul];
-    n = q < 0 ? 0 : (q < n ? q : n);
+// next work item of the calling wave (wave-uniform), or -1 when none is left
+__device__ __forceinline__ int64_t next_item(const WalkArgs& a, int64_t& static_item, int lane) {
+  if (a.map.queue == nullptr) {
+    const int64_t it = static_item;
+    static_item = -1;
+    return (it >= 0 && it < a.map.n_items) ? it : -1;
   }
-  return (n + m.chunk - 1) / m.chunk;
+  uint32_t t = 0;
+  if (lane == 0) t = atomicAdd(a.map.queue, 1u);
+  const int64_t k = int64_t(__builtin_amdgcn_readfirstlane(t));
+  if (k >= a.map.n_items) return -1;
+  if (a.map.unit_order == nullptr) return k;
+  const int64_t pos = k / a.map.chunks_per_unit;
+  return int64_t(a.map.unit_order[pos]) * a.map.chunks_per_unit + (k - pos * a.map.chunks_per_unit);
 }
 
-// One work item: paths [pb, pe) of unit u, processed by the calling wave.
-template <int K, bool ADJ>
-__device__ void walk_item(const WalkArgs& a, const PhiloxKey& ks, int64_t u, int64_t pb, int64_t pe,
-                          int64_t item, double* wl, int lane) {
-  if (pb >= pe && !a.direct) return;  // empty trailing item: the reduction skips it
-  const UnitParams<K> up = load_unit<K>(a, u);
-  const WalkGeom& geo = a.geo;
-  if (!up.ok) {
-    if (lane == 0) atomicOr(a.flags, RW_FLAG_BAD_PARAMS);
-    pe = pb;
-  }
-  float cotR = 0.0f;
-  const float* cotB = nullptr;
-  if (ADJ) {
-    if (a.cot_R) cotR = a.cot_R[u];
-    if (a.cot_bins) cotB = a.cot_bins + u * int64_t(geo.n_bins + 2);
-  }
-  double sx = 0.0, sx2 = 0.0, sT = 0.0, sA = 0.0;
-  uint32_t nv = 0;
-  bool capped = false;
-  Path p;
-  bool alive = false;
-  uint32_t path = 0, v = 0;
-  int64_t cursor = pb;
-  for (;;) {
-    const uint64_t need = __ballot(!alive);
-    if (need) {
-      if (!alive) {
-        const uint32_t rank =
-            __builtin_amdgcn_mbcnt_hi(uint32_t(need >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(need), 0u));
-        const int64_t cand = cursor + rank;
-        if (cand < pe) {
-          path = uint32_t(cand);
-          v = 0;
-          alive = true;
-        }
-      }
-      cursor += __popcll(need);
-    }
-    if (!__any(alive)) break;
-    if (alive) {
-      const uint4 w = philox(v, path, uint32_t(u), a.tag, ks);
-      if (v == 0) {
-        start_path<K>(p, w, up, geo);
-      } else {
-        ++nv;
-        const int ev = vertex_step<ADJ>(p, w, geo);
-        if (ev >= EV_EXIT_TOP) {
-          alive = false;
-          sA += double(p.A);
-          if (ev == EV_EXIT_TOP) {
-            const int slot = radial_slot(p.x, p.y, geo);
-            const double x = double(p.W);
-            if (!ADJ) {
-              sx += x;
-              sx2 += x * x;
-              atomicAdd(&wl[2 * slot], x);
-              atomicAdd(&wl[2 * slot + 1], x * x);
-            } else {
-              const double c = x * double(cotR + (cotB ? cotB[slot] : 0.0f));
-              if (c != 0.0) {
-                const float nc = float(p.ncoll);
-                const double ss = double(p.D);
-                const double sa = p.ncoll ? double(nc / p.m.alb) : 0.0;
-                const double sg = double(fmaf(nc, p.m.gc, p.Sg));
-                double* acc = wl + 8 * p.k;
-                atomicAdd(&acc[0], c);
-                atomicAdd(&acc[1], c * c);
-                atomicAdd(&acc[2], c * ss);
-                atomicAdd(&acc[3], (c * ss) * (c * ss));
-                atomicAdd(&acc[4], c * sa);
-                atomicAdd(&acc[5], (c * sa) * (c * sa));
-                atomicAdd(&acc[6], c * sg);
-                atomicAdd(&acc[7], (c * sg) * (c * sg));
-              }
-            }
-          } else if (ev == EV_EXIT_BOTTOM) {
-            sT += double(p.W);
-          }
-        }
-      }
-      ++v;
-      if (alive && v > geo.max_vertices) {
-        alive = false;
-        capped = true;
-        sA += double(p.A);
-      }
-    }
-  }
-  if (__any(capped) && lane == 0) atomicOr(a.flags, RW_FLAG_VERTEX_CAP);
+// ---- accumulation ------------------------------------------------------------
+// Forward sums are exact integers: a per-path value x in [0, x_max) becomes
+// round(x * 2^s) (32 bits, s = 31 - ceil(log2 x_max)) and is added to 64-bit
+// counters, so a unit's sums do not depend on the order in which paths end,
+// on the schedule or on the launch shape.
+__device__ __forceinline__ u64 fix32(float x, float scale, float cap) {
+  return u64(uint32_t(fmaf(__builtin_amdgcn_fmed3f(x, 0.0f, cap), scale, 0.5f)));
+}
 
-  // flush: per-wave sums -> item slot (or the unit's outputs)
+// In a 64-lane wave some lane ends its path in almost every iteration, so
+// whatever an ending path costs inline is paid per iteration.  A path of the
+// wave's current unit therefore only appends an exit record to a ring in LDS;
+// once a batch of 64 records is waiting, the whole wave tallies them, one per
+// lane.  Records (forward, 16 bytes): {W, A, where, vertices} with where = the
+// exit radius for a top exit, -1 for a bottom exit, -2 otherwise.  Adjoint (32
+// bytes): {W at a top exit else 0, radius, score_sigma, score_alpha} and
+// {score_g, medium, vertices, 0}.
+constexpr float kWhereBottom = -1.0f;
+constexpr float kWhereNone = -2.0f;
+
+// LDS region of one wave (8-byte words).  Forward: bins [n_bins+2][2] (sum of
+// x and x^2 per slot), then the counters T, A, vertices.  Adjoint: FP64
+// [K][8], then the vertex counter.  Both: then the unit's media table, the
+// cold constants and the exit ring of kExitRing records.  Before a batch of
+// ending paths is appended, the ring is tallied if the batch might not fit, so
+// it never holds more than kExitRing records.
+struct WaveLds {
+  u64* acc;         // accumulators (cleared at start and at each flush)
+  u64* ctr;         // wave counters inside acc
+  float* media;
+  ColdConst* cold;
+  float4* ring;
+};
+
+// Read from LDS where used: reads that a store in the loop may alias stay in
+// place instead of being hoisted into registers for the whole loop.
+__device__ __forceinline__ ColdConst read_cold(const WaveLds& L) {
+  const float4* q = reinterpret_cast<const float4*>(L.cold);
+  const float4 c0 = q[0], c1 = q[1];
+  ColdConst c;
+  c.r_min = c0.x; c.r_max = c0.y; c.log2_rmin = c0.z; c.bin_scale = c0.w;
+  c.n_bins = __float_as_int(c1.x); c.entry_weight = c1.y; c.fix_scale = c1.z; c.fix_cap = c1.w;
+  return c;
+}
+
+__device__ __forceinline__ float exit_where(int ev, const Path& p) {
+  return ev == EV_EXIT_TOP ? exit_radius(p.x, p.y)
+                           : (ev == EV_EXIT_BOTTOM ? kWhereBottom : kWhereNone);
+}
+
+// Tally records [head, head + n) of the ring (n <= 64), one per lane.
+__device__ __forceinline__ void tally_forward(const WaveLds& L, uint32_t head, uint32_t n,
+                                              int lane) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const uint64_t nvt = wave_sum_u64(uint64_t(nv));
-  const int nd = a.lds_doubles_per_wave;
+  if (uint32_t(lane) < n) {
+    const ColdConst cc = read_cold(L);
+    const float sc = cc.fix_scale, cap = cc.fix_cap;
+    const float4 r = L.ring[(head + lane) & (kExitRing - 1)];
+    if (r.z >= 0.0f) {
+      const int slot = radial_slot_r(r.z, cc);
+      atomicAdd(&L.acc[2 * slot], fix32(r.x, sc, cap));
+      atomicAdd(&L.acc[2 * slot + 1], fix32(r.x * r.x, sc, cap));
+    } else if (r.z == kWhereBottom) {
+      atomicAdd(&L.ctr[0], fix32(r.x, sc, cap));
+    }
+    atomicAdd(&L.ctr[1], fix32(r.y, sc, cap));
+    atomicAdd(&L.ctr[2], u64(__float_as_uint(r.w)));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <int K>
+__device__ __forceinline__ void tally_adjoint(const WalkArgs& a, const WaveLds& L, uint32_t unit,
+                                              uint32_t head, uint32_t n, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (uint32_t(lane) < n) {
+    const uint32_t i = (head + lane) & (kExitRing - 1);
+    const float4 r0 = L.ring[2 * i], r1 = L.ring[2 * i + 1];
+    atomicAdd(&L.ctr[0], u64(__float_as_uint(r1.z)));
+    if (r0.x > 0.0f) {
+      const ColdConst cc = read_cold(L);
+      const int slot = radial_slot_r(r0.y, cc);
+      float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
+      if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + slot];
+      const double c = double(r0.x) * double(cot);
+      if (c != 0.0) {
+        const double css = c * double(r0.z), csa = c * double(r0.w), csg = c * double(r1.x);
+        double* t = reinterpret_cast<double*>(L.acc) + 8 * __float_as_uint(r1.y);
+        atomicAdd(&t[0], c);
+        atomicAdd(&t[1], c * c);
+        atomicAdd(&t[2], css);
+        atomicAdd(&t[3], css * css);
+        atomicAdd(&t[4], csa);
+        atomicAdd(&t[5], csa * csa);
+        atomicAdd(&t[6], csg);
+        atomicAdd(&t[7], csg * csg);
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Path of an earlier visit (still in flight after the wave moved to another
+// unit): tally straight into that visit's slot, which only this wave writes
+// and which it has already flushed.
+__device__ __forceinline__ void exit_global_forward(const WalkArgs& a, const WaveLds& L,
+                                                    uint32_t slot, int ev, const Path& p,
+                                                    uint32_t nv) {
+  const ColdConst cc = read_cold(L);
+  const float sc = cc.fix_scale, cap = cc.fix_cap;
+  const int nb2 = 2 * (cc.n_bins + 2);
+  if (ev == EV_EXIT_TOP) {
+    const int b = radial_slot(p.x, p.y, cc);
+    u64* B = reinterpret_cast<u64*>(a.tb + int64_t(slot) * nb2);
+    atomicAdd(&B[2 * b], fix32(p.W, sc, cap));
+    atomicAdd(&B[2 * b + 1], fix32(p.W * p.W, sc, cap));
+  } else if (ev == EV_EXIT_BOTTOM) {
+    atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 2]), fix32(p.W, sc, cap));
+  }
+  atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 3]), fix32(p.A, sc, cap));
+  atomicAdd(reinterpret_cast<u64*>(&a.tv[slot]), u64(nv));
+}
+
+// Adjoint scores of an ending path: c = x * (cot_R + cot_bins[slot]) with the
+// per-path sigma_t, albedo and g scores of its medium.
+__device__ __forceinline__ float score_alpha(const Path& p) {
+  return p.ncoll ? float(p.ncoll) * __builtin_amdgcn_rcpf(p.m.alb) : 0.0f;
+}
+__device__ __forceinline__ float score_g(const Path& p) { return fmaf(float(p.ncoll), p.m.gc, p.Sg); }
+
+template <int K>
+__device__ __forceinline__ void exit_global_adjoint(const WalkArgs& a, const WaveLds& L,
+                                                    uint32_t slot, uint32_t unit, int ev,
+                                                    const Path& p, uint32_t nv) {
+  if (ev == EV_EXIT_TOP) {
+    const ColdConst cc = read_cold(L);
+    const int slot = radial_slot(p.x, p.y, cc);
+    float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
+    if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + slot];
+    const double c = double(p.W) * double(cot);
+    if (c != 0.0) {
+      const double css = c * double(p.D), csa = c * double(score_alpha(p)),
+                   csg = c * double(score_g(p));
+      double* t = a.adj + (int64_t(slot) * K + p.k) * 8;
+      unsafeAtomicAdd(&t[0], c);
+      unsafeAtomicAdd(&t[1], c * c);
+      unsafeAtomicAdd(&t[2], css);
+      unsafeAtomicAdd(&t[3], css * css);
+      unsafeAtomicAdd(&t[4], csa);
+      unsafeAtomicAdd(&t[5], csa * csa);
+      unsafeAtomicAdd(&t[6], csg);
+      unsafeAtomicAdd(&t[7], csg * csg);
+    }
+  }
+  atomicAdd(reinterpret_cast<u64*>(&a.adj_vertices[slot]), u64(nv));
+}
+
+// Tally what is left in the ring, then store the wave's sums of the visit
+// (unit u) into its slot and clear them.  The slot belongs to this wave alone,
+// so plain stores do; paths of the visit still in flight add to it afterwards.
+template <int K, bool ADJ>
+__device__ __forceinline__ void flush_unit(const WalkArgs& a, const WaveLds& L, uint32_t& head,
+                                           uint32_t tail, int64_t slot, int64_t u, int lane) {
+  while (head != tail) {
+    const uint32_t n = (tail - head) < uint32_t(kWave) ? (tail - head) : uint32_t(kWave);
+    if (!ADJ) tally_forward(L, head, n, lane);
+    else tally_adjoint<K>(a, L, uint32_t(u), head, n, lane);
+    head += n;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (!ADJ) {
-    sx = wave_sum(sx);
-    sx2 = wave_sum(sx2);
-    sT = wave_sum(sT);
-    sA = wave_sum(sA);
-    if (a.direct || a.atomic) {
-      double* R = a.R + u * 4;
-      double* B = a.bins + u * int64_t(nd);
-      if (a.direct) {
-        if (lane == 0) {
-          R[0] = sx; R[1] = sx2; R[2] = sT; R[3] = sA;
-          a.vertices[u] = int64_t(nvt);
-        }
-        for (int i = lane; i < nd; i += kWave) {
-          B[i] = wl[i];
-          wl[i] = 0.0;
-        }
-      } else {
-        if (lane == 0) {
-          unsafeAtomicAdd(&R[0], sx); unsafeAtomicAdd(&R[1], sx2);
-          unsafeAtomicAdd(&R[2], sT); unsafeAtomicAdd(&R[3], sA);
-          atomicAdd(reinterpret_cast<unsigned long long*>(&a.vertices[u]),
-                    static_cast<unsigned long long>(nvt));
-        }
-        for (int i = lane; i < nd; i += kWave) {
-          const double t = wl[i];
-          if (t != 0.0) unsafeAtomicAdd(&B[i], t);
-          wl[i] = 0.0;
-        }
-      }
-    } else {
-      double* P = a.partial + item * int64_t(a.part_len);
-      if (lane == 0) {
-        P[0] = sx; P[1] = sx2; P[2] = sT; P[3] = sA; P[4] = double(nvt);
-      }
-      for (int i = lane; i < nd; i += kWave) {
-        P[5 + i] = wl[i];
-        wl[i] = 0.0;
-      }
+    const int nb2 = 2 * (a.geo.n_bins + 2);
+    u64* B = reinterpret_cast<u64*>(a.tb + slot * nb2);
+    for (int i = lane; i < nb2; i += kWave) {
+      B[i] = L.acc[i];
+      L.acc[i] = 0ull;
+    }
+    if (lane == 0) {
+      a.tc[slot * 4 + 2] = int64_t(L.ctr[0]);
+      a.tc[slot * 4 + 3] = int64_t(L.ctr[1]);
+      a.tv[slot] = int64_t(L.ctr[2]);
+      L.ctr[0] = 0ull;
+      L.ctr[1] = 0ull;
+      L.ctr[2] = 0ull;
     }
   } else {
-    double* P = a.partial + item * int64_t(a.part_len);
-    for (int i = lane; i < nd; i += kWave) {
-      P[i] = wl[i];
-      wl[i] = 0.0;
+    double* accd = reinterpret_cast<double*>(L.acc);
+    double* G = a.adj + slot * (8 * K);
+    for (int m = lane; m < 8 * K; m += kWave) {
+      G[m] = accd[m];
+      accd[m] = 0.0;
     }
-    if (lane == 0) P[nd] = double(nvt);
+    if (lane == 0) {
+      a.adj_vertices[slot] = int64_t(L.ctr[0]);
+      L.ctr[0] = 0ull;
+    }
   }
+  // the stores land before any later add to the same slot
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 template <int K, bool ADJ>
 __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
-  extern __shared__ double lds[];
+  extern __shared__ u64 lds[];
   const int lane = lane_id();
-  const int wid = threadIdx.x / kWave;
-  const int waves_per_wg = blockDim.x / kWave;
-  double* wl = lds + int64_t(wid) * a.lds_doubles_per_wave;
-  for (int i = lane; i < a.lds_doubles_per_wave; i += kWave) wl[i] = 0.0;
+  // the wave index is uniform; say so, or every schedule value derived from it
+  // is treated as divergent
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wpw = blockDim.x / kWave;
+  WaveLds L;
+  L.acc = lds + int64_t(wid) * a.lds_words_per_wave;
+  L.ctr = L.acc + (ADJ ? 8 * K : 2 * (a.geo.n_bins + 2));
+  L.media = reinterpret_cast<float*>(L.acc + a.acc_words);
+  L.cold = reinterpret_cast<ColdConst*>(L.acc + a.acc_words + kMediaTableWords);
+  L.ring = reinterpret_cast<float4*>(L.acc + a.acc_words + kMediaTableWords + kColdConstWords);
+  for (int i = lane; i < a.acc_words; i += kWave) L.acc[i] = 0ull;
+  if (lane == 0) {
+    float4* q = reinterpret_cast<float4*>(L.cold);
+    q[0] = make_float4(a.geo.r_min, a.geo.r_max, a.geo.log2_rmin, a.geo.bin_scale);
+    q[1] = make_float4(__int_as_float(a.geo.n_bins), a.geo.entry_weight, a.fix_scale32, a.fix_cap);
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-  int64_t next = int64_t(blockIdx.x) * waves_per_wg + wid;
-  const int64_t stride = int64_t(gridDim.x) * waves_per_wg;
+  const WalkGeom geo = step_geom_in_vgprs(a.geo);
+
+  // wave-uniform schedule state: the current item's next path index and end,
+  // the unit whose parameters are staged and whose sums sit in LDS, the slot
+  // of this visit, the ring
+  int64_t u_cur = -1, cur_slot = -1;
+  uint32_t cursor = 0, pend = 0, head = 0, tail = 0, iter = 0;
+  int64_t static_item = int64_t(blockIdx.x) * wpw + wid;
+  bool done = false, unit_ok = false, boosted = false;
+  // lane state
+  Path p;
+  bool alive = false, capped = false;
+  uint32_t path = 0, v = 0, lunit = 0, lslot = 0;
+
   for (;;) {
-    int64_t item;
-    if (a.map.queue) {
-      uint32_t it = 0;
-      if (lane == 0) it = atomicAdd(a.map.queue, 1u);
-      item = int64_t(__builtin_amdgcn_readfirstlane(it));
-    } else {
-      item = next;
-      next += stride;
+    // Idle lanes take the next path indices of the current item.  When the
+    // item is used up, the wave moves to the next item of a valid unit (paths
+    // of the previous unit still in flight finish with that unit's medium and
+    // tally to global memory); lanes left idle by the end of an item wait for
+    // the next iteration.
+    const uint64_t idle = __ballot(!alive);
+    if (idle != 0) {
+      if (cursor >= pend && !done) {
+        for (;;) {
+          const int64_t item = next_item(a, static_item, lane);
+          if (item < 0) {
+            done = true;
+            break;
+          }
+          int64_t ul, pb, pe;
+          map_item(a.map, item, ul, pb, pe);
+          if (pb >= pe) continue;
+          const int64_t u = a.map.unit_begin + ul;
+          if (u != u_cur) {
+            if (u_cur >= 0) flush_unit<K, ADJ>(a, L, head, tail, cur_slot, u_cur, lane);
+            const UnitParams<K> up = load_unit<K>(a, u);
+            u_cur = u;
+            cur_slot = (!ADJ && a.direct) ? u : item;
+            unit_ok = up.ok;
+            if (unit_ok) stage_unit<K>(up, L.media, lane);
+            else if (lane == 0) atomicOr(a.flags, RW_FLAG_BAD_PARAMS);
+          }
+          if (!unit_ok) continue;  // an invalid unit keeps zero tallies
+          cursor = uint32_t(pb);
+          pend = uint32_t(pe);
+          break;
+        }
+        cursor = __builtin_amdgcn_readfirstlane(cursor);
+        pend = __builtin_amdgcn_readfirstlane(pend);
+      }
+      if (!alive) {
+        const uint32_t cand = cursor + lane_rank(idle);
+        if (cand < pend) {
+          path = cand;
+          v = 0;
+          alive = true;
+          lunit = uint32_t(u_cur);
+          lslot = uint32_t(cur_slot);
+        }
+      }
+      const uint32_t next = cursor + uint32_t(__popcll(idle));
+      cursor = next < pend ? next : pend;
     }
-    if (item >= a.map.n_items) break;
-    if (a.map.order) item = a.map.order[item];
-    int64_t ul, pb, pe;
-    map_item(a.map, item, ul, pb, pe);
-    walk_item<K, ADJ>(a, ks, a.map.unit_begin + ul, pb, pe, item, wl, lane);
+    // no lane alive: the last item has been handed out and every path ended
+    if (__ballot(alive) == 0) break;
+
+    // A wave carrying a long path is on the critical path of the launch:
+    // raise its issue priority while it does (checked every 16 iterations).
+    if ((++iter & 15u) == 0) {
+      const bool want = __ballot(alive && v > kLongPath) != 0;
+      if (want != boosted) {
+        if (want) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(0);
+        boosted = want;
+      }
+    }
+
+    int ev = EV_COLLIDE;
+    if (alive) {
+      const uint4 w = philox(v, path, a.tag, lunit, ks);
+      if (v == 0) {
+        start_path_lds<K>(p, w, L.media, L.cold->entry_weight);
+        v = 1;
+      } else {
+        ev = vertex_step<ADJ>(p, w, geo);
+        if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+          ev = EV_CAP;
+          capped = true;
+        }
+        if (ev >= EV_EXIT_TOP) alive = false;
+        else ++v;
+      }
+    }
+    const bool ending = ev >= EV_EXIT_TOP;
+    if (__ballot(ending) != 0) {
+      const bool local = lslot == uint32_t(cur_slot);
+      const uint64_t lm = __ballot(ending && local);
+      const uint32_t n_new = uint32_t(__popcll(lm));
+      if (tail - head + n_new > uint32_t(kExitRing)) {
+        // make room: tally what is waiting (at most one wave's worth)
+        const uint32_t n = (tail - head) < uint32_t(kWave) ? (tail - head) : uint32_t(kWave);
+        if (!ADJ) tally_forward(L, head, n, lane);
+        else tally_adjoint<K>(a, L, uint32_t(u_cur), head, n, lane);
+        head += n;
+      }
+      if (ending) {
+        if (local) {
+          const uint32_t i = (tail + lane_rank(lm)) & (kExitRing - 1);
+          const float where = exit_where(ev, p);
+          if (!ADJ) {
+            L.ring[i] = make_float4(p.W, p.A, where, __uint_as_float(v));
+          } else {
+            const bool top = ev == EV_EXIT_TOP;
+            L.ring[2 * i] = make_float4(top ? p.W : 0.0f, where, p.D, score_alpha(p));
+            L.ring[2 * i + 1] = make_float4(score_g(p), __uint_as_float(uint32_t(p.k)),
+                                            __uint_as_float(v), 0.0f);
+          }
+        } else {
+          if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
+          else exit_global_adjoint<K>(a, L, lslot, lunit, ev, p, v);
+        }
+      }
+      tail += n_new;
+    }
+  }
+  if (boosted) __builtin_amdgcn_s_setprio(0);
+  if (u_cur >= 0) flush_unit<K, ADJ>(a, L, head, tail, cur_slot, u_cur, lane);
+  if (__any(capped) && lane == 0) atomicOr(a.flags, RW_FLAG_VERTEX_CAP);
+}
+
+// Forward: per unit, the sums of its slots (exact int64) -> FP64 outputs; the
+// top totals are the sums over all radial slots (every top exit lands in one).
+// One block per unit.  Direct: the unit's single slot is its output, converted
+// in place (each word is read before it is overwritten by the same thread).
+__global__ void __launch_bounds__(kConvertThreads) convert_forward_kernel(const WalkArgs a) {
+  __shared__ long long red[2][kConvertThreads / kWave];
+  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
+  __syncthreads();  // red[] of the previous unit has been read
+  const int64_t u = a.map.unit_begin + ul;
+  const int tid = threadIdx.x;
+  const int nb2 = 2 * (a.geo.n_bins + 2);
+  const double inv = 1.0 / double(a.fix_scale32);
+  const int64_t s0 = a.direct ? u : ul * a.map.chunks_per_unit;
+  const int64_t ns = a.direct ? 1 : a.map.chunks_per_unit;
+  double* B = a.out_bins + u * nb2;
+  long long s1 = 0, s2 = 0;
+  for (int i = tid; i < nb2; i += kConvertThreads) {
+    long long v = 0;
+    for (int64_t c = 0; c < ns; ++c) v += a.tb[(s0 + c) * nb2 + i];
+    if (i & 1) s2 += v; else s1 += v;
+    B[i] = double(v) * inv;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_xor(s1, off, kWave);
+    s2 += __shfl_xor(s2, off, kWave);
+  }
+  if ((tid & (kWave - 1)) == 0) {
+    red[0][tid / kWave] = s1;
+    red[1][tid / kWave] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    long long t1 = 0, t2 = 0, tt = 0, ta = 0, tv = 0;
+    for (int w = 0; w < kConvertThreads / kWave; ++w) {
+      t1 += red[0][w];
+      t2 += red[1][w];
+    }
+    for (int64_t c = 0; c < ns; ++c) {
+      tt += a.tc[(s0 + c) * 4 + 2];
+      ta += a.tc[(s0 + c) * 4 + 3];
+      tv += a.tv[s0 + c];
+    }
+    double* R = a.out_R + u * 4;
+    R[0] = double(t1) * inv;
+    R[1] = double(t2) * inv;
+    R[2] = double(tt) * inv;
+    R[3] = double(ta) * inv;
+    a.out_vertices[u] = tv;
+  }
   }
 }
 
-// Sum the item slots of each unit in item order.  One block per unit; the
-// threads split the slot entries.
-__global__ void __launch_bounds__(256) reduce_forward_kernel(const WalkArgs a) {
-  const int64_t ul = blockIdx.x;
-  const WorkMap& m = a.map;
-  const int64_t i0 = ul * m.chunks_per_unit;
-  const int64_t i1 = i0 + unit_items(m, ul);
-  const int64_t u = m.unit_begin + ul;
-  const int len = a.part_len;
-  const int nb2 = (a.geo.n_bins + 2) * 2;
-  for (int e = threadIdx.x; e < len; e += blockDim.x) {
-    double s = 0.0;
-    for (int64_t it = i0; it < i1; ++it) s += a.partial[it * len + e];
-    if (e < 4) {
-      a.R[u * 4 + e] = s;
-    } else if (e == 4) {
-      a.vertices[u] = int64_t(s);
-    } else if (e - 5 < nb2) {
-      a.bins[u * nb2 + (e - 5)] = s;
-    }
-  }
-}
-
-// Adjoint: per unit, sum the [K][8] slots of its items, then map the per-medium
-// sums to gradients:  sigma_t_k, alpha_k, g_k directly;  logit_j = C_j - w_j C
-// with sumsq (1 - w_j)^2 Q_j + w_j^2 (Q - Q_j).  One thread per unit.
+// Adjoint: per unit, the sums of its slots (in slot order), then the [K][8]
+// sums (C, Q, Ss, Ss2, Sa, Sa2, Sg, Sg2) to gradients: sigma_t_k, alpha_k, g_k
+// directly; logit_j = C_j - w_j C with sum of squares (1 - w_j)^2 Q_j +
+// w_j^2 (Q - Q_j).  One wave per unit.
 template <int K>
-__global__ void __launch_bounds__(256) reduce_adjoint_kernel(const WalkArgs a, double* grad,
-                                                             double* grad_sumsq) {
-  const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const WorkMap& m = a.map;
-  if (ul >= m.n_units) return;
-  const int64_t i0 = ul * m.chunks_per_unit;
-  const int64_t i1 = i0 + unit_items(m, ul);
-  const int64_t u = m.unit_begin + ul;
-  double acc[K * 8 + 1];
-#pragma unroll
-  for (int e = 0; e < K * 8 + 1; ++e) acc[e] = 0.0;
-  for (int64_t it = i0; it < i1; ++it) {
-    const double* P = a.partial + it * a.part_len;
-#pragma unroll
-    for (int e = 0; e < K * 8 + 1; ++e) acc[e] += P[e];
+__global__ void __launch_bounds__(kWave) convert_adjoint_kernel(const WalkArgs a, double* grad,
+                                                                double* grad_sumsq,
+                                                                int64_t* vertices_out) {
+  __shared__ double sums[8 * K];
+  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
+  __syncthreads();  // sums[] of the previous unit has been read
+  const int64_t u = a.map.unit_begin + ul;
+  const int tid = threadIdx.x;
+  const int64_t s0 = ul * a.map.chunks_per_unit;
+  const int64_t ns = a.map.chunks_per_unit;
+  if (tid < 8 * K) {
+    double v = 0.0;
+    for (int64_t c = 0; c < ns; ++c) v += a.adj[(s0 + c) * (8 * K) + tid];
+    sums[tid] = v;
+  } else if (tid == 8 * K && vertices_out) {
+    long long nv = 0;
+    for (int64_t c = 0; c < ns; ++c) nv += a.adj_vertices[s0 + c];
+    vertices_out[u] = nv;
   }
+  __syncthreads();
+  if (tid != 0) continue;
+  const double* s = sums;
   const UnitParams<K> up = load_unit<K>(a, u);
   double C = 0.0, Q = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    C += acc[8 * k + 0];
-    Q += acc[8 * k + 1];
+    C += s[8 * k + 0];
+    Q += s[8 * k + 1];
   }
   double* G = grad + u * (4 * K);
   double* S = grad_sumsq ? grad_sumsq + u * (4 * K) : nullptr;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double w = double(up.w[k]);
-    G[k] = acc[8 * k + 2];
-    G[K + k] = acc[8 * k + 4];
-    G[2 * K + k] = acc[8 * k + 6];
-    G[3 * K + k] = acc[8 * k + 0] - w * C;
+    G[k] = s[8 * k + 2];
+    G[K + k] = s[8 * k + 4];
+    G[2 * K + k] = s[8 * k + 6];
+    G[3 * K + k] = s[8 * k + 0] - w * C;
     if (S) {
-      S[k] = acc[8 * k + 3];
-      S[K + k] = acc[8 * k + 5];
-      S[2 * K + k] = acc[8 * k + 7];
-      S[3 * K + k] = (1.0 - w) * (1.0 - w) * acc[8 * k + 1] + w * w * (Q - acc[8 * k + 1]);
+      S[k] = s[8 * k + 3];
+      S[K + k] = s[8 * k + 5];
+      S[2 * K + k] = s[8 * k + 7];
+      S[3 * K + k] = (1.0 - w) * (1.0 - w) * s[8 * k + 1] + w * w * (Q - s[8 * k + 1]);
     }
   }
-  if (a.vertices) a.vertices[u] = int64_t(acc[K * 8]);
+  }
 }
 
-__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = v;
+// Longest-first order of the units (persistent schedule).  The estimate of
+// the mean vertices per path of a medium only orders work and never changes a
+// result: paths end at the surface or by roulette, which starts after
+// n_rr = ln(rr_weight / W0) / ln(alpha) collisions; before that the walk
+// leaves like a diffusing particle, about c sqrt(n / (1 - g)) collisions for a
+// horizon of n (c ~ 5 fitted on walks of this kind).
+__device__ __forceinline__ float est_path_vertices(float alb, float g, const WalkGeom& geo) {
+  const float cap = float(geo.max_vertices);
+  float n_rr;
+  if (!(geo.rr_weight > 0.0f) || alb >= 1.0f) {
+    n_rr = cap;
+  } else if (alb <= 0.0f) {
+    n_rr = 1.0f;
+  } else {
+    n_rr = fminf(__logf(geo.rr_weight / geo.entry_weight) / __logf(alb), cap);
+  }
+  return 2.0f + fminf(n_rr, 5.0f * sqrtf(n_rr / fmaxf(1.0f - g, 1e-3f)));
 }
 
-__global__ void fill_i64_kernel(int64_t* p, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = 0;
+template <int K>
+__global__ void __launch_bounds__(256) unit_cost_kernel(const WalkArgs a, int32_t* bucket,
+                                                        uint32_t* hist) {
+  const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (ul >= a.map.n_units) return;
+  const UnitParams<K> up = load_unit<K>(a, a.map.unit_begin + ul);
+  float c = 1.0f;
+  if (up.ok) {
+    c = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) c += up.w[k] * est_path_vertices(up.alb[k], up.g[k], a.geo);
+  }
+  int b = int(4.0f * __log2f(c + 1.0f));
+  b = b < 0 ? 0 : (b > kOrderBuckets - 1 ? kOrderBuckets - 1 : b);
+  b = kOrderBuckets - 1 - b;  // descending cost
+  bucket[ul] = b;
+  atomicAdd(&hist[b], 1u);
+}
+
+// exclusive prefix of the bucket counts, in place (one wave)
+__global__ void order_scan_kernel(uint32_t* hist) {
+  if (threadIdx.x != 0) return;
+  uint32_t acc = 0;
+  for (int b = 0; b < kOrderBuckets; ++b) {
+    const uint32_t c = hist[b];
+    hist[b] = acc;
+    acc += c;
+  }
+}
+
+// scatter local unit indices to their bucket ranges (order within a bucket is
+// arbitrary; it only affects timing)
+__global__ void __launch_bounds__(256) order_scatter_kernel(int64_t n_units, const int32_t* bucket,
+                                                            uint32_t* cursor, int32_t* unit_order) {
+  const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (ul >= n_units) return;
+  const uint32_t pos = atomicAdd(&cursor[bucket[ul]], 1u);
+  unit_order[pos] = int32_t(ul);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = v;
+}
+
+__global__ void fill_u64_kernel(uint64_t* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0ull;
 }
 
 // eq. radsss: mean, SE, per-area radial density and normalised profile
@@ -386,7 +661,7 @@ __global__ void trace_kernel(const WalkArgs a, const uint32_t* words, int64_t n_
       const uint32_t* q = words + (pth * n_blocks + v) * 4;
       w = make_uint4(q[0], q[1], q[2], q[3]);
     } else {
-      w = philox(uint32_t(v), uint32_t(pth), unit_index, a.tag, ks);
+      w = philox(uint32_t(v), uint32_t(pth), a.tag, unit_index, ks);
     }
     int code;
     if (v == 0) {
@@ -435,41 +710,19 @@ __global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+int walk_lds_bytes(const WalkArgs& a, int waves_per_wg) {
+  return waves_per_wg * a.lds_words_per_wave * int(sizeof(u64));
+}
+
 template <int K>
 static hipError_t launch_walk_k(const WalkArgs& a, bool adjoint, int waves_per_wg, int grid,
                                 hipStream_t s) {
-  const size_t lds = size_t(waves_per_wg) * a.lds_doubles_per_wave * sizeof(double);
+  const size_t lds = size_t(walk_lds_bytes(a, waves_per_wg));
   if (adjoint)
     hipLaunchKernelGGL((walk_kernel<K, true>), dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   else
     hipLaunchKernelGGL((walk_kernel<K, false>), dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   return hipGetLastError();
-}
-
-int walk_lds_bytes(const WalkArgs& a, int waves_per_wg) {
-  return waves_per_wg * a.lds_doubles_per_wave * int(sizeof(double));
-}
-
-const void* walk_kernel_ptr(int K, bool adjoint) {
-  switch (K) {
-    case 1: return adjoint ? (const void*)walk_kernel<1, true> : (const void*)walk_kernel<1, false>;
-    case 2: return adjoint ? (const void*)walk_kernel<2, true> : (const void*)walk_kernel<2, false>;
-    case 3: return adjoint ? (const void*)walk_kernel<3, true> : (const void*)walk_kernel<3, false>;
-    case 4: return adjoint ? (const void*)walk_kernel<4, true> : (const void*)walk_kernel<4, false>;
-    default: return nullptr;
-  }
-}
-
-const void* fill_u32_kernel_ptr() { return (const void*)fill_u32_kernel; }
-const void* reduce_forward_kernel_ptr() { return (const void*)reduce_forward_kernel; }
-const void* reduce_adjoint_kernel_ptr(int K) {
-  switch (K) {
-    case 1: return (const void*)reduce_adjoint_kernel<1>;
-    case 2: return (const void*)reduce_adjoint_kernel<2>;
-    case 3: return (const void*)reduce_adjoint_kernel<3>;
-    case 4: return (const void*)reduce_adjoint_kernel<4>;
-    default: return nullptr;
-  }
 }
 
 hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg, int grid_wgs,
@@ -483,22 +736,61 @@ hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg,
   }
 }
 
+const void* walk_kernel_ptr(int K, bool adjoint) {
+  switch (K) {
+    case 1: return adjoint ? (const void*)walk_kernel<1, true> : (const void*)walk_kernel<1, false>;
+    case 2: return adjoint ? (const void*)walk_kernel<2, true> : (const void*)walk_kernel<2, false>;
+    case 3: return adjoint ? (const void*)walk_kernel<3, true> : (const void*)walk_kernel<3, false>;
+    case 4: return adjoint ? (const void*)walk_kernel<4, true> : (const void*)walk_kernel<4, false>;
+    default: return nullptr;
+  }
+}
+
+const void* fill_u32_kernel_ptr() { return (const void*)fill_u32_kernel; }
+const void* fill_u64_kernel_ptr() { return (const void*)fill_u64_kernel; }
+const void* unit_cost_kernel_ptr(int K) {
+  switch (K) {
+    case 1: return (const void*)unit_cost_kernel<1>;
+    case 2: return (const void*)unit_cost_kernel<2>;
+    case 3: return (const void*)unit_cost_kernel<3>;
+    case 4: return (const void*)unit_cost_kernel<4>;
+    default: return nullptr;
+  }
+}
+const void* order_scan_kernel_ptr() { return (const void*)order_scan_kernel; }
+const void* order_scatter_kernel_ptr() { return (const void*)order_scatter_kernel; }
+const void* convert_forward_kernel_ptr() { return (const void*)convert_forward_kernel; }
+const void* convert_adjoint_kernel_ptr(int K) {
+  switch (K) {
+    case 1: return (const void*)convert_adjoint_kernel<1>;
+    case 2: return (const void*)convert_adjoint_kernel<2>;
+    case 3: return (const void*)convert_adjoint_kernel<3>;
+    case 4: return (const void*)convert_adjoint_kernel<4>;
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_unit_order(const WalkArgs& a, int K, int32_t* bucket, uint32_t* hist,
+                             int32_t* unit_order, hipStream_t s) {
+  const int64_t n = a.map.n_units;
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = unsigned((n + 255) / 256);
+  switch (K) {
+    case 1: hipLaunchKernelGGL(unit_cost_kernel<1>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
+    case 2: hipLaunchKernelGGL(unit_cost_kernel<2>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
+    case 3: hipLaunchKernelGGL(unit_cost_kernel<3>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
+    case 4: hipLaunchKernelGGL(unit_cost_kernel<4>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, n, bucket, hist, unit_order);
+  return hipGetLastError();
+}
+
 static int fill_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
   return int(g < 1 ? 1 : g);
-}
-
-hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_f64_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_i64(int64_t* p, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_i64_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
@@ -507,21 +799,28 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_forward(const WalkArgs& a, hipStream_t s) {
-  if (a.map.n_units <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_forward_kernel, dim3(unsigned(a.map.n_units)), dim3(256), 0, s, a);
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_adjoint(const WalkArgs& a, int K, double* grad, double* grad_sumsq,
-                                 hipStream_t s) {
+hipError_t launch_convert_forward(const WalkArgs& a, hipStream_t s) {
   if (a.map.n_units <= 0) return hipSuccess;
-  const unsigned grid = unsigned((a.map.n_units + 255) / 256);
+  hipLaunchKernelGGL(convert_forward_kernel, dim3(convert_blocks(a.map.n_units)),
+                     dim3(kConvertThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_adjoint(const WalkArgs& a, int K, double* grad, double* grad_sumsq,
+                                  int64_t* vertices_out, hipStream_t s) {
+  if (a.map.n_units <= 0) return hipSuccess;
+  const unsigned grid = convert_blocks(a.map.n_units);
   switch (K) {
-    case 1: hipLaunchKernelGGL(reduce_adjoint_kernel<1>, dim3(grid), dim3(256), 0, s, a, grad, grad_sumsq); break;
-    case 2: hipLaunchKernelGGL(reduce_adjoint_kernel<2>, dim3(grid), dim3(256), 0, s, a, grad, grad_sumsq); break;
-    case 3: hipLaunchKernelGGL(reduce_adjoint_kernel<3>, dim3(grid), dim3(256), 0, s, a, grad, grad_sumsq); break;
-    case 4: hipLaunchKernelGGL(reduce_adjoint_kernel<4>, dim3(grid), dim3(256), 0, s, a, grad, grad_sumsq); break;
+    case 1: hipLaunchKernelGGL(convert_adjoint_kernel<1>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 2: hipLaunchKernelGGL(convert_adjoint_kernel<2>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 3: hipLaunchKernelGGL(convert_adjoint_kernel<3>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 4: hipLaunchKernelGGL(convert_adjoint_kernel<4>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

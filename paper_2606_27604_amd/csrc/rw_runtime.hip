@@ -1,8 +1,8 @@
 // Host runtime of the C ABI declared in include/rw.h.
 //
 // Responsibilities: argument validation (before anything is enqueued), the
-// context's device workspace (per-item partial sums, the persistent queue
-// counter), launch shapes (plain static grid, or a persistent grid sized from
+// context's device workspace (adjoint sums, the persistent queue counter and
+// the longest-first schedule), launch shapes (plain static grid, or a persistent grid sized from
 // the device's compute-unit count and the kernel's occupancy), the autotuner
 // that picks the chunk size and workgroup shape by timing candidates with HIP
 // events, and hipGraph replay of the batched launch sequence.
@@ -46,9 +46,12 @@ struct rw_context {
   int device = -1;          // -1: validation-only context (no device)
   int n_cu = 0;
   std::string last_error;
-  double* partial = nullptr;
-  size_t partial_bytes = 0;
+  void* workspace = nullptr;      // adjoint sums (128-bit) and vertex counts
+  size_t workspace_bytes = 0;
   uint32_t* queue = nullptr;
+  // longest-first schedule: [hist (kOrderBuckets u32) | bucket (n i32) | order (n i32)]
+  char* sched = nullptr;
+  size_t sched_bytes = 0;
   std::map<std::string, TuneCfg> tune;
   std::map<std::string, GraphEntry> graphs;
   bool tune_cache_loaded = false;
@@ -145,24 +148,58 @@ rw_status need_device(rw_context* ctx) {
   return RW_OK;
 }
 
-rw_status ensure_partial(rw_context* ctx, size_t bytes) {
-  if (bytes <= ctx->partial_bytes) return RW_OK;
+rw_status ensure_workspace(rw_context* ctx, size_t bytes) {
+  if (bytes <= ctx->workspace_bytes) return RW_OK;
   if (fault_injected("alloc")) return fail(ctx, RW_E_NOMEM, "injected allocation failure");
-  if (ctx->partial) {
+  if (ctx->workspace) {
     // the old buffer may still be read by queued work
     RW_HIP(ctx, hipDeviceSynchronize());
-    RW_HIP(ctx, hipFree(ctx->partial));
-    ctx->partial = nullptr;
-    ctx->partial_bytes = 0;
+    RW_HIP(ctx, hipFree(ctx->workspace));
+    ctx->workspace = nullptr;
+    ctx->workspace_bytes = 0;
   }
   size_t want = std::max(bytes, size_t(1) << 20);
-  if (hipMalloc(&ctx->partial, want) != hipSuccess) {
-    ctx->partial = nullptr;
+  if (hipMalloc(&ctx->workspace, want) != hipSuccess) {
+    ctx->workspace = nullptr;
     (void)hipGetLastError();
     return fail(ctx, RW_E_NOMEM, "workspace allocation of %zu bytes failed", want);
   }
-  ctx->partial_bytes = want;
+  ctx->workspace_bytes = want;
   return RW_OK;
+}
+
+rw_status ensure_sched(rw_context* ctx, int64_t n_units) {
+  const size_t bytes = 256 + size_t(n_units) * 8;
+  if (bytes <= ctx->sched_bytes) return RW_OK;
+  if (fault_injected("alloc")) return fail(ctx, RW_E_NOMEM, "injected allocation failure");
+  if (ctx->sched) {
+    RW_HIP(ctx, hipDeviceSynchronize());
+    RW_HIP(ctx, hipFree(ctx->sched));
+    ctx->sched = nullptr;
+    ctx->sched_bytes = 0;
+  }
+  const size_t want = std::max(bytes, size_t(1) << 16);
+  if (hipMalloc(&ctx->sched, want) != hipSuccess) {
+    ctx->sched = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, RW_E_NOMEM, "schedule workspace allocation of %zu bytes failed", want);
+  }
+  ctx->sched_bytes = want;
+  return RW_OK;
+}
+
+struct SchedPtrs {
+  uint32_t* hist;
+  int32_t* bucket;
+  int32_t* order;
+};
+
+SchedPtrs sched_ptrs(rw_context* ctx, int64_t n_units) {
+  SchedPtrs p;
+  p.hist = reinterpret_cast<uint32_t*>(ctx->sched);
+  p.bucket = reinterpret_cast<int32_t*>(ctx->sched + 256);
+  p.order = p.bucket + n_units;
+  return p;
 }
 
 // Work description shared by the four walk entry points.
@@ -180,6 +217,7 @@ rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_g
                      int64_t n_units, const int32_t* paths, int64_t paths_uniform, uint64_t seed,
                      int64_t ub, int64_t ue, bool adjoint, const TuneCfg& cfg) {
   WalkArgs& a = P.a;
+  a = WalkArgs{};
   a.sigma_t = media->sigma_t;
   a.albedo = media->albedo;
   a.g = media->g;
@@ -206,10 +244,21 @@ rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_g
   m.chunk = chunk;
   m.chunks_per_unit = paths_uniform > 0 ? int((paths_uniform + chunk - 1) / chunk) : 0;
   m.n_items = m.n_units * int64_t(m.chunks_per_unit);
-  m.order = nullptr;
+  m.unit_order = nullptr;
   m.queue = nullptr;
-  a.lds_doubles_per_wave = adjoint ? 8 * P.K : (geom->n_bins + 2) * 2;
-  a.part_len = adjoint ? adjoint_part_len(P.K) : forward_part_len(geom->n_bins);
+  if (m.n_items >= (int64_t(1) << 32))
+    return fail(ctx, RW_E_UNSUPPORTED, "more than 2^32 work items (%lld) in one call",
+                (long long)m.n_items);
+  // fixed point of the forward sums: every per-path value (weight, squared
+  // weight, absorbed weight) is below x_max, so with s = 31 - ceil(log2 x_max)
+  // fraction bits it fits 32 bits, and N <= 2^31 paths keep a unit's 64-bit
+  // sum below 2^63
+  const double x_max = 2.0 * std::max(1.0, double(a.geo.rr_weight) * double(a.geo.rr_boost));
+  const int frac_bits = 31 - int(std::ceil(std::log2(x_max)));
+  a.fix_scale32 = float(std::ldexp(1.0, frac_bits));
+  a.fix_cap = float(x_max * (1.0 - 0x1p-20));
+  a.acc_words = adjoint ? adjoint_acc_words(P.K) : forward_acc_words(geom->n_bins);
+  a.lds_words_per_wave = walk_lds_words_per_wave(a.acc_words, adjoint);
   return RW_OK;
 }
 
@@ -225,6 +274,58 @@ int occupancy_wgs(const Plan& P, int waves_per_wg) {
   return blocks;
 }
 
+// Tally buffers of a plan.  Forward: slot sums in the workspace, [n_items]
+// x ((n_bins+2)*2 + 4 + 1) int64 (bins, T/A at 2/3, vertices), reduced into the
+// caller's tally; or, when every unit is one item, the caller's tally itself
+// (slot = unit).  Adjoint: [n_items] x (8K) FP64 + [n_items] int64 in the
+// workspace.  `clear` receives the regions to zero before the walk.
+struct Region {
+  uint64_t* p;
+  int64_t n;
+};
+
+rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, std::vector<Region>& clear) {
+  WalkArgs& a = P.a;
+  const int64_t ub = a.map.unit_begin;
+  const int64_t nb2 = 2 * (a.geo.n_bins + 2);
+  const int64_t ni = a.map.n_items;
+  clear.clear();
+  if (!P.adjoint) {
+    a.out_R = out->R;
+    a.out_bins = out->bins;
+    a.out_vertices = out->vertices;
+    a.direct = a.map.chunks_per_unit == 1 ? 1 : 0;
+    if (a.direct) {
+      a.tb = reinterpret_cast<int64_t*>(out->bins);
+      a.tc = reinterpret_cast<int64_t*>(out->R);
+      a.tv = out->vertices;
+      clear.push_back({reinterpret_cast<uint64_t*>(a.tb + ub * nb2), P.n_window * nb2});
+      clear.push_back({reinterpret_cast<uint64_t*>(a.tc + ub * 4), P.n_window * 4});
+      clear.push_back({reinterpret_cast<uint64_t*>(a.tv + ub), P.n_window});
+    } else {
+      rw_status st = ensure_workspace(ctx, size_t(ni) * size_t(nb2 + 5) * sizeof(int64_t));
+      if (st != RW_OK) return st;
+      a.tb = reinterpret_cast<int64_t*>(ctx->workspace);
+      a.tc = a.tb + ni * nb2;
+      a.tv = a.tc + ni * 4;
+      clear.push_back({reinterpret_cast<uint64_t*>(a.tb), ni * (nb2 + 5)});
+    }
+  } else {
+    rw_status st = ensure_workspace(ctx, size_t(ni) * size_t(8 * P.K + 1) * sizeof(double));
+    if (st != RW_OK) return st;
+    a.adj = reinterpret_cast<double*>(ctx->workspace);
+    a.adj_vertices = reinterpret_cast<int64_t*>(a.adj + ni * (8 * P.K));
+    clear.push_back({reinterpret_cast<uint64_t*>(a.adj), ni * (8 * P.K + 1)});
+  }
+  return RW_OK;
+}
+
+int64_t persistent_grid(rw_context* ctx, const Plan& P) {
+  const int wpw = P.cfg.waves_per_wg;
+  const int per_cu = P.cfg.wgs_per_cu > 0 ? P.cfg.wgs_per_cu : occupancy_wgs(P, wpw);
+  return std::min<int64_t>(int64_t(ctx->n_cu) * per_cu, (P.a.map.n_items + wpw - 1) / wpw);
+}
+
 // Enqueue the launch sequence of a plan (no graph).
 rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, double* grad,
                   double* grad_sumsq, int64_t* adj_vertices, int32_t* flags, hipStream_t s) {
@@ -233,47 +334,34 @@ rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, doub
   RW_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(flags), 1, 0u, s));
   a.flags = flags;
   if (P.n_window <= 0) return RW_OK;
-  const int64_t nd = (a.geo.n_bins + 2) * 2;
-  if (!P.adjoint) {
-    a.R = out->R;
-    a.bins = out->bins;
-    a.vertices = out->vertices;
-    const int64_t ub = a.map.unit_begin;
-    if (a.map.n_items == 0 || a.atomic) {
-      RW_HIP(ctx, launch_fill_f64(a.R + ub * 4, P.n_window * 4, 0.0, s));
-      RW_HIP(ctx, launch_fill_f64(a.bins + ub * nd, P.n_window * nd, 0.0, s));
-      RW_HIP(ctx, launch_fill_i64(a.vertices + ub, P.n_window, s));
-      if (a.map.n_items == 0) return RW_OK;
+  std::vector<Region> clear;
+  rw_status st0 = setup_tallies(ctx, P, out, clear);
+  if (st0 != RW_OK) return st0;
+  for (const Region& r : clear) RW_HIP(ctx, launch_fill_u64(r.p, r.n, s));
+  if (a.map.n_items > 0) {
+    const int wpw = P.cfg.waves_per_wg;
+    int64_t grid;
+    if (persistent) {
+      a.map.queue = ctx->queue;
+      RW_HIP(ctx, launch_fill_u32(ctx->queue, 1, 0u, s));
+      rw_status st = ensure_sched(ctx, a.map.n_units);
+      if (st != RW_OK) return st;
+      const SchedPtrs sp = sched_ptrs(ctx, a.map.n_units);
+      RW_HIP(ctx, launch_fill_u32(sp.hist, kOrderBuckets, 0u, s));
+      RW_HIP(ctx, launch_unit_order(a, P.K, sp.bucket, sp.hist, sp.order, s));
+      a.map.unit_order = sp.order;
+      grid = persistent_grid(ctx, P);
+    } else {
+      a.map.queue = nullptr;
+      grid = (a.map.n_items + wpw - 1) / wpw;
     }
-  } else {
-    a.vertices = adj_vertices;
-    if (a.map.n_items == 0) {
-      const int64_t ub = a.map.unit_begin;
-      RW_HIP(ctx, launch_fill_f64(grad + ub * 4 * P.K, P.n_window * 4 * P.K, 0.0, s));
-      if (grad_sumsq)
-        RW_HIP(ctx, launch_fill_f64(grad_sumsq + ub * 4 * P.K, P.n_window * 4 * P.K, 0.0, s));
-      if (adj_vertices) RW_HIP(ctx, launch_fill_i64(adj_vertices + ub, P.n_window, s));
-      return RW_OK;
-    }
+    if (grid > 0x7FFFFFFF) return fail(ctx, RW_E_UNSUPPORTED, "grid too large");
+    RW_HIP(ctx, launch_walk(a, P.K, P.adjoint, wpw, int(grid), s));
   }
-  const int wpw = P.cfg.waves_per_wg;
-  int64_t grid;
-  if (persistent) {
-    a.map.queue = ctx->queue;
-    RW_HIP(ctx, launch_fill_u32(ctx->queue, 1, 0u, s));
-    const int per_cu = P.cfg.wgs_per_cu > 0 ? P.cfg.wgs_per_cu : occupancy_wgs(P, wpw);
-    grid = int64_t(ctx->n_cu) * per_cu;
-    grid = std::min<int64_t>(grid, (a.map.n_items + wpw - 1) / wpw);
-  } else {
-    a.map.queue = nullptr;
-    grid = (a.map.n_items + wpw - 1) / wpw;
-  }
-  if (grid > 0x7FFFFFFF) return fail(ctx, RW_E_UNSUPPORTED, "grid too large");
-  RW_HIP(ctx, launch_walk(a, P.K, P.adjoint, wpw, int(grid), s));
   if (P.adjoint) {
-    RW_HIP(ctx, launch_reduce_adjoint(a, P.K, grad, grad_sumsq, s));
-  } else if (!a.direct && !a.atomic) {
-    RW_HIP(ctx, launch_reduce_forward(a, s));
+    RW_HIP(ctx, launch_convert_adjoint(a, P.K, grad, grad_sumsq, adj_vertices, s));
+  } else {
+    RW_HIP(ctx, launch_convert_forward(a, s));
   }
   return RW_OK;
 }
@@ -350,12 +438,6 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
       m.chunk = c;
       m.chunks_per_unit = int((paths + c - 1) / c);
       m.n_items = m.n_units * int64_t(m.chunks_per_unit);
-      P.a.direct = (!P.adjoint && m.chunks_per_unit == 1 && !P.a.atomic) ? 1 : 0;
-      if (!P.a.direct && !P.a.atomic) {
-        rw_status st = ensure_partial(ctx, size_t(m.n_items) * P.a.part_len * sizeof(double));
-        if (st != RW_OK) continue;
-        P.a.partial = ctx->partial;
-      }
       float ms_sum = 0.0f;
       bool ok = true;
       for (int rep = 0; rep < 3 && ok; ++rep) {
@@ -456,40 +538,59 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
                         int64_t* adj_vertices, int32_t* flags, hipStream_t s) {
   WalkArgs& a = P.a;
   a.flags = flags;
-  if (P.adjoint) {
-    a.vertices = adj_vertices;
-  } else {
-    a.R = out->R;
-    a.bins = out->bins;
-    a.vertices = out->vertices;
-  }
-  if (P.n_window <= 0 || a.map.n_items == 0 || a.atomic)
+  if (P.n_window <= 0 || a.map.n_items == 0)
     return enqueue(ctx, P, true, out, grad, grad_sumsq, adj_vertices, flags, s);
+  std::vector<Region> clear;
+  rw_status st0 = setup_tallies(ctx, P, out, clear);
+  if (st0 != RW_OK) return st0;
   const int wpw = P.cfg.waves_per_wg;
   a.map.queue = ctx->queue;
-  const int per_cu = P.cfg.wgs_per_cu > 0 ? P.cfg.wgs_per_cu : occupancy_wgs(P, wpw);
-  int64_t grid = std::min<int64_t>(int64_t(ctx->n_cu) * per_cu, (a.map.n_items + wpw - 1) / wpw);
+  rw_status st = ensure_sched(ctx, a.map.n_units);
+  if (st != RW_OK) return st;
+  const SchedPtrs sp = sched_ptrs(ctx, a.map.n_units);
+  a.map.unit_order = sp.order;
+  const int64_t grid = persistent_grid(ctx, P);
   std::vector<NodeSpec> specs;
   uint32_t* flags_u = reinterpret_cast<uint32_t*>(flags);
   const int64_t one = 1;
+  const int64_t nbuck = kOrderBuckets;
   const uint32_t zero = 0;
+  const unsigned ugrid = unsigned((a.map.n_units + 255) / 256);
+  auto fill64 = [&](void* p, int64_t n) {
+    uint64_t* q = reinterpret_cast<uint64_t*>(p);
+    int64_t g = (n + 255) / 256;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+    specs.push_back({fill_u64_kernel_ptr(), dim3(unsigned(g)), dim3(256), 0,
+                     {arg_bytes(q), arg_bytes(n)}});
+  };
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(flags_u), arg_bytes(one), arg_bytes(zero)}});
+  for (const Region& r : clear) fill64(r.p, r.n);
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(ctx->queue), arg_bytes(one), arg_bytes(zero)}});
+  specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
+                   {arg_bytes(sp.hist), arg_bytes(nbuck), arg_bytes(zero)}});
+  specs.push_back({unit_cost_kernel_ptr(P.K), dim3(ugrid), dim3(256), 0,
+                   {arg_bytes(a), arg_bytes(sp.bucket), arg_bytes(sp.hist)}});
+  specs.push_back({order_scan_kernel_ptr(), dim3(1), dim3(64), 0, {arg_bytes(sp.hist)}});
+  specs.push_back({order_scatter_kernel_ptr(), dim3(ugrid), dim3(256), 0,
+                   {arg_bytes(a.map.n_units), arg_bytes(sp.bucket), arg_bytes(sp.hist),
+                    arg_bytes(sp.order)}});
   specs.push_back({walk_kernel_ptr(P.K, P.adjoint), dim3(unsigned(grid)), dim3(wpw * kWave),
                    unsigned(walk_lds_bytes(a, wpw)), {arg_bytes(a)}});
   if (P.adjoint) {
-    specs.push_back({reduce_adjoint_kernel_ptr(P.K), dim3(unsigned((a.map.n_units + 255) / 256)),
-                     dim3(256), 0, {arg_bytes(a), arg_bytes(grad), arg_bytes(grad_sumsq)}});
-  } else if (!a.direct) {
-    specs.push_back({reduce_forward_kernel_ptr(), dim3(unsigned(a.map.n_units)), dim3(256), 0,
-                     {arg_bytes(a)}});
+    specs.push_back({convert_adjoint_kernel_ptr(P.K), dim3(convert_blocks(a.map.n_units)),
+                     dim3(kWave), 0,
+                     {arg_bytes(a), arg_bytes(grad), arg_bytes(grad_sumsq),
+                      arg_bytes(adj_vertices)}});
+  } else {
+    specs.push_back({convert_forward_kernel_ptr(), dim3(convert_blocks(a.map.n_units)),
+                     dim3(kConvertThreads), 0, {arg_bytes(a)}});
   }
   char key[200];
-  std::snprintf(key, sizeof(key), "K%d adj%d direct%d grid%lld wpw%d lds%d units%lld nodes%zu",
-                P.K, int(P.adjoint), a.direct, (long long)grid, wpw, walk_lds_bytes(a, wpw),
-                (long long)a.map.n_units, specs.size());
+  std::snprintf(key, sizeof(key), "K%d adj%d grid%lld wpw%d lds%d units%lld direct%d nodes%zu",
+                P.K, int(P.adjoint), (long long)grid, wpw, walk_lds_bytes(a, wpw),
+                (long long)a.map.n_units, int(a.direct), specs.size());
   return graph_launch(ctx, key, specs, s);
 }
 
@@ -521,11 +622,10 @@ rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* ge
     if (!flags) return fail(ctx, RW_E_INVALID, "flags is NULL");
   }
   int64_t ub = 0, ue = n_units;
-  bool use_graph = false, tune = false, deterministic = true;
+  bool use_graph = false, tune = false;
   if (opts) {
     use_graph = opts->use_graph != 0;
     tune = opts->autotune != 0;
-    deterministic = opts->deterministic_reduce != 0;
     if (opts->unit_end > 0 || opts->unit_begin != 0) {
       ub = opts->unit_begin;
       ue = opts->unit_end > 0 ? opts->unit_end : n_units;
@@ -534,8 +634,6 @@ rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* ge
                     (long long)ue, (long long)n_units);
     }
   }
-  if (adjoint && !deterministic)
-    return fail(ctx, RW_E_UNSUPPORTED, "the adjoint always reduces per item (deterministic)");
   st = need_device(ctx);
   if (st != RW_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -546,14 +644,14 @@ rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* ge
   if (batched) {
     load_tune_cache(ctx);
     // a tune-key probe plan (shape only)
-    build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
+    st = build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
+    if (st != RW_OK) return st;
     key = tune_key(P, true, paths_uniform);
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) cfg = it->second;
   }
-  build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
-  P.a.atomic = (!adjoint && !deterministic) ? 1 : 0;
-  P.a.direct = (!adjoint && !P.a.atomic && P.a.map.chunks_per_unit == 1) ? 1 : 0;
+  st = build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
+  if (st != RW_OK) return st;
   if (adjoint) {
     P.a.cot_R = cot_R;
     P.a.cot_bins = cot_bins;
@@ -565,18 +663,12 @@ rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* ge
     if (st != RW_OK) return st;
     ctx->tune[key] = best;
     save_tune_cache(ctx);
-    build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, best);
-    P.a.atomic = (!adjoint && !deterministic) ? 1 : 0;
-    P.a.direct = (!adjoint && !P.a.atomic && P.a.map.chunks_per_unit == 1) ? 1 : 0;
+    st = build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, best);
+    if (st != RW_OK) return st;
     if (adjoint) {
       P.a.cot_R = cot_R;
       P.a.cot_bins = cot_bins;
     }
-  }
-  if (!P.a.direct && !P.a.atomic && P.a.map.n_items > 0) {
-    st = ensure_partial(ctx, size_t(P.a.map.n_items) * P.a.part_len * sizeof(double));
-    if (st != RW_OK) return st;
-    P.a.partial = ctx->partial;
   }
   if (batched && use_graph)
     return enqueue_graph(ctx, P, out, grad, grad_sumsq, adj_vertices, flags, s);
@@ -648,7 +740,8 @@ rw_status rw_destroy(rw_context* ctx) {
       if (kv.second.graph) hipGraphDestroy(kv.second.graph);
       if (kv.second.done) hipEventDestroy(kv.second.done);
     }
-    if (ctx->partial) hipFree(ctx->partial);
+    if (ctx->workspace) hipFree(ctx->workspace);
+    if (ctx->sched) hipFree(ctx->sched);
     if (ctx->queue) hipFree(ctx->queue);
   }
   delete ctx;
@@ -666,7 +759,7 @@ rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* 
 rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                            const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
                            rw_tally* out, const rw_batch_opts* opts, void* stream) {
-  rw_batch_opts def{1, 0, 1, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0};
   return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, out, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false, stream);
 }
@@ -684,7 +777,7 @@ rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geom
                            const float* cot_R, const float* cot_bins, double* grad,
                            double* grad_sumsq, int64_t* vertices, int32_t* flags,
                            const rw_batch_opts* opts, void* stream) {
-  rw_batch_opts def{1, 0, 1, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0};
   return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, nullptr, cot_R, cot_bins,
                   grad, grad_sumsq, vertices, flags, opts ? opts : &def, true, true, stream);
 }

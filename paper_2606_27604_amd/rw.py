@@ -73,7 +73,6 @@ class RwBatchOptsC(ctypes.Structure):
     _fields_ = [
         ("use_graph", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
-        ("deterministic_reduce", ctypes.c_int32),
         ("unit_begin", ctypes.c_int64),
         ("unit_end", ctypes.c_int64),
     ]
@@ -280,8 +279,8 @@ class Context:
             raise RwError(st, self.last_error())
 
 
-def _opts(use_graph=True, autotune=False, deterministic=True, unit_begin=0, unit_end=0):
-    return RwBatchOptsC(int(use_graph), int(autotune), int(deterministic), unit_begin, unit_end)
+def _opts(use_graph=True, autotune=False, unit_begin=0, unit_end=0):
+    return RwBatchOptsC(int(use_graph), int(autotune), unit_begin, unit_end)
 
 
 # ---------------------------------------------------------------------------
@@ -296,12 +295,12 @@ def rw_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit: int, 
 
 
 def rw_batch_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit, paths_uniform: int,
-                     seed: int, out: Tally, use_graph=True, autotune=False, deterministic=True,
-                     unit_begin=0, unit_end=0, stream=None):
+                     seed: int, out: Tally, use_graph=True, autotune=False, unit_begin=0,
+                     unit_end=0, stream=None):
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (media.n_units,), "paths_per_unit")
     g = geom.c()
-    o = _opts(use_graph, autotune, deterministic, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end)
     ctx._check(load_library().rw_batch_forward(ctx.h, ctypes.byref(media._c), ctypes.byref(g),
                                                _ptr(paths_per_unit), int(paths_uniform), int(seed),
                                                ctypes.byref(out._c), ctypes.byref(o),
@@ -339,7 +338,7 @@ def rw_batch_adjoint(ctx: Context, media: Media, geom: Geometry, paths_per_unit,
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (media.n_units,), "paths_per_unit")
     g = geom.c()
-    o = _opts(use_graph, autotune, True, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end)
     ctx._check(load_library().rw_batch_adjoint(
         ctx.h, ctypes.byref(media._c), ctypes.byref(g), _ptr(paths_per_unit), int(paths_uniform),
         int(seed), _ptr(cot_R), _ptr(cot_bins), _ptr(grad), _ptr(grad_sumsq), _ptr(vertices),

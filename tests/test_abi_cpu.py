@@ -103,23 +103,23 @@ def test_validation_rejects_bad_arguments_without_a_device(lib):
 def test_batch_and_adjoint_validation(lib):
     ctx = rw.Context(-1)
     g, m, t = _args()
-    opts = rw.RwBatchOptsC(1, 0, 1, 10, 5)  # window end before begin
+    opts = rw.RwBatchOptsC(1, 0, 10, 5)  # window end before begin
     assert lib.rw_batch_forward(ctx.h, ctypes.byref(m), ctypes.byref(g), None, 64, 0,
                                 ctypes.byref(t), ctypes.byref(opts), None) == rw.RW_E_INVALID
-    opts = rw.RwBatchOptsC(1, 0, 1, 0, 0)
+    opts = rw.RwBatchOptsC(1, 0, 0, 0)
     # a per-unit path array needs the largest count in paths_uniform
     assert lib.rw_batch_forward(ctx.h, ctypes.byref(m), ctypes.byref(g), 0x9000, 0, 0,
                                 ctypes.byref(t), ctypes.byref(opts), None) == rw.RW_E_INVALID
     assert lib.rw_batch_forward(ctx.h, ctypes.byref(m), ctypes.byref(g), 0x9000, 128, 0,
                                 ctypes.byref(t), ctypes.byref(opts), None) == rw.RW_E_UNSUPPORTED
-    # adjoint: grad and flags are required; atomic accumulation is not offered
+    # adjoint: grad and flags are required
     assert lib.rw_adjoint(ctx.h, ctypes.byref(m), ctypes.byref(g), 64, 0, None, None, None, None,
                           None, 0x8000, None) == rw.RW_E_INVALID
     assert lib.rw_adjoint(ctx.h, ctypes.byref(m), ctypes.byref(g), 64, 0, None, None, 0x9000,
                           None, None, None, None) == rw.RW_E_INVALID
-    nondet = rw.RwBatchOptsC(1, 0, 0, 0, 0)
+    ok_opts = rw.RwBatchOptsC(0, 0, 0, 0)
     assert lib.rw_batch_adjoint(ctx.h, ctypes.byref(m), ctypes.byref(g), None, 64, 0, None, None,
-                                0x9000, None, None, 0x8000, ctypes.byref(nondet),
+                                0x9000, None, None, 0x8000, ctypes.byref(ok_opts),
                                 None) == rw.RW_E_UNSUPPORTED
     # trace takes one unit only
     assert lib.rw_debug_trace(ctx.h, ctypes.byref(m), ctypes.byref(g), None, 4, 4, 0, 0, 0x1,
