@@ -107,6 +107,11 @@ typedef struct {
   int64_t k_stride;           /* elements between media k and k+1 in each array;
                                  0 means n_sets * n_wl (a sub-range of a larger SoA
                                  array passes the full array's unit count) */
+  int64_t unit_base;          /* index of this call's first unit in the random-number
+                                 counter (unit u draws with index unit_base + u, mod
+                                 2^32), so a call on a sub-range of a larger set draws
+                                 the same random numbers as the call on the whole set;
+                                 0 for a call on a whole set */
 } rw_media;
 
 /* Raw FP64 sums, DEVICE pointers, caller-owned.  The library overwrites them

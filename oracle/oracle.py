@@ -134,10 +134,11 @@ def _bind(L):
     u32p = ctypes.POINTER(ctypes.c_uint32)
     gp = ctypes.POINTER(OrcGeometry)
     L.orc_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_int64, i64p, ctypes.c_uint64,
-                              ctypes.c_uint32, ctypes.c_int, dp, dp, i64p]
+                              ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, dp, dp, i64p]
     L.orc_forward.restype = ctypes.c_int
     L.orc_adjoint.argtypes = [gp, dp, dp, dp, dp, ctypes.c_int64, i64p, ctypes.c_uint64,
-                              ctypes.c_uint32, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+                              ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, dp, dp, dp, dp, dp,
+                              dp]
     L.orc_adjoint.restype = ctypes.c_int
     L.orc_trace.argtypes = [gp, dp, dp, dp, dp, u32p, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, dp, dp, dp]
@@ -193,11 +194,11 @@ def default_threads() -> int:
 
 
 def forward(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, tag: int = 0,
-            n_threads: int | None = None):
+            n_threads: int | None = None, unit_base: int = 0):
     """Raw FP64 sums per unit.
 
     Parameters are SoA arrays of shape [K, n_units] (any float dtype; FP32 values
-    are taken exactly).  Returns (tally[n_units, 8], bins[n_units, n_bins+2, 2],
+    are taken exactly).  Unit u draws its random numbers as unit unit_base + u.  Returns (tally[n_units, 8], bins[n_units, n_bins+2, 2],
     vertices[n_units])."""
     K = geo.n_media
     sigma_t = np.asarray(sigma_t)
@@ -209,7 +210,8 @@ def forward(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, tag: int = 0
     vert = np.zeros(n_units, dtype=np.int64)
     cg = geo.c()
     rc = lib().orc_forward(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(ww), n_units,
-                           _i64ptr(p), seed, tag, n_threads or default_threads(), _dptr(tally),
+                           _i64ptr(p), seed, tag, unit_base, n_threads or default_threads(),
+                           _dptr(tally),
                            _dptr(bins), _i64ptr(vert))
     if rc != 0:
         raise ValueError(f"orc_forward failed with code {rc}")
@@ -217,7 +219,8 @@ def forward(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, tag: int = 0
 
 
 def adjoint(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, cot_R=None, cot_bins=None,
-            tag: int = 0, n_threads: int | None = None, jacobian: bool = False):
+            tag: int = 0, n_threads: int | None = None, jacobian: bool = False,
+            unit_base: int = 0):
     """Score-function gradient sums (see orc_adjoint).  Returns (grad, sumsq) of
     shape [n_units, 4K], plus (jac_R [n_units, 4K], jac_bins [n_units, n_bins+2, 4K])
     when jacobian=True."""
@@ -236,7 +239,7 @@ def adjoint(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, cot_R=None, 
     jB = np.zeros((n_units, geo.n_bins + 2, P)) if jacobian else None
     cg = geo.c()
     rc = lib().orc_adjoint(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(ww), n_units,
-                           _i64ptr(p), seed, tag, n_threads or default_threads(),
+                           _i64ptr(p), seed, tag, unit_base, n_threads or default_threads(),
                            _dptr(cR) if cR is not None else None,
                            _dptr(cB) if cB is not None else None, _dptr(grad), _dptr(sumsq),
                            _dptr(jR) if jacobian else None, _dptr(jB) if jacobian else None)

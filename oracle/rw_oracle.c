@@ -387,6 +387,7 @@ typedef struct {
   const int64_t* paths;
   uint64_t seed;
   uint32_t tag;
+  uint32_t unit_base; /* counter index of unit 0 (unit u draws as unit_base + u) */
   /* adjoint inputs (NULL for the forward) */
   int adjoint;
   const double* cot_R;
@@ -447,7 +448,7 @@ static void run_task(job_t* job, int64_t t) {
   memset(&src, 0, sizeof(src));
   src.key[0] = (uint32_t)job->seed;
   src.key[1] = (uint32_t)(job->seed >> 32);
-  src.unit = (uint32_t)u;
+  src.unit = (uint32_t)((uint64_t)job->unit_base + (uint64_t)u);
   src.tag = job->tag;
   src.n_blocks = INT64_MAX;
   double score[4 * ORC_MAX_K];
@@ -582,8 +583,8 @@ static int check_geometry(const orc_geometry* g) {
  * -3 invalid unit parameters. */
 int orc_forward(const orc_geometry* geo, const double* sigma_t, const double* albedo,
                 const double* g, const double* w, int64_t n_units, const int64_t* paths,
-                uint64_t seed, uint32_t tag, int n_threads, double* tally, double* bins,
-                int64_t* vertices) {
+                uint64_t seed, uint32_t tag, uint32_t unit_base, int n_threads, double* tally,
+                double* bins, int64_t* vertices) {
   if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || !paths || n_units < 0 ||
       !tally || !bins || !vertices)
     return -1;
@@ -593,6 +594,7 @@ int orc_forward(const orc_geometry* geo, const double* sigma_t, const double* al
   job.geo = geo; job.K = geo->n_media;
   job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
   job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
   job.part_len = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
   int rc = run_job(&job, n_threads);
   if (rc == -1 || rc == -2) return rc;
@@ -620,9 +622,9 @@ int orc_forward(const orc_geometry* geo, const double* sigma_t, const double* al
  * divided by the path count). */
 int orc_adjoint(const orc_geometry* geo, const double* sigma_t, const double* albedo,
                 const double* g, const double* w, int64_t n_units, const int64_t* paths,
-                uint64_t seed, uint32_t tag, int n_threads, const double* cot_R,
-                const double* cot_bins, double* grad, double* grad_sumsq, double* jac_R,
-                double* jac_bins) {
+                uint64_t seed, uint32_t tag, uint32_t unit_base, int n_threads,
+                const double* cot_R, const double* cot_bins, double* grad, double* grad_sumsq,
+                double* jac_R, double* jac_bins) {
   if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || !paths || n_units < 0 ||
       !grad || !grad_sumsq)
     return -1;
@@ -634,6 +636,7 @@ int orc_adjoint(const orc_geometry* geo, const double* sigma_t, const double* al
   job.geo = geo; job.K = geo->n_media;
   job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
   job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
   job.adjoint = 1; job.cot_R = cot_R; job.cot_bins = cot_bins;
   job.want_jac = jac_R != NULL;
   job.part_len = 2 * P + (job.want_jac ? P + (int64_t)(nb + 2) * P : 0);

@@ -54,6 +54,7 @@ struct WalkArgs {
   const float* weight;
   int32_t weights_are_logits;
   int64_t k_stride;            // elements between consecutive media in the SoA arrays
+  uint32_t unit_base;          // counter index of unit 0 of the call
   int64_t n_units_total;
   WalkGeom geo;
   WorkMap map;

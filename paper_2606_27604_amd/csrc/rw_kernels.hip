@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
   // lane state
   Path p;
   bool alive = false, capped = false;
-  uint32_t path = 0, v = 0, lunit = 0, lslot = 0;
+  uint32_t path = 0, v = 0, lunit = 0, lslot = 0, lctr = 0;
 
   for (;;) {
     // Idle lanes take the next path indices of the current item.  When the
@@ -347,6 +347,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
           alive = true;
           lunit = uint32_t(u_cur);
           lslot = uint32_t(cur_slot);
+          lctr = a.unit_base + lunit;
         }
       }
       const uint32_t next = cursor + uint32_t(__popcll(idle));
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
 
     int ev = EV_COLLIDE;
     if (alive) {
-      const uint4 w = philox(v, path, a.tag, lunit, ks);
+      const uint4 w = philox(v, path, a.tag, lctr, ks);
       if (v == 0) {
         start_path_lds<K>(p, w, L.media, L.cold->entry_weight);
         v = 1;

@@ -225,6 +225,7 @@ rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_g
   a.weights_are_logits = media->weights_are_logits ? 1 : 0;
   a.n_units_total = n_units;
   a.k_stride = media->k_stride ? media->k_stride : n_units;
+  a.unit_base = uint32_t(uint64_t(media->unit_base));
   a.geo = make_geom(geom);
   a.key0 = uint32_t(seed);
   a.key1 = uint32_t(seed >> 32);

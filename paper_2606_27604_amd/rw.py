@@ -57,6 +57,7 @@ class RwMediaC(ctypes.Structure):
         ("n_wl", ctypes.c_int64),
         ("wavelength_nm", ctypes.c_void_p),
         ("k_stride", ctypes.c_int64),
+        ("unit_base", ctypes.c_int64),
     ]
 
 
@@ -188,7 +189,8 @@ class Media:
     """Device-resident media parameters, SoA float32 [K, n_units] (unit = set * n_wl + wl)."""
 
     def __init__(self, sigma_t, albedo, g, weight, n_sets: int, n_wl: int = 1,
-                 weights_are_logits: bool = False, wavelength_nm=None, k_stride: int = 0):
+                 weights_are_logits: bool = False, wavelength_nm=None, k_stride: int = 0,
+                 unit_base: int = 0):
         K = sigma_t.shape[0]
         n = n_sets * n_wl
         cols = k_stride if k_stride else n
@@ -202,8 +204,10 @@ class Media:
         self.logits = weights_are_logits
         self.wavelength_nm = wavelength_nm
         self.k_stride = k_stride
+        self.unit_base = unit_base
         self._c = RwMediaC(_ptr(sigma_t), _ptr(albedo), _ptr(g), _ptr(weight),
-                           int(weights_are_logits), n_sets, n_wl, _ptr(wavelength_nm), k_stride)
+                           int(weights_are_logits), n_sets, n_wl, _ptr(wavelength_nm), k_stride,
+                           unit_base)
 
     @property
     def n_units(self) -> int:
@@ -216,16 +220,19 @@ class Media:
         return cls(f(sigma_t), f(albedo), f(g), f(weight), n_sets, n_wl, weights_are_logits)
 
     def unit_range(self, begin: int, count: int) -> "Media":
-        """A view on units [begin, begin + count) of the same SoA arrays (n_sets = count)."""
+        """A view on units [begin, begin + count) of the same SoA arrays (n_sets = count).
+        Its units keep their random-number index (unit_base), so a call on the view
+        draws the same random numbers for them as a call on the whole set."""
         stride = self.k_stride or self.n_units
         sub = object.__new__(Media)
         sub.sigma_t, sub.albedo, sub.g, sub.weight = self.sigma_t, self.albedo, self.g, self.weight
         sub.K, sub.n_sets, sub.n_wl = self.K, count, 1
         sub.logits, sub.wavelength_nm, sub.k_stride = self.logits, None, stride
+        sub.unit_base = self.unit_base + begin
         es = 4  # float32
         sub._c = RwMediaC(self.sigma_t.data_ptr() + begin * es, self.albedo.data_ptr() + begin * es,
                           self.g.data_ptr() + begin * es, self.weight.data_ptr() + begin * es,
-                          int(self.logits), count, 1, None, stride)
+                          int(self.logits), count, 1, None, stride, sub.unit_base)
         return sub
 
 
