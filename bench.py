@@ -46,21 +46,32 @@ METRIC = "MC path vertices/s, fwd & adjoint, batched vs plain, at matched stat. 
 N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
 ISSUE_PEAK = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ  # lane-slots / s
 
-# Algorithmic work of one vertex, in VALU lane-slots (an op's issue cost in
-# full-rate cycles): one Philox4x32-10 block = 10 rounds x (2 32x32->64
-# products + 2 three-input XORs); ~60 FP32 add/mul/FMA/compare/select;
-# 7 transcendentals (log, rcp, sqrt, sin, cos, rsq, rcp).  32x32->64 integer
-# products and transcendentals issue at quarter rate on CDNA (4 slots).
-ALG_FP32_PER_VERTEX = 60
-ALG_TRANS_PER_VERTEX = 7
+# Algorithmic work of one vertex (what the method computes, not loop control),
+# in VALU lane-slots: each op weighted by its issue cost relative to a full-rate
+# FP32 FMA, as measured by `bench.py --micro` on the MI355X
+# (profiles/issue_rates_micro.md).
+#   random numbers: one Philox4x32-10 block = 10 rounds x (2 32x32->64
+#     multiply-adds + 2 three-input XORs); 4 word->float conversions (2 ops each);
+#   free flight: log, 1 mul, 1 fma; surface test: 2 compares;
+#   collision: position 2 fma, absorbed-weight fma + sub, weight mul, roulette
+#     compare; Henyey-Greenstein inversion ~12 ops + rcp; scattering frame and
+#     rotation ~30 ops + sqrt, sin, cos, rsq;
+#   surface hit (about 1 vertex in 20): distance rcp + 3 ops, Fresnel ~12 ops +
+#     sqrt + 2 rcp.
+# The adjoint adds the score bookkeeping: flight-length sum (2), collision
+# count (1), g-score fma chain (2).
 ALG_MAD64_PER_VERTEX = 20
-ALG_XOR_PER_VERTEX = 20
-QUARTER = 4.0
+ALG_XOR3_PER_VERTEX = 20
+ALG_FP32_PER_VERTEX = 65          # add/mul/fma/compare/select/convert, incl. word->float
+ALG_FP32_ADJ_EXTRA = 5
+ALG_TRANS_PER_VERTEX = 6.2        # log, rcp, sqrt, sin, cos, rsq + 1/20 x (3 at a surface hit)
+COST_MAD64, COST_XOR3, COST_TRANS = 1.21, 1.07, 2.33   # measured issue costs (FMA = 1)
 
 
-def alg_slots_per_vertex(mad_cost=QUARTER, trans_cost=QUARTER) -> float:
-    return (ALG_MAD64_PER_VERTEX * mad_cost + ALG_XOR_PER_VERTEX + ALG_FP32_PER_VERTEX +
-            ALG_TRANS_PER_VERTEX * trans_cost)
+def alg_slots_per_vertex(adjoint: bool) -> float:
+    return (ALG_MAD64_PER_VERTEX * COST_MAD64 + ALG_XOR3_PER_VERTEX * COST_XOR3 +
+            ALG_FP32_PER_VERTEX + (ALG_FP32_ADJ_EXTRA if adjoint else 0) +
+            ALG_TRANS_PER_VERTEX * COST_TRANS)
 
 
 def kernel_source_hash() -> str:
@@ -255,11 +266,11 @@ def main():
     adj_avg = float(np.mean(bat["adj_ms"]))
     vf_avg = float(np.mean(bat["vf"]))
     va_avg = float(np.mean(bat["va"]))
-    slots = alg_slots_per_vertex()
     if adj_avg >= fwd_avg:
         dom, dom_ms, dom_v = "walk_kernel<3, adjoint>", adj_avg, va_avg
     else:
         dom, dom_ms, dom_v = "walk_kernel<3, forward>", fwd_avg, vf_avg
+    slots = alg_slots_per_vertex(dom.endswith("adjoint>"))
     achieved = slots * dom_v / (dom_ms * 1e-3) / 1e12
     peak = ISSUE_PEAK / 1e12
     traffic = load_traffic(dom)
@@ -292,7 +303,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": traffic, "kernel": dom,
                      "slots_per_vertex": slots,
-                     "note": "VALU lane-slots (issue-cost weighted algorithmic ops) per second"},
+                     "note": "algorithmic VALU lane-slots (ops x measured issue cost) per second "
+                             "against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; traffic = HBM bytes "
+                             "per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated)"},
     }
     if plain is not None:
         pv = sum(plain["vf"]) + sum(plain["va"])
