@@ -104,11 +104,19 @@ hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg,
                        hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, hipStream_t stream);
-// forward: sum each unit's int64 fixed-point slots -> FP64 outputs, R sums from the bins
-constexpr int kConvertThreads = 256;
-// convert kernels loop over units with a grid stride
+// forward: sum each unit's int64 fixed-point slots -> FP64 outputs.  The
+// convert kernels use blocks of kConvWords words x kConvGroups slot groups and
+// loop over units with a grid stride.
+constexpr int kConvWords = 64;
+constexpr int kConvGroups = 4;
 inline unsigned convert_blocks(int64_t n_units) {
   return unsigned(n_units < (int64_t(1) << 20) ? n_units : (int64_t(1) << 20));
+}
+inline dim3 convert_forward_grid(int64_t n_units, int n_bins) {
+  const int words = 2 * (n_bins + 2) + 5;
+  const int64_t rows = (words + kConvWords - 1) / kConvWords;
+  const int64_t cap = (int64_t(1) << 22) / rows;
+  return dim3(unsigned(n_units < cap ? n_units : cap), unsigned(rows));
 }
 hipError_t launch_convert_forward(const WalkArgs& a, hipStream_t stream);
 // adjoint: FP64 sums -> gradients (and sums of squares), logits from the weights

@@ -115,23 +115,72 @@ __device__ __forceinline__ float exit_where(int ev, const Path& p) {
                            : (ev == EV_EXIT_BOTTOM ? kWhereBottom : kWhereNone);
 }
 
+// Exit records of an ending path (layout above).
+__device__ __forceinline__ float4 forward_record(int ev, const Path& p, uint32_t nv) {
+  return make_float4(p.W, p.A, exit_where(ev, p), __uint_as_float(nv));
+}
+
+// Adjoint scores of an ending path: c = x * (cot_R + cot_bins[slot]) with the
+// per-path sigma_t, albedo and g scores of its medium.
+__device__ __forceinline__ float score_alpha(const Path& p) {
+  return p.ncoll ? float(p.ncoll) * __builtin_amdgcn_rcpf(p.m.alb) : 0.0f;
+}
+__device__ __forceinline__ float score_g(const Path& p) { return fmaf(float(p.ncoll), p.m.gc, p.Sg); }
+
+
+__device__ __forceinline__ void adjoint_record(int ev, const Path& p, uint32_t nv, float4& r0,
+                                               float4& r1) {
+  const bool top = ev == EV_EXIT_TOP;
+  r0 = make_float4(top ? p.W : 0.0f, exit_where(ev, p), p.D, score_alpha(p));
+  r1 = make_float4(score_g(p), __uint_as_float(uint32_t(p.k)), __uint_as_float(nv), 0.0f);
+}
+
+// Add one record to the wave's LDS sums of the current unit.
+__device__ __forceinline__ void tally_forward_record(const WaveLds& L, const ColdConst& cc,
+                                                     float4 r) {
+  const float sc = cc.fix_scale, cap = cc.fix_cap;
+  if (r.z >= 0.0f) {
+    const int slot = radial_slot_r(r.z, cc);
+    atomicAdd(&L.acc[2 * slot], fix32(r.x, sc, cap));
+    atomicAdd(&L.acc[2 * slot + 1], fix32(r.x * r.x, sc, cap));
+  } else if (r.z == kWhereBottom) {
+    atomicAdd(&L.ctr[0], fix32(r.x, sc, cap));
+  }
+  atomicAdd(&L.ctr[1], fix32(r.y, sc, cap));
+  atomicAdd(&L.ctr[2], u64(__float_as_uint(r.w)));
+}
+
+__device__ __forceinline__ void tally_adjoint_record(const WalkArgs& a, const WaveLds& L,
+                                                     uint32_t unit, float4 r0, float4 r1) {
+  atomicAdd(&L.ctr[0], u64(__float_as_uint(r1.z)));
+  if (r0.x > 0.0f) {
+    const ColdConst cc = read_cold(L);
+    const int slot = radial_slot_r(r0.y, cc);
+    float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
+    if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + slot];
+    const double c = double(r0.x) * double(cot);
+    if (c != 0.0) {
+      const double css = c * double(r0.z), csa = c * double(r0.w), csg = c * double(r1.x);
+      double* t = reinterpret_cast<double*>(L.acc) + 8 * __float_as_uint(r1.y);
+      atomicAdd(&t[0], c);
+      atomicAdd(&t[1], c * c);
+      atomicAdd(&t[2], css);
+      atomicAdd(&t[3], css * css);
+      atomicAdd(&t[4], csa);
+      atomicAdd(&t[5], csa * csa);
+      atomicAdd(&t[6], csg);
+      atomicAdd(&t[7], csg * csg);
+    }
+  }
+}
+
 // Tally records [head, head + n) of the ring (n <= 64), one per lane.
 __device__ __forceinline__ void tally_forward(const WaveLds& L, uint32_t head, uint32_t n,
                                               int lane) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (uint32_t(lane) < n) {
     const ColdConst cc = read_cold(L);
-    const float sc = cc.fix_scale, cap = cc.fix_cap;
-    const float4 r = L.ring[(head + lane) & (kExitRing - 1)];
-    if (r.z >= 0.0f) {
-      const int slot = radial_slot_r(r.z, cc);
-      atomicAdd(&L.acc[2 * slot], fix32(r.x, sc, cap));
-      atomicAdd(&L.acc[2 * slot + 1], fix32(r.x * r.x, sc, cap));
-    } else if (r.z == kWhereBottom) {
-      atomicAdd(&L.ctr[0], fix32(r.x, sc, cap));
-    }
-    atomicAdd(&L.ctr[1], fix32(r.y, sc, cap));
-    atomicAdd(&L.ctr[2], u64(__float_as_uint(r.w)));
+    tally_forward_record(L, cc, L.ring[(head + lane) & (kExitRing - 1)]);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -142,27 +191,7 @@ __device__ __forceinline__ void tally_adjoint(const WalkArgs& a, const WaveLds& 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (uint32_t(lane) < n) {
     const uint32_t i = (head + lane) & (kExitRing - 1);
-    const float4 r0 = L.ring[2 * i], r1 = L.ring[2 * i + 1];
-    atomicAdd(&L.ctr[0], u64(__float_as_uint(r1.z)));
-    if (r0.x > 0.0f) {
-      const ColdConst cc = read_cold(L);
-      const int slot = radial_slot_r(r0.y, cc);
-      float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
-      if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + slot];
-      const double c = double(r0.x) * double(cot);
-      if (c != 0.0) {
-        const double css = c * double(r0.z), csa = c * double(r0.w), csg = c * double(r1.x);
-        double* t = reinterpret_cast<double*>(L.acc) + 8 * __float_as_uint(r1.y);
-        atomicAdd(&t[0], c);
-        atomicAdd(&t[1], c * c);
-        atomicAdd(&t[2], css);
-        atomicAdd(&t[3], css * css);
-        atomicAdd(&t[4], csa);
-        atomicAdd(&t[5], csa * csa);
-        atomicAdd(&t[6], csg);
-        atomicAdd(&t[7], csg * csg);
-      }
-    }
+    tally_adjoint_record(a, L, unit, L.ring[2 * i], L.ring[2 * i + 1]);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -179,21 +208,17 @@ __device__ __forceinline__ void exit_global_forward(const WalkArgs& a, const Wav
   if (ev == EV_EXIT_TOP) {
     const int b = radial_slot(p.x, p.y, cc);
     u64* B = reinterpret_cast<u64*>(a.tb + int64_t(slot) * nb2);
-    atomicAdd(&B[2 * b], fix32(p.W, sc, cap));
-    atomicAdd(&B[2 * b + 1], fix32(p.W * p.W, sc, cap));
+    const u64 q1 = fix32(p.W, sc, cap), q2 = fix32(p.W * p.W, sc, cap);
+    atomicAdd(&B[2 * b], q1);
+    atomicAdd(&B[2 * b + 1], q2);
+    atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 0]), q1);
+    atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 1]), q2);
   } else if (ev == EV_EXIT_BOTTOM) {
     atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 2]), fix32(p.W, sc, cap));
   }
   atomicAdd(reinterpret_cast<u64*>(&a.tc[int64_t(slot) * 4 + 3]), fix32(p.A, sc, cap));
   atomicAdd(reinterpret_cast<u64*>(&a.tv[slot]), u64(nv));
 }
-
-// Adjoint scores of an ending path: c = x * (cot_R + cot_bins[slot]) with the
-// per-path sigma_t, albedo and g scores of its medium.
-__device__ __forceinline__ float score_alpha(const Path& p) {
-  return p.ncoll ? float(p.ncoll) * __builtin_amdgcn_rcpf(p.m.alb) : 0.0f;
-}
-__device__ __forceinline__ float score_g(const Path& p) { return fmaf(float(p.ncoll), p.m.gc, p.Sg); }
 
 template <int K>
 __device__ __forceinline__ void exit_global_adjoint(const WalkArgs& a, const WaveLds& L,
@@ -238,11 +263,21 @@ __device__ __forceinline__ void flush_unit(const WalkArgs& a, const WaveLds& L, 
   if (!ADJ) {
     const int nb2 = 2 * (a.geo.n_bins + 2);
     u64* B = reinterpret_cast<u64*>(a.tb + slot * nb2);
+    u64 s1 = 0, s2 = 0;  // top totals: every top exit lands in one slot
     for (int i = lane; i < nb2; i += kWave) {
-      B[i] = L.acc[i];
+      const u64 x = L.acc[i];
+      B[i] = x;
+      if (i & 1) s2 += x; else s1 += x;
       L.acc[i] = 0ull;
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1 += __shfl_xor(s1, off, kWave);
+      s2 += __shfl_xor(s2, off, kWave);
+    }
     if (lane == 0) {
+      a.tc[slot * 4 + 0] = int64_t(s1);
+      a.tc[slot * 4 + 1] = int64_t(s2);
       a.tc[slot * 4 + 2] = int64_t(L.ctr[0]);
       a.tc[slot * 4 + 3] = int64_t(L.ctr[1]);
       a.tv[slot] = int64_t(L.ctr[2]);
@@ -354,7 +389,11 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
       cursor = next < pend ? next : pend;
     }
     // no lane alive: the last item has been handed out and every path ended
-    if (__ballot(alive) == 0) break;
+    const uint64_t busy = __ballot(alive);
+    if (busy == 0) break;
+    // no further path will come and at most half the lanes are busy: finish
+    // in the tail loop below
+    if (done && cursor >= pend && __popcll(busy) <= kWave / 2) break;
 
     // A wave carrying a long path is on the critical path of the launch:
     // raise its issue priority while it does (checked every 16 iterations).
@@ -397,14 +436,10 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
       if (ending) {
         if (local) {
           const uint32_t i = (tail + lane_rank(lm)) & (kExitRing - 1);
-          const float where = exit_where(ev, p);
           if (!ADJ) {
-            L.ring[i] = make_float4(p.W, p.A, where, __uint_as_float(v));
+            L.ring[i] = forward_record(ev, p, v);
           } else {
-            const bool top = ev == EV_EXIT_TOP;
-            L.ring[2 * i] = make_float4(top ? p.W : 0.0f, where, p.D, score_alpha(p));
-            L.ring[2 * i + 1] = make_float4(score_g(p), __uint_as_float(uint32_t(p.k)),
-                                            __uint_as_float(v), 0.0f);
+            adjoint_record(ev, p, v, L.ring[2 * i], L.ring[2 * i + 1]);
           }
         } else {
           if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
@@ -414,114 +449,183 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
       tail += n_new;
     }
   }
+
+  // ---- tail: the paths still running after the last one was handed out ----
+  // A wave here holds a few long paths and little else, and one iteration of
+  // it is bound by the latency of its dependent chain (Philox rounds, then the
+  // vertex step).  The idle lanes take the Philox blocks off that chain: each
+  // round, lane l computes the block of vertex v + (l mod d) of the
+  // (l / d)-th running path (d = 64 / running paths, rounded to a power of
+  // two) into LDS, and every running path then takes d steps, reading one
+  // block per step.  Ending paths tally directly (few lanes).
+  if (__ballot(alive) != 0) {
+    while (head != tail) {  // the ring's LDS is reused for the blocks
+      const uint32_t n = (tail - head) < uint32_t(kWave) ? (tail - head) : uint32_t(kWave);
+      if (!ADJ) tally_forward(L, head, n, lane);
+      else tally_adjoint<K>(a, L, uint32_t(u_cur), head, n, lane);
+      head += n;
+    }
+    __builtin_amdgcn_s_setprio(3);
+    boosted = true;
+    uint4* blk = reinterpret_cast<uint4*>(L.ring);  // kWave blocks of 16 bytes
+    for (;;) {
+      const uint64_t am = __ballot(alive);
+      if (am == 0) break;
+      const uint32_t na = uint32_t(__popcll(am));
+      const uint32_t lg = na <= 1 ? 6u : na <= 2 ? 5u : na <= 4 ? 4u : na <= 8 ? 3u
+                        : na <= 16 ? 2u : na <= 32 ? 1u : 0u;
+      const uint32_t rank = lane_rank(am);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (alive) blk[rank] = make_uint4(path, v, lctr, 0u);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint32_t j = uint32_t(lane) >> lg;
+      const uint32_t t = uint32_t(lane) & ((1u << lg) - 1u);
+      uint4 q = make_uint4(0u, 0u, 0u, 0u);
+      if (j < na) q = blk[j];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (j < na) blk[lane] = philox(q.y + t, q.x, a.tag, q.z, ks);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint32_t depth = 1u << lg;
+      for (uint32_t s = 0; s < depth; ++s) {
+        if (__ballot(alive) == 0) break;
+        if (alive) {
+          const uint4 w = blk[(rank << lg) + s];
+          int ev = EV_COLLIDE;
+          if (v == 0) {
+            start_path_lds<K>(p, w, L.media, L.cold->entry_weight);
+            v = 1;
+          } else {
+            ev = vertex_step<ADJ>(p, w, geo);
+            if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+              ev = EV_CAP;
+              capped = true;
+            }
+            if (ev >= EV_EXIT_TOP) alive = false;
+            else ++v;
+          }
+          if (ev >= EV_EXIT_TOP) {
+            if (lslot == uint32_t(cur_slot)) {
+              if (!ADJ) {
+                tally_forward_record(L, read_cold(L), forward_record(ev, p, v));
+              } else {
+                float4 r0, r1;
+                adjoint_record(ev, p, v, r0, r1);
+                tally_adjoint_record(a, L, lunit, r0, r1);
+              }
+            } else {
+              if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
+              else exit_global_adjoint<K>(a, L, lslot, lunit, ev, p, v);
+            }
+          }
+        }
+      }
+    }
+  }
   if (boosted) __builtin_amdgcn_s_setprio(0);
   if (u_cur >= 0) flush_unit<K, ADJ>(a, L, head, tail, cur_slot, u_cur, lane);
   if (__any(capped) && lane == 0) atomicOr(a.flags, RW_FLAG_VERTEX_CAP);
 }
 
-// Forward: per unit, the sums of its slots (exact int64) -> FP64 outputs; the
-// top totals are the sums over all radial slots (every top exit lands in one).
-// One block per unit.  Direct: the unit's single slot is its output, converted
-// in place (each word is read before it is overwritten by the same thread).
-__global__ void __launch_bounds__(kConvertThreads) convert_forward_kernel(const WalkArgs a) {
-  __shared__ long long red[2][kConvertThreads / kWave];
-  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
-  __syncthreads();  // red[] of the previous unit has been read
-  const int64_t u = a.map.unit_begin + ul;
-  const int tid = threadIdx.x;
+// Forward: per unit, the sums of its slots -> outputs.  A slot holds the words
+// bins[(n_bins+2)*2] | R[4] = (sum x, sum x^2, T, A) | vertices, all exact
+// int64; the unit's slots are added exactly and converted to FP64 (vertices
+// stay int64).  Block = kConvWords words x kConvGroups groups of slots;
+// blockIdx.y picks the words, blockIdx.x strides over the units.  Direct: the
+// unit's single slot is its output, converted in place (every word is read
+// before the barrier and written after it by the same thread).
+__global__ void __launch_bounds__(kConvWords * kConvGroups) convert_forward_kernel(const WalkArgs a) {
+  __shared__ long long part[kConvGroups][kConvWords];
   const int nb2 = 2 * (a.geo.n_bins + 2);
+  const int wi = threadIdx.x % kConvWords, grp = threadIdx.x / kConvWords;
+  const int w = blockIdx.y * kConvWords + wi;
   const double inv = 1.0 / double(a.fix_scale32);
-  const int64_t s0 = a.direct ? u : ul * a.map.chunks_per_unit;
   const int64_t ns = a.direct ? 1 : a.map.chunks_per_unit;
-  double* B = a.out_bins + u * nb2;
-  long long s1 = 0, s2 = 0;
-  for (int i = tid; i < nb2; i += kConvertThreads) {
+  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
+    const int64_t u = a.map.unit_begin + ul;
+    const int64_t s0 = a.direct ? u : ul * a.map.chunks_per_unit;
     long long v = 0;
-    for (int64_t c = 0; c < ns; ++c) v += a.tb[(s0 + c) * nb2 + i];
-    if (i & 1) s2 += v; else s1 += v;
-    B[i] = double(v) * inv;
-  }
+    if (w < nb2 + 5) {
+      for (int64_t c = grp; c < ns; c += kConvGroups) {
+        const int64_t sl = s0 + c;
+        v += w < nb2 ? a.tb[sl * nb2 + w] : (w < nb2 + 4 ? a.tc[sl * 4 + (w - nb2)] : a.tv[sl]);
+      }
+    }
+    part[grp][wi] = v;
+    __syncthreads();
+    if (grp == 0 && w < nb2 + 5) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s1 += __shfl_xor(s1, off, kWave);
-    s2 += __shfl_xor(s2, off, kWave);
-  }
-  if ((tid & (kWave - 1)) == 0) {
-    red[0][tid / kWave] = s1;
-    red[1][tid / kWave] = s2;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    long long t1 = 0, t2 = 0, tt = 0, ta = 0, tv = 0;
-    for (int w = 0; w < kConvertThreads / kWave; ++w) {
-      t1 += red[0][w];
-      t2 += red[1][w];
+      for (int g = 1; g < kConvGroups; ++g) v += part[g][wi];
+      if (w < nb2) a.out_bins[u * nb2 + w] = double(v) * inv;
+      else if (w < nb2 + 4) a.out_R[u * 4 + (w - nb2)] = double(v) * inv;
+      else a.out_vertices[u] = v;
     }
-    for (int64_t c = 0; c < ns; ++c) {
-      tt += a.tc[(s0 + c) * 4 + 2];
-      ta += a.tc[(s0 + c) * 4 + 3];
-      tv += a.tv[s0 + c];
-    }
-    double* R = a.out_R + u * 4;
-    R[0] = double(t1) * inv;
-    R[1] = double(t2) * inv;
-    R[2] = double(tt) * inv;
-    R[3] = double(ta) * inv;
-    a.out_vertices[u] = tv;
-  }
+    __syncthreads();
   }
 }
 
-// Adjoint: per unit, the sums of its slots (in slot order), then the [K][8]
-// sums (C, Q, Ss, Ss2, Sa, Sa2, Sg, Sg2) to gradients: sigma_t_k, alpha_k, g_k
-// directly; logit_j = C_j - w_j C with sum of squares (1 - w_j)^2 Q_j +
-// w_j^2 (Q - Q_j).  One wave per unit.
+// Adjoint: per unit, the sums of its slots (fixed order: by group, groups
+// combined in group order), then the [K][8] sums (C, Q, Ss, Ss2, Sa, Sa2, Sg,
+// Sg2) to gradients: sigma_t_k, alpha_k, g_k directly; logit_j = C_j - w_j C
+// with sum of squares (1 - w_j)^2 Q_j + w_j^2 (Q - Q_j).  One block per unit
+// (grid-stride), kConvWords x kConvGroups threads.
 template <int K>
-__global__ void __launch_bounds__(kWave) convert_adjoint_kernel(const WalkArgs a, double* grad,
-                                                                double* grad_sumsq,
-                                                                int64_t* vertices_out) {
-  __shared__ double sums[8 * K];
-  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
-  __syncthreads();  // sums[] of the previous unit has been read
-  const int64_t u = a.map.unit_begin + ul;
-  const int tid = threadIdx.x;
-  const int64_t s0 = ul * a.map.chunks_per_unit;
+__global__ void __launch_bounds__(kConvWords * kConvGroups) convert_adjoint_kernel(
+    const WalkArgs a, double* grad, double* grad_sumsq, int64_t* vertices_out) {
+  static_assert(8 * K + 1 <= kConvWords, "adjoint slot wider than a block row");
+  __shared__ double part[kConvGroups][kConvWords];
+  __shared__ long long vpart[kConvGroups];
+  const int wi = threadIdx.x % kConvWords, grp = threadIdx.x / kConvWords;
   const int64_t ns = a.map.chunks_per_unit;
-  if (tid < 8 * K) {
-    double v = 0.0;
-    for (int64_t c = 0; c < ns; ++c) v += a.adj[(s0 + c) * (8 * K) + tid];
-    sums[tid] = v;
-  } else if (tid == 8 * K && vertices_out) {
-    long long nv = 0;
-    for (int64_t c = 0; c < ns; ++c) nv += a.adj_vertices[s0 + c];
-    vertices_out[u] = nv;
-  }
-  __syncthreads();
-  if (tid != 0) continue;
-  const double* s = sums;
-  const UnitParams<K> up = load_unit<K>(a, u);
-  double C = 0.0, Q = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    C += s[8 * k + 0];
-    Q += s[8 * k + 1];
-  }
-  double* G = grad + u * (4 * K);
-  double* S = grad_sumsq ? grad_sumsq + u * (4 * K) : nullptr;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double w = double(up.w[k]);
-    G[k] = s[8 * k + 2];
-    G[K + k] = s[8 * k + 4];
-    G[2 * K + k] = s[8 * k + 6];
-    G[3 * K + k] = s[8 * k + 0] - w * C;
-    if (S) {
-      S[k] = s[8 * k + 3];
-      S[K + k] = s[8 * k + 5];
-      S[2 * K + k] = s[8 * k + 7];
-      S[3 * K + k] = (1.0 - w) * (1.0 - w) * s[8 * k + 1] + w * w * (Q - s[8 * k + 1]);
+  for (int64_t ul = blockIdx.x; ul < a.map.n_units; ul += gridDim.x) {
+    const int64_t u = a.map.unit_begin + ul;
+    const int64_t s0 = ul * ns;
+    if (wi < 8 * K) {
+      double v = 0.0;
+      for (int64_t c = grp; c < ns; c += kConvGroups) v += a.adj[(s0 + c) * (8 * K) + wi];
+      part[grp][wi] = v;
+    } else if (wi == 8 * K) {
+      long long nv = 0;
+      for (int64_t c = grp; c < ns; c += kConvGroups) nv += a.adj_vertices[s0 + c];
+      vpart[grp] = nv;
     }
-  }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s[8 * K];
+      for (int m = 0; m < 8 * K; ++m) {
+        double v = part[0][m];
+        for (int g = 1; g < kConvGroups; ++g) v += part[g][m];
+        s[m] = v;
+      }
+      if (vertices_out) {
+        long long nv = 0;
+        for (int g = 0; g < kConvGroups; ++g) nv += vpart[g];
+        vertices_out[u] = nv;
+      }
+      const UnitParams<K> up = load_unit<K>(a, u);
+      double C = 0.0, Q = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        C += s[8 * k + 0];
+        Q += s[8 * k + 1];
+      }
+      double* G = grad + u * (4 * K);
+      double* S = grad_sumsq ? grad_sumsq + u * (4 * K) : nullptr;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double wk = double(up.w[k]);
+        G[k] = s[8 * k + 2];
+        G[K + k] = s[8 * k + 4];
+        G[2 * K + k] = s[8 * k + 6];
+        G[3 * K + k] = s[8 * k + 0] - wk * C;
+        if (S) {
+          S[k] = s[8 * k + 3];
+          S[K + k] = s[8 * k + 5];
+          S[2 * K + k] = s[8 * k + 7];
+          S[3 * K + k] = (1.0 - wk) * (1.0 - wk) * s[8 * k + 1] + wk * wk * (Q - s[8 * k + 1]);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -808,8 +912,8 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, hipStream_t s) {
 
 hipError_t launch_convert_forward(const WalkArgs& a, hipStream_t s) {
   if (a.map.n_units <= 0) return hipSuccess;
-  hipLaunchKernelGGL(convert_forward_kernel, dim3(convert_blocks(a.map.n_units)),
-                     dim3(kConvertThreads), 0, s, a);
+  hipLaunchKernelGGL(convert_forward_kernel, convert_forward_grid(a.map.n_units, a.geo.n_bins),
+                     dim3(kConvWords * kConvGroups), 0, s, a);
   return hipGetLastError();
 }
 
@@ -818,10 +922,10 @@ hipError_t launch_convert_adjoint(const WalkArgs& a, int K, double* grad, double
   if (a.map.n_units <= 0) return hipSuccess;
   const unsigned grid = convert_blocks(a.map.n_units);
   switch (K) {
-    case 1: hipLaunchKernelGGL(convert_adjoint_kernel<1>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
-    case 2: hipLaunchKernelGGL(convert_adjoint_kernel<2>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
-    case 3: hipLaunchKernelGGL(convert_adjoint_kernel<3>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
-    case 4: hipLaunchKernelGGL(convert_adjoint_kernel<4>, dim3(grid), dim3(kWave), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 1: hipLaunchKernelGGL(convert_adjoint_kernel<1>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 2: hipLaunchKernelGGL(convert_adjoint_kernel<2>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 3: hipLaunchKernelGGL(convert_adjoint_kernel<3>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case 4: hipLaunchKernelGGL(convert_adjoint_kernel<4>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

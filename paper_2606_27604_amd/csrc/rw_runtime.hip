@@ -26,7 +26,7 @@ using namespace rw;
 namespace {
 
 struct TuneCfg {
-  int chunk = 4096;        // paths per work item (multiple of 64)
+  int chunk = 2048;        // paths per work item (multiple of 64)
   int waves_per_wg = 4;    // workgroup = waves_per_wg wavefronts
   int wgs_per_cu = 0;      // persistent grid: workgroups per CU (0: occupancy limit)
 };
@@ -581,12 +581,12 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
                    unsigned(walk_lds_bytes(a, wpw)), {arg_bytes(a)}});
   if (P.adjoint) {
     specs.push_back({convert_adjoint_kernel_ptr(P.K), dim3(convert_blocks(a.map.n_units)),
-                     dim3(kWave), 0,
+                     dim3(kConvWords * kConvGroups), 0,
                      {arg_bytes(a), arg_bytes(grad), arg_bytes(grad_sumsq),
                       arg_bytes(adj_vertices)}});
   } else {
-    specs.push_back({convert_forward_kernel_ptr(), dim3(convert_blocks(a.map.n_units)),
-                     dim3(kConvertThreads), 0, {arg_bytes(a)}});
+    specs.push_back({convert_forward_kernel_ptr(), convert_forward_grid(a.map.n_units, a.geo.n_bins),
+                     dim3(kConvWords * kConvGroups), 0, {arg_bytes(a)}});
   }
   char key[200];
   std::snprintf(key, sizeof(key), "K%d adj%d grid%lld wpw%d lds%d units%lld direct%d nodes%zu",
