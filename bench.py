@@ -1,6 +1,7 @@
 """Benchmark of the mixture-of-media random walk on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3] [--micro]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3] [--no-c4]
+                    [--micro]
 
 One step is one pass of the whole path over the 81-wavelength three-medium
 workload (81 wavelengths 380-780 nm, per-medium sigma_t log-uniform in
@@ -17,7 +18,8 @@ numbers, same estimates).
 
 Extra fields: the batched sweep of 65,536 three-medium sets x 16 wavelengths
 at 4,096 paths (one persistent launch) and its per-set plain launches timed on
-a subset of sets; the roofline of the dominant kernel (ALU-bound: VALU issue
+a subset of sets; the adjoint sweep (1,024 sets x 81 wavelengths x 2^14
+paths, random bin cotangents); the roofline of the dominant kernel (ALU-bound: VALU issue
 slots per vertex x vertices / measured kernel time, against the issue peak of
 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
@@ -126,7 +128,8 @@ def micro(args):
 
 def cpu_baseline(wl, seed, max_seconds=30.0):
     """The FP64 oracle on the host on a bounded sample of the same workload: all
-    81 wavelengths at fewer paths (forward + adjoint)."""
+    81 wavelengths, forward + adjoint, at a path count doubled from 2^16 until one
+    pass takes 8 s (or reaches the workload's 2^20)."""
     from oracle import oracle as O
 
     try:
@@ -134,7 +137,7 @@ def cpu_baseline(wl, seed, max_seconds=30.0):
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))  # the host share of one GPU
-    paths = 1 << 13
+    paths = 1 << 16
     geo = O.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins)
     total_v, total_t = 0, 0.0
     rng = np.random.default_rng(99)
@@ -147,7 +150,7 @@ def cpu_baseline(wl, seed, max_seconds=30.0):
                   cot_R=np.ones(wl.n_units), cot_bins=cot_B, n_threads=cores)
         dt = time.perf_counter() - t0
         total_v, total_t = 2 * int(vert.sum()), dt
-        if dt > 4.0 or paths >= (1 << 17) or dt * 2 > max_seconds:
+        if dt > 8.0 or paths >= wl.paths_per_unit or dt * 2 > max_seconds:
             break
         paths *= 2
     return {"value": total_v / total_t, "unit": "vertices/s", "cores": cores, "kind": "oracle",
@@ -165,6 +168,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--c3-sets", type=int, default=65536)
     ap.add_argument("--c3-plain-sets", type=int, default=512)
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--c4-sets", type=int, default=1024)
     ap.add_argument("--micro", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run an elementwise copy of 256 MiB in / 256 MiB out (reference "
@@ -320,6 +325,8 @@ def main():
 
     if not args.no_c3:
         out["batched_sweep"] = c3(ctx, rw, api, workloads, torch, args)
+    if not args.no_c4:
+        out["adjoint_sweep"] = c4(ctx, rw, workloads, torch, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, seed=5)
     print(json.dumps(out), flush=True)
@@ -376,6 +383,41 @@ def c3(ctx, rw, api, workloads, torch, args):
                 "per_set_over_batched_time": sub_p_ms / sub_b_ms,
                 "same_estimates_as_batched": same})
     return res
+
+
+def c4(ctx, rw, workloads, torch, args):
+    """Adjoint sweep: 1,024 three-medium sets x 81 wavelengths x 2^14 paths,
+    cotangents v_R = 1 and v_bins ~ N(0, 1): one batched path-replay launch
+    (after its forward), timed with HIP events on the launch stream."""
+    wl = workloads.config4(n_sets=args.c4_sets)
+    media = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_sets, wl.n_wl)
+    geom = rw.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins)
+    n, P = wl.n_units, wl.paths_per_unit
+    cot_R = torch.from_numpy(wl.extra["cot_R"]).cuda()
+    cot_B = torch.from_numpy(wl.extra["cot_bins"]).cuda()
+    grad = torch.empty((n, 12), dtype=torch.float64, device="cuda")
+    sq = torch.empty_like(grad)
+    vert = torch.empty(n, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tally = rw.Tally(n, wl.n_bins)
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for rep in range(2):  # first repetition warms up (graph build)
+        ev[0].record(s)
+        rw.rw_batch_forward(ctx, media, geom, None, P, 41 + rep, tally, stream=s)
+        ev[1].record(s)
+        rw.rw_batch_adjoint(ctx, media, geom, None, P, 41 + rep, cot_R, cot_B, grad, sq, vert,
+                            flags, stream=s)
+        ev[2].record(s)
+        torch.cuda.synchronize()
+    fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    v = int(vert.sum().item())
+    return {"workload": f"adjoint-{wl.n_sets}x81: K=3, n=1.4, {P} paths per unit, v_R = 1, "
+                        "v_bins ~ N(0, 1)",
+            "units": n, "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+            "adjoint_vertices_per_s": v / (adj_ms * 1e-3),
+            "forward_vertices_per_s": int(tally.vertices.sum().item()) / (fwd_ms * 1e-3),
+            "device_flags": int(flags.item()) | int(tally.flags.item())}
 
 
 if __name__ == "__main__":

@@ -306,3 +306,25 @@ def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     sq = np64(outs[0][1])[:, :3] * sub.sigma_t.T.astype(np.float64) ** 2
     tot, tot_se = gs.sum(1), np.sqrt(sq.sum(1))
     assert np.all(np.abs(tot) <= 4 * tot_se + 1e-9), tot / tot_se
+
+
+def test_adjoint_workload_subset_vs_oracle_gradient():
+    """Sets of the adjoint workload (K = 3, 81 wavelengths, 2^14 paths, v_R = 1,
+    v_bins ~ N(0, 1)) against the oracle's FP64 score gradient, same streams."""
+    wl = workloads.config4(n_sets=2)
+    m = media(wl.sigma_t, wl.albedo, wl.g, wl.weight)
+    g, og = geoms(3, wl.n_rel)
+    cR, cB = wl.extra["cot_R"], wl.extra["cot_bins"]
+    grad, sq, vert, flags = api.adjoint(ctx(), m, g, wl.paths_per_unit, 13,
+                                        cot_R=torch.from_numpy(cR).cuda(),
+                                        cot_bins=torch.from_numpy(cB).cuda())
+    assert rw.rw_check(ctx(), flags) == 0
+    og_, osq = O.adjoint(og, wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.paths_per_unit, 13,
+                         cot_R=cR, cot_bins=cB)
+    N = wl.paths_per_unit
+    mg, sg = mean_se(np64(grad), np64(sq), N)
+    mo, so = mean_se(og_, osq, N)
+    z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    # same random numbers: far inside the statistical error
+    assert np.median(np.abs(z)) <= 0.05, np.median(np.abs(z))
