@@ -130,7 +130,8 @@ typedef struct {
  * point; per unit, 64-bit integer sums, converted to FP64 at the end), so
  * results are bit-identical for the same seed whatever the launch shape or
  * scheduling.  A call with more than one work item per unit uses a device
- * workspace of (n_bins + 2) * 16 + 40 bytes per work item (2048 paths). */
+ * workspace of (n_bins + 2) * 16 + 40 bytes per work item (2048 paths, grown
+ * so that the workspace stays within 1 GiB). */
 rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                      int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
 

@@ -93,6 +93,8 @@ struct WalkArgs {
 constexpr int kExitRing = 64;
 constexpr int kMediaTableWords = (kMediaTableFloats + 1) / 2;
 constexpr int kColdConstWords = 4;  // 32 bytes after the media table
+// bound on the forward slot workspace of one call (bytes)
+constexpr int64_t kMaxSlotBytes = int64_t(1) << 30;
 inline int forward_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
 inline int adjoint_acc_words(int K) { return 8 * K + 2; }
 inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {

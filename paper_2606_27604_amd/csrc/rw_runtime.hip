@@ -234,9 +234,21 @@ rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_g
   P.adjoint = adjoint;
   P.cfg = cfg;
   P.n_window = ue - ub;
-  // chunk: at most the configured size, and no larger than the (rounded) path count
+  // chunk: at most the configured size, and no larger than the (rounded) path
+  // count.  Forward calls with several items per unit keep one slot of sums
+  // per item in the workspace; when that would exceed kMaxSlotBytes, items
+  // grow (up to one item per unit, which needs no workspace at all).
   int chunk = cfg.chunk;
   if (paths_uniform > 0 && paths_uniform < chunk) chunk = std::max(64, round_up(paths_uniform, 64));
+  if (!adjoint && paths_uniform > chunk) {
+    const double slot_bytes = double(2 * (geom->n_bins + 2) + 5) * 8.0;
+    while (paths_uniform > chunk &&
+           double(ue - ub) * double((paths_uniform + chunk - 1) / chunk) * slot_bytes >
+               double(kMaxSlotBytes) &&
+           chunk < (1 << 30))
+      chunk *= 2;
+    if (paths_uniform <= chunk) chunk = std::max(64, round_up(paths_uniform, 64));
+  }
   WorkMap& m = a.map;
   m.n_units = ue - ub;
   m.unit_begin = ub;

@@ -19,7 +19,7 @@ Targets are the forward model's own R(lambda) and R(r, lambda) for random
 three-medium parameters drawn like the 81-wavelength workload, with 1 %
 relative Gaussian noise on every value.
 
-    python -m paper_2606_27604_amd.fit [--targets 4096] [--iters 200] [--paths 4096]
+    python -m paper_2606_27604_amd.fit [--targets 4096] [--iters 200] [--paths 4096] [--lut N]
 
 prints one JSON line: wall time, loss history, spectral RMSE against the
 noise-free targets and parameter recovery (up to component permutation).
@@ -211,6 +211,50 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
     }
 
 
+def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_paths: int = 1 << 14,
+                target_paths: int = 1 << 18, lr: float = 1e-2, noise: float = 0.01, seed: int = 5,
+                device: str = "cuda") -> dict:
+    """The paper's own fitting route on the same targets as run_fit: tables
+    R(alpha, g), P_d(r | alpha, g) from the walk at sigma_t = 1 (lut_n x lut_n
+    cells at lut_paths photons), then Adam on eq. joint_loss with the LUT
+    mixture model (eq. mixture).  The fitted parameters are scored with the
+    Monte Carlo forward model, as in run_fit."""
+    from . import lut as L
+
+    ctx = rw.Context(torch.device(device).index or 0)
+    geom = rw.Geometry(n_media=3, n_rel=1.4, n_bins=workloads.N_BINS,
+                       r_min_mm=workloads.R_MIN_MM, r_max_mm=workloads.R_MAX_MM)
+    n_wl = workloads.wavelengths_81().size
+    n_units = n_targets * n_wl
+    true = draw(n_targets, seed, device)
+    tg = make_targets(ctx, geom, *true, target_paths, seed + 1000, noise, device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    table = L.generate(ctx, lut_n, lut_n, lut_paths, n_rel=1.4, n_bins=workloads.N_BINS,
+                       r_min=workloads.R_MIN_MM, r_max=workloads.R_MAX_MM)
+    torch.cuda.synchronize()
+    t_lut = time.perf_counter() - t0
+    nb = workloads.N_BINS
+    lr_min, lr_max = math.log(workloads.R_MIN_MM), math.log(workloads.R_MAX_MM)
+    step = (lr_max - lr_min) / nb
+    r = torch.exp(lr_min + (torch.arange(nb, dtype=torch.float32, device=device) + 0.5) * step)
+    start = draw(n_targets, seed + 1, device)
+    t1 = time.perf_counter()
+    (s, a, g, w), hist = L.fit(table, tg["R_noisy"], tg["Pd_noisy"], tg["mass"], start, r,
+                                iters=iters, lr=lr)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t1
+    with torch.no_grad():
+        m = rw.Media(s.float().contiguous(), a.float().contiguous(), g.float().contiguous(),
+                     w.float().contiguous(), n_units, 1)
+        fin = api.forward(ctx, m, geom, target_paths, seed + 2000)
+        rmse = float(torch.sqrt(((fin.R - tg["R"]) ** 2).mean()))
+    return {"workload": f"LUT refit: {n_targets} targets x {n_wl} wavelengths, LUT {lut_n}x{lut_n} "
+                        f"at {lut_paths} photons, {iters} Adam steps",
+            "lut_seconds": t_lut, "fit_seconds": t_fit, "loss_history": hist,
+            "spectral_rmse": rmse, "recovery_median_abs_error": recovery((s, a, g, w), true)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--targets", type=int, default=4096)
@@ -218,8 +262,14 @@ def main():
     ap.add_argument("--paths", type=int, default=4096)
     ap.add_argument("--target-paths", type=int, default=1 << 18)
     ap.add_argument("--log-every", type=int, default=20)
+    ap.add_argument("--lut", type=int, default=0,
+                    help="also run the LUT-based fit with an N x N table on the same targets")
+    ap.add_argument("--lut-paths", type=int, default=1 << 14)
     args = ap.parse_args()
     res = run_fit(args.targets, args.iters, args.paths, args.target_paths, log_every=args.log_every)
+    if args.lut:
+        res["lut_fit"] = run_lut_fit(args.targets, args.iters, args.lut, args.lut_paths,
+                                     args.target_paths)
     print(json.dumps(res), flush=True)
 
 

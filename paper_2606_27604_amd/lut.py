@@ -1,0 +1,169 @@
+"""Scale-independent lookup tables and the LUT-based K-media fit (Sec. 4.2).
+
+Generation (Sec. 4.2, "Scale-independent lookup table").  For a homogeneous
+semi-infinite medium the normalised profile depends on (alpha, g) only, and
+sigma_t rescales the radial axis (eq. separability):
+    P_d(r | alpha, g, sigma_t) = sigma_t^2 P_d(sigma_t r | alpha, g, 1).
+So one batched walk over an (alpha, g) grid at sigma_t = 1 gives R(alpha, g) and
+P_d(r | alpha, g) for every sigma_t.  Each grid cell is a K = 1 unit of the
+batched forward launch; the paper uses an 800 x 800 grid at 10^6 photons per
+cell.
+
+Fit (Sec. 4.2, eq. mixture, eq. joint_loss, "Optimization").  The K-media
+profile is
+    R_d_fit(r) = sum_k w_k R(alpha_k, g_k) P(r | alpha_k, g_k, sigma_t_k),
+with R bilinear in (alpha, g) and P trilinear in (alpha, g, log r), the radial
+coordinate scaled by sigma_t as above.  The loss is eq. joint_loss (lambda_R =
+5) and the optimiser Adam.  The interpolation and loss are differentiable torch
+code on the GPU; the tables come from the walk kernel.
+
+Readings: the grid is uniform in alpha over [0, alpha_max] and in g over
+[0, g_max] (the paper gives the size, not the spacing); radial interpolation is
+linear in log r between bin centres, and P is 0 outside the table's radial
+range (beyond it the table holds only its under/overflow slots).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import api, rw
+
+
+@dataclass
+class LUT:
+    alpha: torch.Tensor  # [Na] grid
+    g: torch.Tensor      # [Ng] grid
+    R: torch.Tensor      # [Na, Ng] total diffuse reflectance
+    Pd: torch.Tensor     # [Na, Ng, n_bins] normalised profile (mm^-2 at sigma_t = 1)
+    r_min: float
+    r_max: float
+    n_rel: float
+    paths: int
+
+    @property
+    def n_bins(self) -> int:
+        return self.Pd.shape[-1]
+
+
+def generate(ctx: rw.Context, n_alpha: int, n_g: int, paths: int, n_rel: float = 1.4,
+             n_bins: int = 256, r_min: float = 1e-3, r_max: float = 50.0,
+             alpha_max: float = 0.999, g_max: float = 0.99, seed: int = 17,
+             max_units_per_call: int = 1 << 17, stream=None) -> LUT:
+    """Tables over a uniform (alpha, g) grid at sigma_t = 1, one K = 1 unit per
+    cell, batched forward launches of at most max_units_per_call cells."""
+    dev = torch.device("cuda")
+    alpha = torch.linspace(0.0, alpha_max, n_alpha, dtype=torch.float32, device=dev)
+    g = torch.linspace(0.0, g_max, n_g, dtype=torch.float32, device=dev)
+    A, G = torch.meshgrid(alpha, g, indexing="ij")
+    n = n_alpha * n_g
+    sig = torch.ones((1, n), dtype=torch.float32, device=dev)
+    media = rw.Media(sig, A.reshape(1, n).contiguous(), G.reshape(1, n).contiguous(),
+                     torch.ones((1, n), dtype=torch.float32, device=dev), n, 1)
+    geom = rw.Geometry(n_media=1, n_rel=n_rel, n_bins=n_bins, r_min_mm=r_min, r_max_mm=r_max)
+    R = torch.empty(n, dtype=torch.float64, device=dev)
+    Pd = torch.empty((n, n_bins), dtype=torch.float32, device=dev)
+    for b in range(0, n, max_units_per_call):
+        e = min(n, b + max_units_per_call)
+        sub = media.unit_range(b, e - b)
+        res = api.forward(ctx, sub, geom, paths, seed, stream=stream)
+        R[b:e] = res.R
+        Pd[b:e] = res.Pd.float()
+    return LUT(alpha, g, R.float().reshape(n_alpha, n_g), Pd.reshape(n_alpha, n_g, n_bins),
+               r_min, r_max, n_rel, paths)
+
+
+def _cell(t: torch.Tensor, n: int):
+    """Cell index i in [0, n - 2] and weight t - i of a continuous grid coordinate
+    t (clamped to [0, n - 1]); the index is clamped as an integer, so i + 1 is
+    always a valid grid index (a float bound such as n - 1 - eps rounds to
+    n - 1 in FP32 for large n)."""
+    t = t.clamp(0.0, float(n - 1))
+    i = t.floor().long().clamp(0, max(n - 2, 0))
+    return i, t - i.to(t.dtype)
+
+
+def _grid_coord(x: torch.Tensor, grid: torch.Tensor):
+    """Index and weight of x on a uniform grid (clamped to its range)."""
+    n = grid.numel()
+    lo, hi = float(grid[0]), float(grid[-1])
+    return _cell((x - lo) / (hi - lo) * (n - 1), n)
+
+
+def lookup_R(lut: LUT, alpha: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+    """Bilinear R(alpha, g)."""
+    ia, wa = _grid_coord(alpha, lut.alpha)
+    ig, wg = _grid_coord(g, lut.g)
+    T = lut.R
+    r00, r01 = T[ia, ig], T[ia, ig + 1]
+    r10, r11 = T[ia + 1, ig], T[ia + 1, ig + 1]
+    return ((1 - wa) * ((1 - wg) * r00 + wg * r01) + wa * ((1 - wg) * r10 + wg * r11))
+
+
+def lookup_P(lut: LUT, alpha: torch.Tensor, g: torch.Tensor, sigma_t: torch.Tensor,
+             r: torch.Tensor) -> torch.Tensor:
+    """Trilinear P(r | alpha, g, sigma_t) = sigma_t^2 P_d(sigma_t r | alpha, g, 1)
+    (eq. separability); alpha, g, sigma_t: [...]; r: [n_r] radii in mm.
+    Returns [..., n_r]."""
+    ia, wa = _grid_coord(alpha, lut.alpha)
+    ig, wg = _grid_coord(g, lut.g)
+    nb = lut.n_bins
+    # bin centres of the table, log-spaced
+    lr_min, lr_max = math.log(lut.r_min), math.log(lut.r_max)
+    step = (lr_max - lr_min) / nb
+    x = torch.log(sigma_t[..., None] * r) - (lr_min + 0.5 * step)   # [..., n_r]
+    tb = x / step
+    # the table covers [r_min, r_max): half a bin beyond the outer centres (with
+    # a rounding margin), held constant there
+    inside = (tb >= -0.5 - 1e-3) & (tb <= nb - 0.5 + 1e-3)
+    ib, wb = _cell(tb, nb)
+    P = lut.Pd
+
+    def corner(da, dg):
+        plane = P[ia + da, ig + dg]             # [..., nb]
+        lo = torch.gather(plane, -1, ib)
+        hi = torch.gather(plane, -1, ib + 1)
+        return (1 - wb) * lo + wb * hi
+
+    wa_, wg_ = wa[..., None], wg[..., None]
+    val = ((1 - wa_) * ((1 - wg_) * corner(0, 0) + wg_ * corner(0, 1)) +
+           wa_ * ((1 - wg_) * corner(1, 0) + wg_ * corner(1, 1)))
+    return torch.where(inside, val, torch.zeros_like(val)) * (sigma_t[..., None] ** 2)
+
+
+def mixture_profile(lut: LUT, sigma_t, albedo, g, w, r):
+    """eq. mixture: R_hat = sum_k w_k R_k and R_d(r) = sum_k w_k R_k P_k(r);
+    parameters [K, n_units].  Returns (R_hat [n], R_d [n, n_r])."""
+    Rk = lookup_R(lut, albedo, g)                          # [K, n]
+    Pk = lookup_P(lut, albedo, g, sigma_t, r)              # [K, n, n_r]
+    R_hat = (w * Rk).sum(0)
+    Rd = ((w * Rk)[..., None] * Pk).sum(0)
+    return R_hat, Rd
+
+
+def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
+        start, r: torch.Tensor, iters: int = 200, lr: float = 1e-2):
+    """Adam over (log sigma_t, logit alpha, logit g / 0.99, two free logits) per
+    unit on eq. joint_loss with the LUT model.  start: (sigma_t, albedo, g, w)
+    [K, n].  Returns the fitted physical parameters and the loss history."""
+    from .fit import Params, joint_loss  # same parameterisation and loss
+
+    P = Params(*start).to(R_t.device)
+    opt = torch.optim.Adam(P.parameters(), lr=lr)
+    hist = []
+    for it in range(iters):
+        opt.zero_grad(set_to_none=True)
+        s, a, gg, lg = P.physical()
+        w = torch.softmax(lg, 0)
+        R_hat, Rd = mixture_profile(lut, s.float(), a.float(), gg.float(), w.float(), r)
+        Pd = Rd / R_hat.clamp_min(1e-12)[:, None]
+        loss_u = joint_loss(R_hat.double(), Pd.double(), R_t, Pd_t, mass_t)
+        loss_u.sum().backward()
+        opt.step()
+        if it == 0 or it == iters - 1 or it % 20 == 0:
+            hist.append((it, float(loss_u.detach().mean())))
+    with torch.no_grad():
+        s, a, gg, lg = P.physical()
+        return (s, a, gg, torch.softmax(lg, 0)), hist
