@@ -89,7 +89,15 @@ typedef struct {
   float rr_weight;      /* roulette threshold (<= 0 disables roulette) */
   float rr_survive;     /* roulette survival probability, (0, 1] */
   int64_t max_vertices; /* per-path vertex cap, 1..2^31 */
+  int32_t incidence;    /* RW_INCIDENCE_NORMAL: pencil beam at r = 0 along the normal
+                           (Sec. 4.1, eq. radsss); RW_INCIDENCE_COSINE: the
+                           cosine-weighted lobe of Sec. 8 at r = 0, with
+                           cos(theta_i) = sqrt(u1), phi = 2 pi u2 of vertex 0,
+                           refracted by Snell's law, weight 1 - F(theta_i) */
 } rw_geometry;
+
+#define RW_INCIDENCE_NORMAL 0
+#define RW_INCIDENCE_COSINE 1
 
 /* Media parameters: DEVICE pointers, SoA [K][n_units] FP32, caller-owned,
  * unit = set * n_wl + wavelength index (the wavelength list of the paper's

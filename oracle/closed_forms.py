@@ -94,6 +94,23 @@ def R_plane(alpha: float) -> float:
     return 1.0 - H_explicit(1.0, alpha) * math.sqrt(1.0 - alpha)
 
 
+def H_moment1(w: float, form: str = "explicit") -> float:
+    """First moment int_0^1 mu H(mu) dmu, by quadrature of either H form."""
+    if form == "explicit":
+        val, _ = integrate.quad(lambda m: m * H_explicit(m, w), 0.0, 1.0, limit=200,
+                                epsabs=1e-13, epsrel=1e-12)
+        return val
+    x, wt = _gauss_legendre_01(400)
+    return float(np.sum(wt * x * H_iterative(x, w)))
+
+
+def R_spherical(alpha: float) -> float:
+    """Total diffuse reflectance under cosine-weighted (diffuse) incidence,
+    isotropic scattering, n = 1: the cosine-weighted average of the plane
+    albedo, 2 int_0^1 mu (1 - H(mu) sqrt(1 - alpha)) dmu."""
+    return 1.0 - 2.0 * math.sqrt(1.0 - alpha) * H_moment1(alpha)
+
+
 def dlnH1_dw(w: float) -> float:
     def f(t):
         return _theta_cot(t) / ((1.0 - w) + w * _one_minus_theta_cot(t))

@@ -43,6 +43,7 @@ class OrcGeometry(ctypes.Structure):
         ("max_vertices", ctypes.c_int64),
         ("analog", ctypes.c_int32),
         ("order_filter", ctypes.c_int32),
+        ("incidence", ctypes.c_int32),
     ]
 
 
@@ -62,12 +63,13 @@ class Geometry:
     max_vertices: int = 1 << 20
     analog: bool = False
     order_filter: int = 0
+    incidence: int = 0  # 0: normal pencil beam; 1: cosine-weighted lobe
 
     def c(self) -> OrcGeometry:
         return OrcGeometry(
             self.n_media, self.n_bins, self.n_rel, self.slab_mm, self.r_min_mm,
             self.r_max_mm, self.rr_weight, self.rr_survive, self.max_vertices,
-            int(self.analog), self.order_filter,
+            int(self.analog), self.order_filter, int(self.incidence),
         )
 
 

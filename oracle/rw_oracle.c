@@ -23,7 +23,9 @@
  * The paper fixes no walk details.  The readings used (written conventions,
  * identical on the GPU side):
  *   - pencil beam at r = 0 along +z (z = depth), path weight starts at
- *     1 - F(0); specular F(0) is not part of R;
+ *     1 - F(0); specular F(0) is not part of R.  Variant (the cosine-weighted
+ *     lobe of Sec. 8): at r = 0, cos(theta_i) = sqrt(u1), phi = 2 pi u2 of
+ *     vertex 0, refracted by Snell's law, weight 1 - F(theta_i);
  *   - medium k = first index with u0 < c_k (c = cumulative weights, c_{K-1}=1);
  *   - free flight s = -ln(u0)/sigma_t;  top hit when uz < 0 and z + s*uz <= 0;
  *   - boundary: unpolarised Fresnel, total internal reflection when
@@ -68,6 +70,7 @@ typedef struct {
   int64_t max_vertices; /* vertex cap per path */
   int32_t analog;       /* 1: analog absorption, unit weights, no roulette */
   int32_t order_filter; /* > 0: tally only paths with this many collisions */
+  int32_t incidence;    /* 0: normal pencil beam; 1: cosine-weighted lobe at r = 0 */
 } orc_geometry;
 
 /* per-unit tally layout of orc_forward: 8 doubles */
@@ -276,7 +279,7 @@ static void walk(const unit_params* up, const orc_geometry* geo,
   memset(res, 0, sizeof(*res));
   res->slot = -1;
 
-  /* vertex 0: medium choice (and the analog specular test) */
+  /* vertex 0: medium choice (and the entry direction and analog specular test) */
   if (!get_block(src, 0, u)) { res->end = END_NO_BLOCKS; return; }
   int k = up->K - 1;
   for (int j = 0; j < up->K; ++j) {
@@ -287,16 +290,34 @@ static void walk(const unit_params* up, const orc_geometry* geo,
 
   double p[3] = {0.0, 0.0, 0.0};
   double d[3] = {0.0, 0.0, 1.0};
+  /* entry: normal incidence transmits 1 - F(0); the cosine-weighted lobe
+   * (Sec. 8, Limitations) draws cos(theta_i) = sqrt(u1), phi = 2 pi u2 outside,
+   * refracts by Snell's law and transmits 1 - F(theta_i), where the Fresnel
+   * reflectance of the entry equals that of the reverse crossing from inside
+   * at the refracted angle */
+  double F_in = F0;
+  if (geo->incidence == 1) {
+    const double sin2_t = (1.0 - u[1]) / (n * n);
+    if (sin2_t >= 1.0) {
+      F_in = 1.0;
+      d[0] = 0.0; d[1] = 0.0; d[2] = 1.0;
+    } else {
+      const double ct = sqrt(1.0 - sin2_t), st = sqrt(sin2_t);
+      const double phi = 2.0 * M_PI * u[2];
+      F_in = fresnel(ct, n);
+      d[0] = st * cos(phi); d[1] = st * sin(phi); d[2] = ct;
+    }
+  }
   double W;
   if (geo->analog) {
-    if (u[1] < F0) {
+    if ((geo->incidence == 1 ? u[3] : u[1]) < F_in) {
       res->end = END_SPECULAR;
       put_event(events, max_events, 0, EV_START, p, d, 0.0);
       return;
     }
     W = 1.0;
   } else {
-    W = 1.0 - F0;
+    W = 1.0 - F_in;
   }
   put_event(events, max_events, 0, EV_START, p, d, W);
 
@@ -568,6 +589,7 @@ static int check_geometry(const orc_geometry* g) {
   if (!(g->r_min_mm > 0.0) || !(g->r_max_mm > g->r_min_mm)) return -1;
   if (!(g->n_rel > 0.0)) return -1;
   if (g->max_vertices < 1) return -1;
+  if (g->incidence != 0 && g->incidence != 1) return -1;
   if (!g->analog && g->rr_weight > 0.0 && !(g->rr_survive > 0.0 && g->rr_survive <= 1.0))
     return -1;
   return 0;

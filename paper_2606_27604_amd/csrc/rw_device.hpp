@@ -136,6 +136,14 @@ __device__ __forceinline__ float fresnel(float ci, float n, float n2) {
   return 0.5f * fmaf(rs, rs, rp * rp);
 }
 
+// The same reflectance from both cosines: ci inside, co outside (Snell pair).
+__device__ __forceinline__ float fresnel_pair(float ci, float co, float n) {
+  const float nci = n * ci, nco = n * co;
+  const float rs = (nci - co) * __builtin_amdgcn_rcpf(nci + co);
+  const float rp = (ci - nco) * __builtin_amdgcn_rcpf(ci + nco);
+  return 0.5f * fmaf(rs, rs, rp * rp);
+}
+
 // Radial slot of an exit radius: 0 below r_min, 1..n_bins, n_bins+1 at/above r_max.
 template <class G>
 __device__ __forceinline__ int radial_slot_r(float r, const G& geo) {
@@ -282,6 +290,27 @@ __device__ __forceinline__ void init_path(Path& p, int k, const Medium& m, float
   p.Sg = 0.0f;
 }
 
+// Entry through a cosine-weighted lobe (Sec. 8): cos(theta_i) = sqrt(u1) and
+// azimuth 2 pi u2 outside, refracted by Snell's law (sin^2 theta_t =
+// sin^2 theta_i / n^2), transmitted weight 1 - F: the Fresnel reflectance of
+// the entry equals that of the reverse crossing from inside at theta_t.  F is
+// taken from the drawn outside cosine sqrt(u1) itself rather than recomputed
+// from theta_t, which near grazing incidence would cost FP32 digits.
+template <class G>
+__device__ __forceinline__ void cosine_entry(Path& p, uint4 w, const G& geo) {
+  const float u1 = u01(w.y), u2 = u01(w.z);
+  const float s2 = (1.0f - u1) * __builtin_amdgcn_rcpf(geo.n_rel2);
+  if (s2 >= 1.0f) {  // no transmitted ray (outside denser than the medium)
+    p.W = 0.0f;
+    return;
+  }
+  const float ct = __builtin_amdgcn_sqrtf(1.0f - s2), st = __builtin_amdgcn_sqrtf(s2);
+  p.W = 1.0f - fresnel_pair(ct, __builtin_amdgcn_sqrtf(u1), geo.n_rel);
+  p.ux = st * __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
+  p.uy = st * __builtin_amdgcn_sinf(u2);
+  p.uz = ct;
+}
+
 // vertex 0: choose the medium from u0 (first k with u0 < cumulative weight)
 template <int K>
 __device__ __forceinline__ void start_path(Path& p, uint4 w, const UnitParams<K>& up,
@@ -298,6 +327,7 @@ __device__ __forceinline__ void start_path(Path& p, uint4 w, const UnitParams<K>
     g = (k == j) ? up.g[j] : g;
   }
   init_path(p, k, make_medium(s, a, g), geo.entry_weight);
+  if (geo.incidence) cosine_entry(p, w, geo);
 }
 
 // The walk kernel keeps the current unit's media in LDS rather than in scalar
@@ -326,7 +356,7 @@ __device__ __forceinline__ void stage_unit(const UnitParams<K>& up, float* tab, 
 
 template <int K>
 __device__ __forceinline__ void start_path_lds(Path& p, uint4 w, const float* tab,
-                                               float entry_weight) {
+                                               float entry_weight, const WalkGeom& geo) {
   const float u0 = u01(w.x);
   int k = 0;
 #pragma unroll
@@ -337,6 +367,7 @@ __device__ __forceinline__ void start_path_lds(Path& p, uint4 w, const float* ta
   m.flight = e0.x; m.alb = e0.y; m.g = e0.z; m.hq = e0.w;
   m.inv_sig = e1.x; m.gq = e1.y; m.gc = e1.z;
   init_path(p, k, m, entry_weight);
+  if (geo.incidence) cosine_entry(p, w, geo);
 }
 
 // vertex v >= 1: flight, then boundary interaction or collision.  Returns the

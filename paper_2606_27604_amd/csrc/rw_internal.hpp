@@ -28,6 +28,7 @@ struct WalkGeom {
   float bin_scale;        // n_bins / log2(r_max / r_min)
   float rr_weight, rr_survive, rr_boost;  // rr_boost = 1 / rr_survive
   uint32_t max_vertices;
+  int32_t incidence;      // 1: cosine-weighted lobe at entry (else normal pencil beam)
 };
 
 // How work items map to (unit, path range).  Item i covers local unit

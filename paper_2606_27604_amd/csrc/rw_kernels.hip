@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
     if (alive) {
       const uint4 w = philox(v, path, a.tag, lctr, ks);
       if (v == 0) {
-        start_path_lds<K>(p, w, L.media, L.cold->entry_weight);
+        start_path_lds<K>(p, w, L.media, L.cold->entry_weight, geo);
         v = 1;
       } else {
         ev = vertex_step<ADJ>(p, w, geo);
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
           const uint4 w = blk[(rank << lg) + s];
           int ev = EV_COLLIDE;
           if (v == 0) {
-            start_path_lds<K>(p, w, L.media, L.cold->entry_weight);
+            start_path_lds<K>(p, w, L.media, L.cold->entry_weight, geo);
             v = 1;
           } else {
             ev = vertex_step<ADJ>(p, w, geo);

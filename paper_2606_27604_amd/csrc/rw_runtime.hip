@@ -100,6 +100,8 @@ rw_status check_geom(rw_context* ctx, const rw_geometry* g) {
     return fail(ctx, RW_E_INVALID, "rr_survive must be in (0, 1]");
   if (g->max_vertices < 1 || g->max_vertices > (int64_t(1) << 31))
     return fail(ctx, RW_E_INVALID, "max_vertices must be in [1, 2^31]");
+  if (g->incidence != RW_INCIDENCE_NORMAL && g->incidence != RW_INCIDENCE_COSINE)
+    return fail(ctx, RW_E_INVALID, "incidence must be RW_INCIDENCE_NORMAL or RW_INCIDENCE_COSINE");
   return RW_OK;
 }
 
@@ -122,6 +124,7 @@ WalkGeom make_geom(const rw_geometry* g) {
   w.rr_survive = g->rr_weight > 0.0f ? g->rr_survive : 1.0f;
   w.rr_boost = float(1.0 / double(w.rr_survive));
   w.max_vertices = uint32_t(std::min<int64_t>(g->max_vertices, int64_t(0xFFFFFFFFu)));
+  w.incidence = g->incidence;
   return w;
 }
 

@@ -43,6 +43,7 @@ class RwGeometryC(ctypes.Structure):
         ("rr_weight", ctypes.c_float),
         ("rr_survive", ctypes.c_float),
         ("max_vertices", ctypes.c_int64),
+        ("incidence", ctypes.c_int32),
     ]
 
 
@@ -153,10 +154,12 @@ class Geometry:
     rr_weight: float = 1e-4
     rr_survive: float = 0.1
     max_vertices: int = 1 << 20
+    incidence: int = 0  # 0: normal pencil beam; 1: cosine-weighted lobe
 
     def c(self) -> RwGeometryC:
         return RwGeometryC(self.n_media, self.n_bins, self.n_rel, self.slab_mm, self.r_min_mm,
-                           self.r_max_mm, self.rr_weight, self.rr_survive, self.max_vertices)
+                           self.r_max_mm, self.rr_weight, self.rr_survive, self.max_vertices,
+                           self.incidence)
 
 
 def _ptr(t) -> int | None:

@@ -35,13 +35,15 @@ def media(sigma_t, albedo, g, w, logits=False):
 
 
 def geoms(K, n_rel, n_bins=256, slab_mm=0.0, r_min=1e-3, r_max=50.0, rr_weight=1e-4,
-          max_vertices=1 << 20):
+          max_vertices=1 << 20, incidence=0):
     g = rw.Geometry(n_media=K, n_rel=n_rel, slab_mm=slab_mm, n_bins=n_bins, r_min_mm=r_min,
-                    r_max_mm=r_max, rr_weight=rr_weight, max_vertices=max_vertices)
+                    r_max_mm=r_max, rr_weight=rr_weight, max_vertices=max_vertices,
+                    incidence=incidence)
     o = O.Geometry(n_media=K, n_rel=float(np.float32(n_rel)), slab_mm=float(np.float32(slab_mm)),
                    n_bins=n_bins, r_min_mm=float(np.float32(r_min)),
                    r_max_mm=float(np.float32(r_max)), rr_weight=float(np.float32(rr_weight)),
-                   rr_survive=float(np.float32(0.1)), max_vertices=max_vertices)
+                   rr_survive=float(np.float32(0.1)), max_vertices=max_vertices,
+                   incidence=incidence)
     return g, o
 
 

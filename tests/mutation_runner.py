@@ -49,7 +49,8 @@ def pieces(rr_exe):
 
 
 ORDER = ["energy", "special", "plane", "beer", "mixture", "single_scatter", "analog", "scale",
-         "brute", "adj_plane", "adj_mixture", "second_moment", "trace"]
+         "brute", "adj_plane", "adj_mixture", "second_moment", "trace", "spherical",
+         "analog_cosine"]
 
 
 def main():

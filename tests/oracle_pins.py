@@ -111,6 +111,36 @@ def check_analog_vs_weighted(paths=1 << 18, seed=5, k=3.0):
               f"R analog={pa:.5f} weighted={mw:.5f} z={z:.2f}; T {pt:.5f}/{mt:.5f}; counts={counts}")
 
 
+def check_spherical_albedo(paths=1 << 18, seed=15, k=3.0):
+    """Cosine-weighted incidence, isotropic scattering, n = 1: R against the
+    spherical albedo 1 - 2 sqrt(1 - alpha) int mu H(mu) dmu."""
+    al = np.array([0.5, 0.8, 0.95, 0.99])
+    geo = O.Geometry(n_media=1, n_rel=1.0, incidence=1)
+    tal, _, _ = O.forward(geo, np.ones(4), al, np.zeros(4), np.ones(4), paths, seed)
+    m, se = mean_se(tal[:, 0], tal[:, 1], paths)
+    ref = np.array([cf.R_spherical(float(a)) for a in al])
+    z = (m - ref) / se
+    return _r(bool(np.all(np.abs(z) <= k)), f"z={np.round(z, 2)}")
+
+
+def check_analog_vs_weighted_cosine(paths=1 << 18, seed=16, k=3.0):
+    """Both estimators under the cosine-weighted lobe with a Fresnel boundary."""
+    n = 1.4
+    base = dict(n_media=1, n_rel=n, slab_mm=3.0, incidence=1)
+    args = ([2.0], [0.95], [0.6], [1.0], paths)
+    ta, _, _ = O.forward(O.Geometry(analog=True, **base), *args, seed)
+    tw, _, _ = O.forward(O.Geometry(**base), *args, seed + 100)
+    pa = ta[0, 0] / paths
+    sa = math.sqrt(pa * (1 - pa) / paths)
+    mw, sw = mean_se(tw[0, 0], tw[0, 1], paths)
+    z = (pa - mw) / math.hypot(sa, sw)
+    spec = ta[0, 4] / paths
+    # the mean entry reflectance of a cosine lobe at n = 1.4 (hemispherical
+    # average of the Fresnel reflectance, about 0.09)
+    return _r(abs(z) <= k and 0.07 < spec < 0.11, f"R analog={pa:.5f} weighted={mw:.5f} "
+              f"z={z:.2f}; specular {spec:.4f}")
+
+
 def check_beer_lambert(paths=1 << 18, seed=6, k=3.0):
     geo = O.Geometry(n_media=1, n_rel=1.0, slab_mm=1.0)
     tal, _, _ = O.forward(geo, [1.3], [0.0], [0.0], [1.0], paths, seed)
@@ -335,4 +365,6 @@ BATTERY_SMALL = [
     ("brute", lambda: check_brute_force_single_scatter(m=32)),
     ("adj_plane", lambda: check_adjoint_plane(paths=1 << 16, k=4.0)),
     ("adj_mixture", lambda: check_adjoint_mixture(paths=1 << 16, k=4.0)),
+    ("spherical", lambda: check_spherical_albedo(paths=1 << 16, k=4.0)),
+    ("analog_cosine", lambda: check_analog_vs_weighted_cosine(paths=1 << 16, k=4.0)),
 ]

@@ -88,3 +88,21 @@ def test_golden_files_regenerate():
         ss = json.load(f)
     for c in ss["cases"]:
         assert abs(cf.R1_total(1.0, c["g"], c["n"]) - c["R1"]) < 1e-12
+
+
+def test_H_first_moment_two_forms_and_spherical_albedo_limits():
+    for w in (0.3, 0.7, 0.95, 0.999):
+        assert abs(cf.H_moment1(w, "explicit") - cf.H_moment1(w, "iterative")) < 1e-10
+    assert abs(cf.R_spherical(1e-9)) < 1e-8          # no scattering: nothing returns
+    assert abs(cf.R_spherical(1.0) - 1.0) < 1e-12     # conservative: everything returns
+    # diffuse light penetrates less deeply than a normal beam: higher albedo
+    for a in (0.5, 0.9, 0.99):
+        assert cf.R_spherical(a) > cf.R_plane(a)
+    # the cosine-weighted mean of the plane albedo over incidence angles
+    import numpy as np
+    x, w = np.polynomial.legendre.leggauss(64)
+    mu = 0.5 * (x + 1.0)
+    for a in (0.6, 0.9):
+        avg = float(np.sum(0.5 * w * 2 * mu * (1 - np.array([cf.H_explicit(m, a) for m in mu])
+                                                     * np.sqrt(1 - a))))
+        assert abs(avg - cf.R_spherical(a)) < 1e-9

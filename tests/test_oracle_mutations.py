@@ -39,7 +39,10 @@ MUTATIONS = [
      "W *= alb;\n      res->absorbed += W * (1.0 - alb);"),
     ("roulette_weight", "W /= geo->rr_survive;", "W *= geo->rr_survive;"),
     ("medium_choice_uncumulated", "if (u[0] < up->cum[j])", "if (u[0] < up->w[j])"),
-    ("entry_fresnel_dropped", "W = 1.0 - F0;", "W = 1.0;"),
+    ("entry_fresnel_dropped", "W = 1.0 - F_in;", "W = 1.0;"),
+    ("cosine_lobe_not_cosine", "(1.0 - u[1]) / (n * n)", "(1.0 - u[1] * u[1]) / (n * n)"),
+    ("cosine_lobe_no_snell", "(1.0 - u[1]) / (n * n)", "(1.0 - u[1])"),
+    ("cosine_entry_fresnel_angle", "F_in = fresnel(ct, n);", "F_in = fresnel(st, n);"),
     ("bin_log_origin", "log(r / g->r_min_mm)", "log(r)"),
     ("exit_radius_component", "sqrt(p[0] * p[0] + p[1] * p[1])", "sqrt(p[0] * p[0] + p[2] * p[2])"),
     ("reflect_wrong_component", "d[2] = -d[2];", "d[0] = -d[0];"),

@@ -59,6 +59,14 @@ def test_analog_and_weighted_estimators_agree():
     _assert(P.check_analog_vs_weighted())
 
 
+def test_spherical_albedo_under_cosine_incidence():
+    _assert(P.check_spherical_albedo())
+
+
+def test_analog_and_weighted_agree_under_cosine_incidence():
+    _assert(P.check_analog_vs_weighted_cosine())
+
+
 def test_beer_lambert():
     _assert(P.check_beer_lambert())
 
