@@ -1,7 +1,7 @@
 """Benchmark of the mixture-of-media random walk on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3] [--no-c4]
-                    [--micro]
+                    [--micro] [--lut N [--lut-photons P]]
 
 One step is one pass of the whole path over the 81-wavelength three-medium
 workload (81 wavelengths 380-780 nm, per-medium sigma_t log-uniform in
@@ -175,6 +175,11 @@ def main():
                     help="also run an elementwise copy of 256 MiB in / 256 MiB out (reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--lut", type=int, default=0,
+                    help="instead of the step benchmark, time the generation of an N x N "
+                         "(alpha, g) lookup table (Sec. 4.2) and print its own JSON line")
+    ap.add_argument("--lut-photons", type=int, default=1 << 14)
+    ap.add_argument("--lut-cells-per-launch", type=int, default=1 << 17)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the walk shards by unit with no communication, and "
@@ -188,6 +193,9 @@ def main():
 
     if args.micro:
         micro(args)
+        return
+    if args.lut:
+        lut_generation(rw, torch, args)
         return
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -418,6 +426,112 @@ def c4(ctx, rw, workloads, torch, args):
             "adjoint_vertices_per_s": v / (adj_ms * 1e-3),
             "forward_vertices_per_s": int(tally.vertices.sum().item()) / (fwd_ms * 1e-3),
             "device_flags": int(flags.item()) | int(tally.flags.item())}
+
+
+def lut_generation(rw, torch, args):
+    """Lookup-table generation (Sec. 4.2): an N x N grid over (alpha, g) at
+    sigma_t = 1, n = 1.4, one K = 1 unit per cell, through the batched forward
+    walk in launches of --lut-cells-per-launch cells.  The paper's table is
+    800 x 800 at 10^6 photons per cell; the time at 10^6 photons is projected
+    linearly from the measured per-photon rate (every photon costs the same in
+    expectation).  The FP64 oracle is timed on 256 seeded random cells."""
+    from paper_2606_27604_amd import lut
+
+    ctx = rw.Context(0)
+    s = torch.cuda.current_stream()
+    N, P = args.lut, args.lut_photons
+    nb, r_min, r_max = lut.LUT_BINS, lut.LUT_R_MIN, lut.LUT_R_MAX
+    # warm-up: a small table (library set-up, graph build)
+    lut.generate(ctx, 8, 8, 1024, n_bins=nb, r_min=r_min, r_max=r_max, stream=s)
+    torch.cuda.synchronize()
+    evs, verts, flags = [], [], []
+
+    def on_batch(b, e, res):
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(s)
+        evs.append(ev)
+        verts.append(res.vertices.sum())
+        flags.append(res.tally.flags)
+        ev.synchronize()  # progress per finished launch (the next one is enqueued after it)
+        print(f"lut: cells {b}..{e} of {N * N} done, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    t0 = time.perf_counter()
+    table = lut.generate(ctx, N, N, P, n_bins=nb, r_min=r_min, r_max=r_max,
+                         max_units_per_call=args.lut_cells_per_launch, stream=s,
+                         on_batch=on_batch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in zip([e0] + evs[:-1], evs)]
+    v = [int(x.item()) for x in verts]
+    fl = 0
+    for f in flags:
+        fl |= rw.rw_check(ctx, f)
+    gpu_s = sum(ms) * 1e-3
+    total_v = sum(v)
+    slots = alg_slots_per_vertex(False)
+    achieved = slots * total_v / gpu_s / 1e12
+    peak = ISSUE_PEAK / 1e12
+    paths = N * N * P
+    out = {
+        "metric": "LUT generation: MC path vertices/s (forward walk, K = 1 per cell)",
+        "value": total_v / gpu_s, "unit": "vertices/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic (uniform alpha/g grid)",
+        "config": {"workload": f"lut-{N}x{N}: alpha in [0, 0.999], g in [0, 0.99], sigma_t = 1, "
+                               f"n = 1.4, {P} photons per cell, {nb} log bins "
+                               f"[{r_min:g}, {r_max:g}] mm",
+                   "cells": N * N, "photons_per_cell": P,
+                   "cells_per_launch": args.lut_cells_per_launch},
+        "seconds": gpu_s, "wall_seconds": wall, "launches": len(ms),
+        "vertices": total_v, "vertices_per_photon": total_v / paths,
+        "photons_per_s": paths / gpu_s,
+        "projected_seconds_800x800_at_1e6_photons": 800 * 800 * 1e6 * (gpu_s / paths),
+        "device_flags": fl,
+        "R_range": [float(table.R.min()), float(table.R.max())],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                     "frac": achieved / peak, "traffic": load_traffic("walk_kernel<1, forward>"),
+                     "kernel": "walk_kernel<1, forward>", "slots_per_vertex": slots},
+    }
+    del table
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = lut_cpu_baseline(N)
+    print(json.dumps(out), flush=True)
+
+
+def lut_cpu_baseline(N, n_cells=256, max_seconds=30.0):
+    """The FP64 oracle on 256 seeded random cells of the same grid, at a photon
+    count doubled from 2^10 until one pass takes 8 s."""
+    from oracle import oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    rng = np.random.default_rng(123)
+    ia, ig = rng.integers(0, N, n_cells), rng.integers(0, N, n_cells)
+    al = np.float32(np.linspace(0.0, 0.999, N, dtype=np.float32)[ia])[None].astype(np.float64)
+    gg = np.float32(np.linspace(0.0, 0.99, N, dtype=np.float32)[ig])[None].astype(np.float64)
+    from paper_2606_27604_amd import lut
+
+    geo = O.Geometry(n_media=1, n_rel=float(np.float32(1.4)), n_bins=lut.LUT_BINS,
+                     r_min_mm=lut.LUT_R_MIN, r_max_mm=lut.LUT_R_MAX)
+    one = np.ones((1, n_cells))
+    paths = 1 << 10
+    while True:
+        t0 = time.perf_counter()
+        _, _, vert = O.forward(geo, one, al, gg, one, paths, 17, n_threads=cores)
+        dt = time.perf_counter() - t0
+        if dt > 8.0 or dt * 2 > max_seconds:
+            break
+        paths *= 2
+    return {"value": float(vert.sum()) / dt, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_cells} random cells of the {N}x{N} grid x {paths} photons, FP64, "
+                      f"{int(vert.sum())} vertices in {dt:.2f} s"}
 
 
 if __name__ == "__main__":

@@ -19,7 +19,8 @@ Targets are the forward model's own R(lambda) and R(r, lambda) for random
 three-medium parameters drawn like the 81-wavelength workload, with 1 %
 relative Gaussian noise on every value.
 
-    python -m paper_2606_27604_amd.fit [--targets 4096] [--iters 200] [--paths 4096] [--lut N]
+    python -m paper_2606_27604_amd.fit [--targets 4096] [--iters 200] [--paths 4096]
+        [--schedule constant|cosine] [--lut N [--lut-paths P] [--lut-init-k1 S]]
 
 prints one JSON line: wall time, loss history, spectral RMSE against the
 noise-free targets and parameter recovery (up to component permutation).
@@ -30,6 +31,7 @@ import argparse
 import itertools
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -57,7 +59,7 @@ def profile_and_R(R_mean: torch.Tensor, bins_mean: torch.Tensor, area: torch.Ten
     return Rr, Pd
 
 
-def joint_loss(R, Pd, R_t, Pd_t, mass_t):
+def joint_loss(R, Pd, R_t, Pd_t, mass_t, lambda_R: float = LAMBDA_R):
     """Per-unit eq. joint_loss: shape RMSE in log space plus lambda_R times the
     squared reflectance error.  With Monte Carlo estimates at a few thousand
     paths, a bin the target barely reaches is empty in most evaluations, and
@@ -70,7 +72,7 @@ def joint_loss(R, Pd, R_t, Pd_t, mass_t):
     d = torch.log(Pd + floor + LOG_EPS) - torch.log(Pd_t + floor + LOG_EPS)
     n = mask.sum(1).clamp_min(1.0)
     shape = torch.sqrt((d * d * mask).sum(1) / n + 1e-30)
-    return shape + LAMBDA_R * (R - R_t) ** 2
+    return shape + lambda_R * (R - R_t) ** 2
 
 
 class Params(torch.nn.Module):
@@ -91,7 +93,7 @@ class Params(torch.nn.Module):
         sigma_t = torch.exp(self.a)
         albedo = torch.sigmoid(self.b)
         g = 0.99 * torch.sigmoid(self.c)
-        logits = torch.cat([self.l, torch.zeros_like(self.l[:1])], 0)
+        logits = torch.cat([self.l, torch.zeros_like(self.a[:1])], 0)
         return sigma_t, albedo, g, logits
 
 
@@ -150,9 +152,14 @@ def recovery(fit, true):
     return {k: float(v) for k, v in errs.items()}
 
 
+def _progress(on: bool, msg: str):
+    if on:
+        print(msg, file=sys.stderr, flush=True)
+
+
 def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_paths: int = 1 << 18,
             lr: float = 1e-2, noise: float = 0.01, seed: int = 5, device: str = "cuda",
-            log_every: int = 0) -> dict:
+            log_every: int = 0, schedule: str = "constant", progress: bool = False) -> dict:
     ctx = rw.Context(torch.device(device).index or 0)
     geom = rw.Geometry(n_media=3, n_rel=1.4, n_bins=workloads.N_BINS,
                        r_min_mm=workloads.R_MIN_MM, r_max_mm=workloads.R_MAX_MM)
@@ -171,6 +178,9 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for it in range(iters):
+        if schedule == "cosine":
+            for grp in opt.param_groups:
+                grp["lr"] = 0.5 * lr * (1.0 + math.cos(math.pi * it / iters))
         opt.zero_grad(set_to_none=True)
         s, a, g, lg = P.physical()
         R, B = api.RWReflectance.apply(s.float(), a.float(), g.float(), lg.float(), ctx, geom,
@@ -182,6 +192,8 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
         opt.step()
         if it == 0 or it == iters - 1 or (log_every and it % log_every == 0):
             hist.append((it, float(loss_u.detach().mean())))
+            _progress(progress, f"mc fit: iteration {it}, mean loss {hist[-1][1]:.4f}, "
+                                f"{time.perf_counter() - t1:.1f} s")
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t1
     # final estimate at the fitted parameters (fresh seed, more paths)
@@ -201,7 +213,7 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
         "workload": f"refit: {n_targets} targets x {n_wl} wavelengths, K=3, n=1.4, "
                     f"{iters} Adam steps (lr {lr}) at {paths} paths per evaluation, "
                     f"targets at {target_paths} paths + {noise:.0%} noise",
-        "units": n_units, "iters": iters, "paths": paths,
+        "units": n_units, "iters": iters, "paths": paths, "schedule": schedule,
         "fit_seconds": t_fit, "target_seconds": t_targets,
         "seconds_per_iteration": t_fit / max(iters, 1),
         "loss_history": hist,
@@ -213,7 +225,8 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
 
 def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_paths: int = 1 << 14,
                 target_paths: int = 1 << 18, lr: float = 1e-2, noise: float = 0.01, seed: int = 5,
-                device: str = "cuda") -> dict:
+                device: str = "cuda", schedule: str = "constant", init_k1_iters: int = 0,
+                progress: bool = False) -> dict:
     """The paper's own fitting route on the same targets as run_fit: tables
     R(alpha, g), P_d(r | alpha, g) from the walk at sigma_t = 1 (lut_n x lut_n
     cells at lut_paths photons), then Adam on eq. joint_loss with the LUT
@@ -230,10 +243,10 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
     tg = make_targets(ctx, geom, *true, target_paths, seed + 1000, noise, device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    table = L.generate(ctx, lut_n, lut_n, lut_paths, n_rel=1.4, n_bins=workloads.N_BINS,
-                       r_min=workloads.R_MIN_MM, r_max=workloads.R_MAX_MM)
+    table = L.generate(ctx, lut_n, lut_n, lut_paths, n_rel=1.4)
     torch.cuda.synchronize()
     t_lut = time.perf_counter() - t0
+    _progress(progress, f"lut fit: table {lut_n}x{lut_n} at {lut_paths} photons in {t_lut:.1f} s")
     nb = workloads.N_BINS
     lr_min, lr_max = math.log(workloads.R_MIN_MM), math.log(workloads.R_MAX_MM)
     step = (lr_max - lr_min) / nb
@@ -241,7 +254,7 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
     start = draw(n_targets, seed + 1, device)
     t1 = time.perf_counter()
     (s, a, g, w), hist = L.fit(table, tg["R_noisy"], tg["Pd_noisy"], tg["mass"], start, r,
-                                iters=iters, lr=lr)
+                                iters=iters, lr=lr, schedule=schedule, init_k1_iters=init_k1_iters)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t1
     with torch.no_grad():
@@ -250,7 +263,9 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
         fin = api.forward(ctx, m, geom, target_paths, seed + 2000)
         rmse = float(torch.sqrt(((fin.R - tg["R"]) ** 2).mean()))
     return {"workload": f"LUT refit: {n_targets} targets x {n_wl} wavelengths, LUT {lut_n}x{lut_n} "
-                        f"at {lut_paths} photons, {iters} Adam steps",
+                        f"at {lut_paths} photons, {iters} Adam steps ({schedule} schedule"
+                        + (f", K = 1 profile start of {init_k1_iters} steps" if init_k1_iters else "")
+                        + ")",
             "lut_seconds": t_lut, "fit_seconds": t_fit, "loss_history": hist,
             "spectral_rmse": rmse, "recovery_median_abs_error": recovery((s, a, g, w), true)}
 
@@ -265,11 +280,16 @@ def main():
     ap.add_argument("--lut", type=int, default=0,
                     help="also run the LUT-based fit with an N x N table on the same targets")
     ap.add_argument("--lut-paths", type=int, default=1 << 14)
+    ap.add_argument("--schedule", choices=("constant", "cosine"), default="constant")
+    ap.add_argument("--lut-init-k1", type=int, default=0,
+                    help="steps of the K = 1 profile-only fit that starts the LUT fit")
     args = ap.parse_args()
-    res = run_fit(args.targets, args.iters, args.paths, args.target_paths, log_every=args.log_every)
+    res = run_fit(args.targets, args.iters, args.paths, args.target_paths, log_every=args.log_every,
+                  schedule=args.schedule, progress=True)
     if args.lut:
         res["lut_fit"] = run_lut_fit(args.targets, args.iters, args.lut, args.lut_paths,
-                                     args.target_paths)
+                                     args.target_paths, schedule=args.schedule,
+                                     init_k1_iters=args.lut_init_k1, progress=True)
     print(json.dumps(res), flush=True)
 
 

@@ -20,7 +20,14 @@ code on the GPU; the tables come from the walk kernel.
 Readings: the grid is uniform in alpha over [0, alpha_max] and in g over
 [0, g_max] (the paper gives the size, not the spacing); radial interpolation is
 linear in log r between bin centres, and P is 0 outside the table's radial
-range (beyond it the table holds only its under/overflow slots).
+range (beyond it the table holds only its under/overflow slots).  Since
+sigma_t rescales the radius, a table evaluated at radii r for extinctions
+sigma_t must cover sigma_t r: the default range [1e-5, 1e5] mm in 512 log bins
+(50 per decade) covers target radii in [1e-3, 50] mm for sigma_t in
+[0.01, 1000] mm^-1, and the far tail of high-albedo, forward-scattering cells
+at sigma_t = 1.  (A table no wider than the targets would put part of every
+profile off the table as soon as sigma_t differs from 1, and the log-shape loss
+would see cliffs there.)
 """
 from __future__ import annotations
 
@@ -48,12 +55,17 @@ class LUT:
         return self.Pd.shape[-1]
 
 
+LUT_BINS, LUT_R_MIN, LUT_R_MAX = 512, 1e-5, 1e5
+
+
 def generate(ctx: rw.Context, n_alpha: int, n_g: int, paths: int, n_rel: float = 1.4,
-             n_bins: int = 256, r_min: float = 1e-3, r_max: float = 50.0,
+             n_bins: int = LUT_BINS, r_min: float = LUT_R_MIN, r_max: float = LUT_R_MAX,
              alpha_max: float = 0.999, g_max: float = 0.99, seed: int = 17,
-             max_units_per_call: int = 1 << 17, stream=None) -> LUT:
+             max_units_per_call: int = 1 << 17, stream=None, on_batch=None) -> LUT:
     """Tables over a uniform (alpha, g) grid at sigma_t = 1, one K = 1 unit per
-    cell, batched forward launches of at most max_units_per_call cells."""
+    cell, batched forward launches of at most max_units_per_call cells.
+    on_batch(begin, end, result), if given, is called after each launch has been
+    enqueued (for progress and timing)."""
     dev = torch.device("cuda")
     alpha = torch.linspace(0.0, alpha_max, n_alpha, dtype=torch.float32, device=dev)
     g = torch.linspace(0.0, g_max, n_g, dtype=torch.float32, device=dev)
@@ -69,6 +81,8 @@ def generate(ctx: rw.Context, n_alpha: int, n_g: int, paths: int, n_rel: float =
         e = min(n, b + max_units_per_call)
         sub = media.unit_range(b, e - b)
         res = api.forward(ctx, sub, geom, paths, seed, stream=stream)
+        if on_batch is not None:
+            on_batch(b, e, res)
         R[b:e] = res.R
         Pd[b:e] = res.Pd.float()
     return LUT(alpha, g, R.float().reshape(n_alpha, n_g), Pd.reshape(n_alpha, n_g, n_bins),
@@ -119,12 +133,15 @@ def lookup_P(lut: LUT, alpha: torch.Tensor, g: torch.Tensor, sigma_t: torch.Tens
     # a rounding margin), held constant there
     inside = (tb >= -0.5 - 1e-3) & (tb <= nb - 0.5 + 1e-3)
     ib, wb = _cell(tb, nb)
-    P = lut.Pd
+    flat = lut.Pd.reshape(-1)
+    ng = lut.g.numel()
 
     def corner(da, dg):
-        plane = P[ia + da, ig + dg]             # [..., nb]
-        lo = torch.gather(plane, -1, ib)
-        hi = torch.gather(plane, -1, ib + 1)
+        # flat index of (alpha cell, g cell, radial cell): only the needed
+        # entries are gathered, never a whole [..., nb] plane per unit
+        base = (((ia + da) * ng + (ig + dg)) * nb)[..., None]
+        lo = flat[base + ib]
+        hi = flat[base + ib + 1]
         return (1 - wb) * lo + wb * hi
 
     wa_, wg_ = wa[..., None], wg[..., None]
@@ -143,27 +160,61 @@ def mixture_profile(lut: LUT, sigma_t, albedo, g, w, r):
     return R_hat, Rd
 
 
-def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
-        start, r: torch.Tensor, iters: int = 200, lr: float = 1e-2):
-    """Adam over (log sigma_t, logit alpha, logit g / 0.99, two free logits) per
-    unit on eq. joint_loss with the LUT model.  start: (sigma_t, albedo, g, w)
-    [K, n].  Returns the fitted physical parameters and the loss history."""
-    from .fit import Params, joint_loss  # same parameterisation and loss
+# Components of the K = 1 initialisation: extinction factors around the K = 1 fit
+K1_SPREAD = (0.5, 1.0, 2.0, 4.0)
 
-    P = Params(*start).to(R_t.device)
+
+def _adam(lut, P, R_t, Pd_t, mass_t, r, iters, lr, schedule, lambda_R, hist, tag):
+    from .fit import joint_loss
+
     opt = torch.optim.Adam(P.parameters(), lr=lr)
-    hist = []
     for it in range(iters):
+        if schedule == "cosine":
+            for grp in opt.param_groups:
+                grp["lr"] = 0.5 * lr * (1.0 + math.cos(math.pi * it / iters))
         opt.zero_grad(set_to_none=True)
         s, a, gg, lg = P.physical()
         w = torch.softmax(lg, 0)
         R_hat, Rd = mixture_profile(lut, s.float(), a.float(), gg.float(), w.float(), r)
         Pd = Rd / R_hat.clamp_min(1e-12)[:, None]
-        loss_u = joint_loss(R_hat.double(), Pd.double(), R_t, Pd_t, mass_t)
+        loss_u = joint_loss(R_hat.double(), Pd.double(), R_t, Pd_t, mass_t, lambda_R=lambda_R)
         loss_u.sum().backward()
         opt.step()
         if it == 0 or it == iters - 1 or it % 20 == 0:
-            hist.append((it, float(loss_u.detach().mean())))
+            hist.append((tag, it, float(loss_u.detach().mean())))
+
+
+def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
+        start, r: torch.Tensor, iters: int = 200, lr: float = 1e-2, schedule: str = "constant",
+        init_k1_iters: int = 0):
+    """Adam over (log sigma_t, logit alpha, logit g / 0.99, K - 1 free logits)
+    per unit on eq. joint_loss with the LUT model (Sec. 4.2, "Optimization").
+
+    start: (sigma_t, albedo, g, w) [K, n], used as given when init_k1_iters = 0.
+    schedule "cosine" anneals the learning rate as 0.5 lr (1 + cos(pi t / T)).
+    init_k1_iters > 0 first fits a single medium to the profile alone (the
+    shape term, lambda_R = 0) from alpha = 0.9, g = 0.5, sigma_t = 1 mm^-1, as
+    the paper initialises its fit; the K components then start at that medium
+    with sigma_t scaled by 0.5, 1, 2 (, 4) and equal weights, since identical
+    components would stay identical under a symmetric loss.
+    Returns the fitted physical parameters and the loss history
+    [(stage, iteration, mean loss)]."""
+    from .fit import LAMBDA_R, Params  # same parameterisation and loss
+
+    dev = R_t.device
+    hist = []
+    if init_k1_iters > 0:
+        K, n = start[0].shape
+        one = torch.ones((1, n), dtype=torch.float64, device=dev)
+        P1 = Params(one, 0.9 * one, 0.5 * one, one).to(dev)
+        _adam(lut, P1, R_t, Pd_t, mass_t, r, init_k1_iters, lr, schedule, 0.0, hist, "k1")
+        with torch.no_grad():
+            s1, a1, g1, _ = P1.physical()
+            f = torch.tensor(K1_SPREAD[:K], dtype=torch.float64, device=dev)[:, None]
+            start = (s1 * f, a1.expand(K, n).clone(), g1.expand(K, n).clone(),
+                     torch.full((K, n), 1.0 / K, dtype=torch.float64, device=dev))
+    P = Params(*start).to(dev)
+    _adam(lut, P, R_t, Pd_t, mass_t, r, iters, lr, schedule, LAMBDA_R, hist, "mix")
     with torch.no_grad():
         s, a, gg, lg = P.physical()
         return (s, a, gg, torch.softmax(lg, 0)), hist

@@ -33,16 +33,18 @@ def test_table_R_matches_plane_albedo_and_separability():
                  torch.full((1, 1), g, device="cuda"), torch.ones((1, 1), device="cuda"), 1, 1)
     geom = rw.Geometry(n_media=1, n_rel=1.0)
     res = api.forward(ctx(), m, geom, 1 << 20, 3)
-    nb = t.n_bins
-    step = (math.log(t.r_max) - math.log(t.r_min)) / nb
-    r = torch.exp(math.log(t.r_min) + (torch.arange(nb, device="cuda", dtype=torch.float32) + 0.5) * step)
+    # the walk's own bins (256 over [1e-3, 50] mm), predicted from the wider table
+    nb = geom.n_bins
+    step = (math.log(geom.r_max_mm) - math.log(geom.r_min_mm)) / nb
+    r = torch.exp(math.log(geom.r_min_mm) +
+                  (torch.arange(nb, device="cuda", dtype=torch.float32) + 0.5) * step)
     pred = lut.lookup_P(t, t.alpha[6:7], t.g[1:2], torch.full((1,), 2.0, device="cuda"), r)[0]
     got = np64(res.Pd[0])
     pr = np64(pred)
     # compare where both sides expect >= 400 exits in the bin (relative noise
     # <= 5 %): mass per bin = P x annulus area (the sigma_t^2 of the rescaling
     # cancels against the area of the scaled annulus)
-    edges = t.r_min * np.exp(np.arange(nb + 1) * step)
+    edges = geom.r_min_mm * np.exp(np.arange(nb + 1) * step)
     area = np.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
     Rw, Rt = float(res.R[0]), float(t.R[6, 1])
     ok = (got * area * Rw * (1 << 20) >= 400) & (pr * area * Rt * N >= 400)
@@ -88,4 +90,10 @@ def test_mixture_one_hot_and_lut_fit_lowers_loss():
         gen.uniform(0.0, 0.9, (K, n)).astype(np.float32),
         gen.dirichlet(np.ones(K), n).T.astype(np.float32).copy())]
     _, hist = lut.fit(t, R_t.double(), Pd_t, mass, start, r, iters=150, lr=2e-2)
-    assert hist[-1][1] < 0.5 * hist[0][1], hist
+    assert hist[-1][2] < 0.5 * hist[0][2], hist
+    # the paper's schedule: K = 1 profile-only start, cosine-annealed Adam
+    _, hist = lut.fit(t, R_t.double(), Pd_t, mass, start, r, iters=150, lr=2e-2,
+                      schedule="cosine", init_k1_iters=60)
+    k1 = [h for h in hist if h[0] == "k1"]
+    mix = [h for h in hist if h[0] == "mix"]
+    assert k1[-1][2] < k1[0][2] and mix[-1][2] < mix[0][2], hist

@@ -60,3 +60,49 @@ def test_trilinear_P_radial_scaling_and_range():
     far = torch.tensor([1e-6, t.r_min, t.r_max * 0.999, 1e3])
     pf = L.lookup_P(t, a, g, torch.ones(1), far)[0]
     assert float(pf[0]) == 0.0 and float(pf[3]) == 0.0 and float(pf[1]) > 0 and float(pf[2]) > 0
+
+
+def _smooth_table(na=64, ng=32, nb=160):
+    """A table with the qualitative behaviour of the real one: R rises with
+    alpha and falls with g, the profile widens with alpha and g and its tail
+    stretches with g.  The table spans [1e-4, 1e3] mm, evaluation radii
+    [1e-2, 20] mm, so sigma_t in [0.1, 50] stays on the table."""
+    alpha = torch.linspace(0.0, 0.999, na, dtype=torch.float64)
+    g = torch.linspace(0.0, 0.99, ng, dtype=torch.float64)
+    R = alpha[:, None] ** 2 * (1.0 - 0.5 * g[None, :])
+    r_min, r_max = 1e-4, 1e3
+    step = (math.log(r_max) - math.log(r_min)) / nb
+    rc = torch.exp(math.log(r_min) + (torch.arange(nb, dtype=torch.float64) + 0.5) * step)
+    width = (0.3 + 2.0 * alpha[:, None, None])
+    p = 1.0 - 0.5 * g[None, :, None]
+    Pd = torch.exp(-(rc[None, None, :] / width) ** p) / (2 * math.pi * width ** 2)
+    r = torch.exp(torch.linspace(math.log(1e-2), math.log(20.0), 48, dtype=torch.float64))
+    return L.LUT(alpha.float(), g.float(), R.float(), Pd.float().contiguous(), r_min, r_max, 1.4,
+                 1), r.float()
+
+
+def test_fit_k1_start_and_cosine_schedule_lower_the_loss():
+    from paper_2606_27604_amd import fit as F
+
+    t, r = _smooth_table()
+    gen = torch.Generator().manual_seed(4)
+    K, n = 3, 16
+    truth = (10 ** (torch.rand((K, n), generator=gen) - 0.5), 0.5 + 0.45 * torch.rand((K, n), generator=gen),
+             0.8 * torch.rand((K, n), generator=gen), torch.full((K, n), 1.0 / K))
+    R_t, Rd_t = L.mixture_profile(t, *truth, r)
+    Pd_t = (Rd_t / R_t[:, None]).double()
+    # annulus areas of the evaluation radii (log-spaced, as the data's bins)
+    lr = torch.log(r.double())
+    h = float(lr[1] - lr[0])
+    edges = torch.exp(torch.cat([lr - 0.5 * h, lr[-1:] + 0.5 * h]))
+    mass = Pd_t * math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    start = tuple(x.clone() for x in truth)
+    (s, a, g, w), hist = L.fit(t, R_t.double(), Pd_t, mass, start, r, iters=80, lr=5e-2,
+                               schedule="cosine", init_k1_iters=40)
+    k1 = [h for h in hist if h[0] == "k1"]
+    mix = [h for h in hist if h[0] == "mix"]
+    assert k1[-1][2] < 0.5 * k1[0][2], hist
+    assert mix[-1][2] < mix[0][2], hist
+    # the K = 1 start ignores the given start: components share alpha and g,
+    # with extinctions in the ratio 0.5 : 1 : 2 before the mixture stage
+    assert s.shape == (K, n) and torch.all(w.sum(0).sub(1.0).abs() < 1e-9)
