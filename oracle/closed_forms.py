@@ -207,3 +207,70 @@ def R1_slots(alpha: float, g: float, n: float, sigma_t: float, n_bins: int, r_mi
 
 def beer_lambert(sigma_t: float, d: float) -> float:
     return math.exp(-sigma_t * d)
+
+
+# --------------------------------------------------------------------------
+# Two-layer tissue (the paper's data-generation geometry, Sec. 3)
+# --------------------------------------------------------------------------
+def exit_cosine_density(mu: float, alpha: float) -> float:
+    """Chandrasekhar's law of diffuse reflection for a semi-infinite isotropic
+    scatterer under normal incidence (ch. IV, mu0 = 1), as a density of the
+    exit cosine: dR/dmu = (alpha/2) mu H(mu) H(1) / (1 + mu).  Its integral over
+    [0, 1] is the plane albedo."""
+    return 0.5 * alpha * mu * H_explicit(mu, alpha) * H_explicit(1.0, alpha) / (1.0 + mu)
+
+
+def R_absorbing_top(alpha: float, tau: float) -> float:
+    """Total reflectance of an isotropic semi-infinite bottom layer (albedo
+    alpha) under a non-scattering absorbing top layer of optical thickness tau,
+    n = 1 everywhere, normal incidence: the beam reaches the bottom with
+    probability e^-tau, and light leaving the bottom at cosine mu crosses the
+    top with e^(-tau/mu) (what collides in the top layer is absorbed):
+    R = e^-tau int_0^1 dR/dmu e^(-tau/mu) dmu."""
+    if tau == 0.0:
+        return R_plane(alpha)
+    val, _ = integrate.quad(lambda m: exit_cosine_density(m, alpha) * math.exp(-tau / m),
+                            0.0, 1.0, limit=200, epsabs=1e-13, epsrel=1e-11)
+    return math.exp(-tau) * val
+
+
+def _stack_at(mu_out: float, n0: float, n1: float):
+    """Top exits R (specular excluded) and bottom exits T of a non-scattering
+    stack outside | top (n0) | bottom (n1) | outside, for light entering at
+    outside cosine mu_out: three parallel interfaces, added incoherently.  The
+    polar angle in each layer follows Snell's law (sin is conserved times n);
+    each interface reflects the same fraction from both sides at conjugate
+    angles (reciprocity), so the adding rule for two interfaces,
+    R_ab = R_a + T_a^2 R_b / (1 - R_a R_b),  T_ab = T_a T_b / (1 - R_a R_b),
+    applies twice."""
+    s2 = 1.0 - mu_out * mu_out
+    c0 = math.sqrt(max(0.0, 1.0 - s2 / (n0 * n0)))       # cosine in the top layer
+    RA = fresnel_hecht(c0, n0)                           # surface
+    RB = fresnel_hecht(c0, n0 / n1)                      # interface, from the top
+    if RB >= 1.0:                                        # total internal reflection
+        RC, c1 = 0.0, 0.0
+    else:
+        c1 = math.sqrt(max(0.0, 1.0 - s2 / (n1 * n1)))   # cosine in the bottom layer
+        RC = fresnel_hecht(c1, n1)                       # bottom face
+    TA, TB, TC = 1.0 - RA, 1.0 - RB, 1.0 - RC
+    # surface + interface, seen from the outside and from the bottom layer
+    den = 1.0 - RA * RB
+    R_ab = RA + TA * TA * RB / den
+    T_ab = TA * TB / den
+    R_ba = RB + TB * TB * RA / den
+    den2 = 1.0 - R_ba * RC
+    R_tot = R_ab + T_ab * T_ab * RC / den2
+    T_tot = T_ab * TC / den2
+    return R_tot - RA, T_tot
+
+
+def stack_RT(n0: float, n1: float, incidence: str = "normal"):
+    """(R, T) of the non-scattering two-layer stack of _stack_at under a normal
+    pencil beam or a cosine-weighted lobe (density 2 mu_out)."""
+    if incidence == "normal":
+        return _stack_at(1.0, n0, n1)
+    R, _ = integrate.quad(lambda m: 2.0 * m * _stack_at(m, n0, n1)[0], 0.0, 1.0, limit=400,
+                          epsabs=1e-13, epsrel=1e-11)
+    T, _ = integrate.quad(lambda m: 2.0 * m * _stack_at(m, n0, n1)[1], 0.0, 1.0, limit=400,
+                          epsabs=1e-13, epsrel=1e-11)
+    return R, T

@@ -7,7 +7,9 @@ and this module never imports the product package.
 The oracle evaluates the random walk of the paper's mixture-of-media model
 (Sec. 4.1, second form of eq. sss: per-path medium choice by weight, then a
 homogeneous walk) in FP64, following the estimator conventions listed at the
-top of ``rw_oracle.c``.
+top of ``rw_oracle.c``; and the same estimator in the two-layer tissue of the
+paper's data generator (Sec. 3: a top layer of given thickness over a
+semi-infinite bottom layer).
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ T_SUMX, T_SUMX2, T_SUMT, T_SUMA, T_SPEC, T_CAPPED, T_KILLED, T_NEXIT = range(8)
 END_EXIT_TOP, END_EXIT_BOTTOM, END_RR_KILLED, END_CAPPED = 1, 2, 3, 4
 END_ABSORBED, END_SPECULAR, END_NO_BLOCKS = 5, 6, 7
 EV_START, EV_COLLIDE, EV_REFLECT, EV_EXIT_TOP, EV_EXIT_BOTTOM = 0, 1, 2, 3, 4
-EV_RR_KILL, EV_CAP, EV_ABSORB = 5, 6, 7
+EV_RR_KILL, EV_CAP, EV_ABSORB, EV_CROSS = 5, 6, 7, 8
 
 
 class OrcGeometry(ctypes.Structure):
@@ -145,6 +147,14 @@ def _bind(L):
     L.orc_trace.argtypes = [gp, dp, dp, dp, dp, u32p, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, dp, dp, dp]
     L.orc_trace.restype = ctypes.c_int
+    L.orc_layered_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64, i64p,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_int, dp, dp, i64p]
+    L.orc_layered_forward.restype = ctypes.c_int
+    L.orc_layered_trace.argtypes = [gp, dp, dp, dp, ctypes.c_double, ctypes.c_double, u32p,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_uint32, dp, dp]
+    L.orc_layered_trace.restype = ctypes.c_int
     L.orc_philox.argtypes = [u32p, u32p, u32p, ctypes.c_int64]
     L.orc_philox.restype = None
     L.orc_u01.argtypes = [ctypes.c_uint32]
@@ -275,6 +285,54 @@ def trace(geo: Geometry, sigma_t, albedo, g, w, words=None, n_paths: int | None 
     if rc != 0:
         raise ValueError(f"orc_trace failed with code {rc}")
     return ev, out, adj
+
+
+def layered_forward(geo: Geometry, sigma_t, albedo, g, thickness, n_bottom: float, paths,
+                    seed: int, tag: int = 0, n_threads: int | None = None, unit_base: int = 0):
+    """Two-layer tissue: raw FP64 sums per unit, as forward().  sigma_t, albedo,
+    g: [2, n_units] (top, bottom layer); thickness: [n_units] top-layer
+    thickness in mm; n_bottom: the bottom layer's index relative to the
+    outside (the top layer's is geo.n_rel).  geo.n_media must be 2."""
+    sigma_t = np.asarray(sigma_t)
+    n_units = sigma_t.size // 2
+    s, a, gg = (_soa(v, 2, n_units) for v in (sigma_t, albedo, g))
+    d = np.ascontiguousarray(np.asarray(thickness, np.float64).reshape(n_units))
+    p = _paths(paths, n_units)
+    tally = np.zeros((n_units, 8))
+    bins = np.zeros((n_units, geo.n_bins + 2, 2))
+    vert = np.zeros(n_units, dtype=np.int64)
+    cg = geo.c()
+    rc = lib().orc_layered_forward(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(d),
+                                   float(n_bottom), n_units, _i64ptr(p), seed, tag, unit_base,
+                                   n_threads or default_threads(), _dptr(tally), _dptr(bins),
+                                   _i64ptr(vert))
+    if rc != 0:
+        raise ValueError(f"orc_layered_forward failed with code {rc}")
+    return tally, bins, vert
+
+
+def layered_trace(geo: Geometry, sigma_t, albedo, g, thickness: float, n_bottom: float,
+                  words=None, n_paths: int | None = None, n_blocks: int = 64, seed: int = 0,
+                  unit: int = 0, tag: int = 0):
+    """Per-path replay of one two-layer unit (parameters of length 2).  Returns
+    (events [n_paths, n_blocks, 8], path_out [n_paths, 8]); path_out[:, 1] is
+    the layer the path ended in."""
+    s, a, gg = (np.ascontiguousarray(np.asarray(v, np.float64).reshape(2))
+                for v in (sigma_t, albedo, g))
+    if words is not None:
+        words = np.ascontiguousarray(np.asarray(words, dtype=np.uint32))
+        n_paths, n_blocks = words.shape[0], words.shape[1]
+    assert n_paths is not None
+    ev = np.zeros((n_paths, n_blocks, 8))
+    out = np.zeros((n_paths, 8))
+    cg = geo.c()
+    rc = lib().orc_layered_trace(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg),
+                                 float(thickness), float(n_bottom),
+                                 _u32ptr(words) if words is not None else None, n_paths, n_blocks,
+                                 seed, unit, tag, _dptr(ev), _dptr(out))
+    if rc != 0:
+        raise ValueError(f"orc_layered_trace failed with code {rc}")
+    return ev, out
 
 
 def philox(counters, key) -> np.ndarray:

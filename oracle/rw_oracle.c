@@ -43,6 +43,11 @@
  * The adjoint uses the score-function (likelihood-ratio) estimator of the
  * path density, evaluated by replaying the same random numbers.
  *
+ * The same estimator also runs in the two-layer tissue of the paper's data
+ * generator (Sec. 3: a top layer of given thickness over a semi-infinite
+ * bottom layer, per-layer sigma_t, albedo, g and refractive index), see
+ * walk_layers() for its readings at the interface.
+ *
  * Everything is FP64.  Threads split the paths of a unit into fixed ranges;
  * partial sums are merged in range order, so results do not depend on the
  * thread count.
@@ -107,7 +112,8 @@ enum {
   EV_EXIT_BOTTOM = 4,
   EV_RR_KILL = 5,
   EV_CAP = 6,
-  EV_ABSORB = 7
+  EV_ABSORB = 7,
+  EV_CROSS = 8        /* two-layer walk: transmitted through the interface */
 };
 
 /* ------------------------------------------------------------------------- */
@@ -205,6 +211,12 @@ static void scatter_dir(double d[3], double mu, double phi) {
   d[0] = nd[0]; d[1] = nd[1]; d[2] = nd[2];
 }
 
+/* specular reflection off a plane z = const */
+static void reflect(double d[3]) { d[2] = -d[2]; }
+
+/* distance of a surface point from the entry point r = 0 */
+static double exit_radius(const double p[3]) { return sqrt(p[0] * p[0] + p[1] * p[1]); }
+
 /* radial slot: 0 underflow, 1..n_bins log bins, n_bins+1 overflow */
 static int bin_slot(double r, const orc_geometry* g) {
   if (!(r >= g->r_min_mm)) return 0;
@@ -269,11 +281,71 @@ static void put_event(double* ev, int64_t max_ev, int64_t idx, int code,
   e[4] = d[0]; e[5] = d[1]; e[6] = d[2]; e[7] = W;
 }
 
+/* Entry at r = 0 through a surface of relative index n, from the words of
+ * vertex 0: normal incidence transmits 1 - F(0); the cosine-weighted lobe
+ * (Sec. 8, Limitations) draws cos(theta_i) = sqrt(u1), phi = 2 pi u2 outside,
+ * refracts by Snell's law and transmits 1 - F(theta_i), where the Fresnel
+ * reflectance of the entry equals that of the reverse crossing from inside at
+ * the refracted angle.  Sets the direction d and the starting weight *W;
+ * returns 1 when the analog estimator reflects the path specularly. */
+static int enter(const orc_geometry* geo, double n, const double u[4], double d[3], double* W) {
+  d[0] = 0.0; d[1] = 0.0; d[2] = 1.0;
+  double F_in = ((n - 1.0) / (n + 1.0)) * ((n - 1.0) / (n + 1.0));
+  if (geo->incidence == 1) {
+    const double sin2_t = (1.0 - u[1]) / (n * n);
+    if (sin2_t >= 1.0) {
+      F_in = 1.0;
+    } else {
+      const double ct = sqrt(1.0 - sin2_t), st = sqrt(sin2_t);
+      const double phi = 2.0 * M_PI * u[2];
+      F_in = fresnel(ct, n);
+      d[0] = st * cos(phi); d[1] = st * sin(phi); d[2] = ct;
+    }
+  }
+  if (geo->analog) {
+    *W = 1.0;
+    return (geo->incidence == 1 ? u[3] : u[1]) < F_in;
+  }
+  *W = 1.0 - F_in;
+  return 0;
+}
+
+/* A collision with a medium of albedo alb and anisotropy g: absorption
+ * (implicit capture with Russian roulette, or the analog survival test), then
+ * Henyey-Greenstein scattering of the direction d.  Returns END_NONE when the
+ * path goes on, else how it ended. */
+static int collide(const orc_geometry* geo, double alb, double g, const double u[4], double d[3],
+                   double* Wp, path_result* res) {
+  double W = *Wp;
+  res->n_coll += 1;
+  if (geo->analog) {
+    if (!(u[3] < alb)) {
+      res->absorbed += 1.0;
+      return END_ABSORBED;
+    }
+  } else {
+    res->absorbed += W * (1.0 - alb);
+    W *= alb;
+    if (geo->rr_weight > 0.0 && W < geo->rr_weight) {
+      if (u[3] < geo->rr_survive) {
+        W /= geo->rr_survive;
+      } else {
+        *Wp = 0.0;
+        return END_RR_KILLED;
+      }
+    }
+  }
+  *Wp = W;
+  double mu = hg_cos(g, u[1]);
+  res->Sg += hg_dlog_dg(g, mu);
+  scatter_dir(d, mu, 2.0 * M_PI * u[2]);
+  return END_NONE;
+}
+
 static void walk(const unit_params* up, const orc_geometry* geo,
                  const block_source* src, path_result* res,
                  double* events, int64_t max_events) {
   const double n = geo->n_rel;
-  const double F0 = ((n - 1.0) / (n + 1.0)) * ((n - 1.0) / (n + 1.0));
   const int slab = geo->slab_mm > 0.0;
   double u[4];
   memset(res, 0, sizeof(*res));
@@ -289,35 +361,12 @@ static void walk(const unit_params* up, const orc_geometry* geo,
   const double sig = up->sigma_t[k], alb = up->albedo[k], g = up->g[k];
 
   double p[3] = {0.0, 0.0, 0.0};
-  double d[3] = {0.0, 0.0, 1.0};
-  /* entry: normal incidence transmits 1 - F(0); the cosine-weighted lobe
-   * (Sec. 8, Limitations) draws cos(theta_i) = sqrt(u1), phi = 2 pi u2 outside,
-   * refracts by Snell's law and transmits 1 - F(theta_i), where the Fresnel
-   * reflectance of the entry equals that of the reverse crossing from inside
-   * at the refracted angle */
-  double F_in = F0;
-  if (geo->incidence == 1) {
-    const double sin2_t = (1.0 - u[1]) / (n * n);
-    if (sin2_t >= 1.0) {
-      F_in = 1.0;
-      d[0] = 0.0; d[1] = 0.0; d[2] = 1.0;
-    } else {
-      const double ct = sqrt(1.0 - sin2_t), st = sqrt(sin2_t);
-      const double phi = 2.0 * M_PI * u[2];
-      F_in = fresnel(ct, n);
-      d[0] = st * cos(phi); d[1] = st * sin(phi); d[2] = ct;
-    }
-  }
+  double d[3];
   double W;
-  if (geo->analog) {
-    if ((geo->incidence == 1 ? u[3] : u[1]) < F_in) {
-      res->end = END_SPECULAR;
-      put_event(events, max_events, 0, EV_START, p, d, 0.0);
-      return;
-    }
-    W = 1.0;
-  } else {
-    W = 1.0 - F_in;
+  if (enter(geo, n, u, d, &W)) {
+    res->end = END_SPECULAR;
+    put_event(events, max_events, 0, EV_START, p, d, 0.0);
+    return;
   }
   put_event(events, max_events, 0, EV_START, p, d, W);
 
@@ -349,14 +398,14 @@ static void walk(const unit_params* up, const orc_geometry* geo,
       p[2] = (hit == 1) ? 0.0 : geo->slab_mm;
       double F = fresnel(fabs(d[2]), n);
       if (u[3] < F) {
-        d[2] = -d[2];
+        reflect(d);
         put_event(events, max_events, v, EV_REFLECT, p, d, W);
         continue;
       }
       res->x = W;
       if (hit == 1) {
         res->end = END_EXIT_TOP;
-        res->r = sqrt(p[0] * p[0] + p[1] * p[1]);
+        res->r = exit_radius(p);
         res->slot = bin_slot(res->r, geo);
         put_event(events, max_events, v, EV_EXIT_TOP, p, d, W);
       } else {
@@ -369,30 +418,131 @@ static void walk(const unit_params* up, const orc_geometry* geo,
     /* collision */
     res->L += s;
     for (int i = 0; i < 3; ++i) p[i] += s * d[i];
-    res->n_coll += 1;
-    if (geo->analog) {
-      if (!(u[3] < alb)) {
-        res->absorbed += 1.0;
-        res->end = END_ABSORBED;
-        put_event(events, max_events, v, EV_ABSORB, p, d, W);
-        return;
-      }
-    } else {
-      res->absorbed += W * (1.0 - alb);
-      W *= alb;
-      if (geo->rr_weight > 0.0 && W < geo->rr_weight) {
-        if (u[3] < geo->rr_survive) {
-          W /= geo->rr_survive;
-        } else {
-          res->end = END_RR_KILLED;
-          put_event(events, max_events, v, EV_RR_KILL, p, d, 0.0);
-          return;
-        }
-      }
+    const int end = collide(geo, alb, g, u, d, &W, res);
+    if (end != END_NONE) {
+      res->end = end;
+      put_event(events, max_events, v, end == END_ABSORBED ? EV_ABSORB : EV_RR_KILL, p, d,
+                end == END_ABSORBED ? W : 0.0);
+      return;
     }
-    double mu = hg_cos(g, u[1]);
-    res->Sg += hg_dlog_dg(g, mu);
-    scatter_dir(d, mu, 2.0 * M_PI * u[2]);
+    put_event(events, max_events, v, EV_COLLIDE, p, d, W);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Two-layer tissue (Sec. 3): a top layer of thickness d over a bottom layer  */
+/* that is semi-infinite (or ends at slab_mm for tests)                        */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double sigma_t[2], albedo[2], g[2]; /* layer 0 = top, 1 = bottom */
+  double d;                           /* top-layer thickness, mm (> 0) */
+  double n[2];                        /* indices relative to the outside */
+} layer_params;
+
+/* The same estimator as walk(), in layers.  Readings (identical on the GPU
+ * side): the path enters the top layer through the surface of index n[0]; a
+ * flight that reaches the interface z = d stops there (a vertex); the
+ * interface reflects with the unpolarised Fresnel reflectance of the relative
+ * index n_from / n_to (u3 < F), else the path crosses, refracted by Snell's
+ * law, and the next flight is drawn afresh in the other layer (the free-flight
+ * distribution is memoryless, so stopping at the interface does not change
+ * the path density).  The bottom layer's lower face (slab tests) has index
+ * n[1] over the outside.  Forward only: no flight lengths are kept for an
+ * adjoint. */
+static void walk_layers(const layer_params* lp, const orc_geometry* geo,
+                        const block_source* src, path_result* res,
+                        double* events, int64_t max_events) {
+  const int slab = geo->slab_mm > 0.0;
+  double u[4];
+  memset(res, 0, sizeof(*res));
+  res->slot = -1;
+  if (!get_block(src, 0, u)) { res->end = END_NO_BLOCKS; return; }
+  double p[3] = {0.0, 0.0, 0.0};
+  double d[3];
+  double W;
+  int layer = 0;
+  res->k = layer;
+  if (enter(geo, lp->n[0], u, d, &W)) {
+    res->end = END_SPECULAR;
+    put_event(events, max_events, 0, EV_START, p, d, 0.0);
+    return;
+  }
+  put_event(events, max_events, 0, EV_START, p, d, W);
+
+  for (int64_t v = 1;; ++v) {
+    if (v > geo->max_vertices) {
+      res->end = END_CAPPED;
+      put_event(events, max_events, v, EV_CAP, p, d, W);
+      return;
+    }
+    if (!get_block(src, v, u)) { res->end = END_NO_BLOCKS; return; }
+    res->n_vert = v;
+    const double flight = -log(u[0]) / lp->sigma_t[layer];
+    const double zn = p[2] + flight * d[2];
+
+    /* which face of the current layer the flight reaches, if any:
+     * 1 top surface, 2 interface, 3 bottom face of a slab */
+    int face = 0;
+    double zf = 0.0;
+    if (layer == 0) {
+      if (d[2] < 0.0 && zn <= 0.0) { face = 1; zf = 0.0; }
+      else if (d[2] > 0.0 && zn >= lp->d) { face = 2; zf = lp->d; }
+    } else {
+      if (d[2] < 0.0 && zn <= lp->d) { face = 2; zf = lp->d; }
+      else if (slab && d[2] > 0.0 && zn >= geo->slab_mm) { face = 3; zf = geo->slab_mm; }
+    }
+
+    if (face) {
+      const double db = (zf - p[2]) / d[2];
+      p[0] += db * d[0];
+      p[1] += db * d[1];
+      p[2] = zf;
+      if (face == 2) {
+        const double rel = lp->n[layer] / lp->n[1 - layer];
+        if (u[3] < fresnel(fabs(d[2]), rel)) {
+          reflect(d);
+          put_event(events, max_events, v, EV_REFLECT, p, d, W);
+          continue;
+        }
+        /* Snell: the tangential components scale by rel, the normal one
+         * keeps its sign */
+        const double sin2_t = rel * rel * (1.0 - d[2] * d[2]);
+        const double ct = sqrt(fmax(0.0, 1.0 - sin2_t));
+        d[0] *= rel;
+        d[1] *= rel;
+        d[2] = d[2] > 0.0 ? ct : -ct;
+        layer = 1 - layer;
+        res->k = layer;
+        put_event(events, max_events, v, EV_CROSS, p, d, W);
+        continue;
+      }
+      const double F = fresnel(fabs(d[2]), lp->n[layer]);
+      if (u[3] < F) {
+        reflect(d);
+        put_event(events, max_events, v, EV_REFLECT, p, d, W);
+        continue;
+      }
+      res->x = W;
+      if (face == 1) {
+        res->end = END_EXIT_TOP;
+        res->r = exit_radius(p);
+        res->slot = bin_slot(res->r, geo);
+        put_event(events, max_events, v, EV_EXIT_TOP, p, d, W);
+      } else {
+        res->end = END_EXIT_BOTTOM;
+        put_event(events, max_events, v, EV_EXIT_BOTTOM, p, d, W);
+      }
+      return;
+    }
+
+    for (int i = 0; i < 3; ++i) p[i] += flight * d[i];
+    const int end = collide(geo, lp->albedo[layer], lp->g[layer], u, d, &W, res);
+    if (end != END_NONE) {
+      res->end = end;
+      put_event(events, max_events, v, end == END_ABSORBED ? EV_ABSORB : EV_RR_KILL, p, d,
+                end == END_ABSORBED ? W : 0.0);
+      return;
+    }
     put_event(events, max_events, v, EV_COLLIDE, p, d, W);
   }
 }
@@ -409,6 +559,11 @@ typedef struct {
   uint64_t seed;
   uint32_t tag;
   uint32_t unit_base; /* counter index of unit 0 (unit u draws as unit_base + u) */
+  /* two-layer walk: thickness[n_units] of the top layer, index of the bottom
+   * layer (the top layer's is geo->n_rel); sigma_t/albedo/g are [2][n_units] */
+  int layered;
+  const double* thickness;
+  double n_bottom;
   /* adjoint inputs (NULL for the forward) */
   int adjoint;
   const double* cot_R;
@@ -448,6 +603,23 @@ static int load_unit(const job_t* job, int64_t u, unit_params* up) {
   return 0;
 }
 
+static int load_layers(const job_t* job, int64_t u, layer_params* lp) {
+  for (int k = 0; k < 2; ++k) {
+    lp->sigma_t[k] = job->sigma_t[(int64_t)k * job->n_units + u];
+    lp->albedo[k] = job->albedo[(int64_t)k * job->n_units + u];
+    lp->g[k] = job->g[(int64_t)k * job->n_units + u];
+    if (!(lp->sigma_t[k] > 0.0) || !(lp->albedo[k] >= 0.0) || !(lp->albedo[k] <= 1.0) ||
+        !(fabs(lp->g[k]) < 1.0))
+      return -1;
+  }
+  lp->d = job->thickness[u];
+  lp->n[0] = job->geo->n_rel;
+  lp->n[1] = job->n_bottom;
+  if (!(lp->d > 0.0) || !(lp->d < 1e30)) return -1;
+  if (job->geo->slab_mm > 0.0 && !(job->geo->slab_mm > lp->d)) return -1;
+  return 0;
+}
+
 /* partial layout per task:
  *   forward: [T_NSLOTS] + bins[(nb+2)*2] + vertices(1)
  *   adjoint: grad[4K] + sumsq[4K] + (jac: jacR[4K] + jacB[(nb+2)*4K])      */
@@ -459,7 +631,8 @@ static void run_task(job_t* job, int64_t t) {
   int64_t u = job->task_unit[t];
   double* part = job->part + t * job->part_len;
   unit_params up;
-  if (load_unit(job, u, &up) != 0) {
+  layer_params lp;
+  if (job->layered ? load_layers(job, u, &lp) != 0 : load_unit(job, u, &up) != 0) {
     pthread_mutex_lock(&job->lock);
     job->status |= 1;
     pthread_mutex_unlock(&job->lock);
@@ -476,7 +649,8 @@ static void run_task(job_t* job, int64_t t) {
   for (int64_t pth = job->task_begin[t]; pth < job->task_end[t]; ++pth) {
     path_result r;
     src.path = (uint32_t)pth;
-    walk(&up, geo, &src, &r, NULL, 0);
+    if (job->layered) walk_layers(&lp, geo, &src, &r, NULL, 0);
+    else walk(&up, geo, &src, &r, NULL, 0);
     int tallied_top = (r.end == END_EXIT_TOP) &&
                       (geo->order_filter <= 0 || r.n_coll == geo->order_filter);
     if (!job->adjoint) {
@@ -727,6 +901,80 @@ int orc_trace(const orc_geometry* geo, const double* sigma_t, const double* albe
       path_adj[p * 2 + 0] = r.L;
       path_adj[p * 2 + 1] = r.Sg;
     }
+  }
+  return 0;
+}
+
+/* Two-layer forward tallies (Sec. 3 geometry), same outputs as orc_forward.
+ * sigma_t/albedo/g: [2][n_units] (top, bottom); thickness: [n_units] top-layer
+ * thickness in mm (> 0, below slab_mm when the bottom is a slab); n_bottom:
+ * index of the bottom layer relative to the outside (the top layer's is
+ * geo->n_rel; geo->n_media must be 2). */
+int orc_layered_forward(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                        const double* g, const double* thickness, double n_bottom,
+                        int64_t n_units, const int64_t* paths, uint64_t seed, uint32_t tag,
+                        uint32_t unit_base, int n_threads, double* tally, double* bins,
+                        int64_t* vertices) {
+  if (check_geometry(geo) || geo->n_media != 2 || !(n_bottom > 0.0) || !sigma_t || !albedo ||
+      !g || !thickness || !paths || n_units < 0 || !tally || !bins || !vertices)
+    return -1;
+  const int nb = geo->n_bins;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = 2;
+  job.layered = 1; job.thickness = thickness; job.n_bottom = n_bottom;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g;
+  job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
+  job.part_len = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
+  int rc = run_job(&job, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(tally, 0, sizeof(double) * (size_t)n_units * T_NSLOTS);
+  memset(bins, 0, sizeof(double) * (size_t)n_units * (size_t)(nb + 2) * 2);
+  for (int64_t u = 0; u < n_units; ++u) vertices[u] = 0;
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    int64_t u = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int i = 0; i < T_NSLOTS; ++i) tally[u * T_NSLOTS + i] += part[i];
+    for (int i = 0; i < (nb + 2) * 2; ++i) bins[u * (nb + 2) * 2 + i] += part[T_NSLOTS + i];
+    vertices[u] += (int64_t)part[T_NSLOTS + (nb + 2) * 2];
+  }
+  free_job(&job);
+  return rc;
+}
+
+/* Per-path replay of one two-layer unit, as orc_trace (path_out[1] is the
+ * layer the path ended in; EV_CROSS marks interface transmissions). */
+int orc_layered_trace(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                      const double* g, double thickness, double n_bottom, const uint32_t* words,
+                      int64_t n_paths, int64_t n_blocks, uint64_t seed, uint32_t unit,
+                      uint32_t tag, double* events, double* path_out) {
+  if (check_geometry(geo) || geo->n_media != 2 || !(n_bottom > 0.0) || !sigma_t || !albedo ||
+      !g || n_paths < 0 || n_blocks < 1 || !path_out)
+    return -1;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = 2; job.n_units = 1;
+  job.layered = 1; job.thickness = &thickness; job.n_bottom = n_bottom;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g;
+  layer_params lp;
+  if (load_layers(&job, 0, &lp) != 0) return -3;
+  if (events) memset(events, 0, sizeof(double) * (size_t)n_paths * (size_t)n_blocks * 8);
+  for (int64_t p = 0; p < n_paths; ++p) {
+    block_source src;
+    memset(&src, 0, sizeof(src));
+    src.key[0] = (uint32_t)seed;
+    src.key[1] = (uint32_t)(seed >> 32);
+    src.path = (uint32_t)p;
+    src.unit = unit;
+    src.tag = tag;
+    src.n_blocks = n_blocks;
+    if (words) src.words = words + p * n_blocks * 4;
+    path_result r;
+    walk_layers(&lp, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks);
+    double* o = path_out + p * 8;
+    o[0] = r.end; o[1] = r.k; o[2] = r.slot; o[3] = r.x; o[4] = r.r;
+    o[5] = (double)r.n_vert; o[6] = (double)r.n_coll; o[7] = r.absorbed;
   }
   return 0;
 }

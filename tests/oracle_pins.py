@@ -23,6 +23,15 @@ What pins what:
                      and common-random-number central differences of the forward
   brute force      - a deterministic grid of injected words averages to the
                      single-scattering closed form
+  two layers       - Beer-Lambert through two absorbing layers; identical
+                     layers and a vanishing top layer reproduce the
+                     plane albedo; an absorbing non-scattering top layer over an
+                     isotropic bottom follows Chandrasekhar's exit law times
+                     e^(-tau/mu); a non-scattering stack follows the incoherent
+                     adding of its three Fresnel interfaces (R and T, normal and
+                     cosine incidence, with and without total internal
+                     reflection at the interface); analog and weighted agree;
+                     traces obey Snell's law at every crossing
 """
 from __future__ import annotations
 
@@ -351,6 +360,141 @@ def check_adjoint_vs_crn_fd(paths=1 << 15, reps=8, seed=13, k=3.5):
     return _r(np.all(np.abs(z) <= k), f"z={np.round(z, 2)}")
 
 
+# ---- two-layer tissue ------------------------------------------------------
+def _layered(geo, top, bot, d, n_bottom, paths, seed, n=1):
+    """top/bot = (sigma_t, albedo, g) of each layer, repeated over n units.
+    Raises when a path hits the vertex cap (these set-ups never come near
+    it), so that a walk that stops making progress fails fast."""
+    s = np.array([[top[0]] * n, [bot[0]] * n], np.float64)
+    a = np.array([[top[1]] * n, [bot[1]] * n], np.float64)
+    g = np.array([[top[2]] * n, [bot[2]] * n], np.float64)
+    geo = O.Geometry(**{**geo.__dict__, "max_vertices": min(geo.max_vertices, 1 << 14)})
+    tal, bins, vert = O.layered_forward(geo, s, a, g, np.full(n, d), n_bottom, paths, seed)
+    if np.any(tal[:, O.T_CAPPED] > 0):
+        raise ValueError("paths reached the vertex cap")
+    return tal, bins, vert
+
+
+def check_two_layer_beer_lambert(paths=1 << 18, seed=25, k=3.0):
+    """Two purely absorbing layers (albedo 0) in a slab, n = 1: the unscattered
+    beam leaves the bottom with probability exp(-sigma_1 d - sigma_2 (L - d))."""
+    geo = O.Geometry(n_media=2, n_rel=1.0, slab_mm=1.0)
+    s1, s2, d = 1.7, 0.6, 0.3
+    tal, _, _ = _layered(geo, (s1, 0.0, 0.0), (s2, 0.0, 0.0), d, 1.0, paths, seed)
+    p = math.exp(-s1 * d - s2 * (1.0 - d))
+    T = tal[0, 2] / paths
+    z = (T - p) / math.sqrt(p * (1 - p) / paths)
+    return _r(abs(z) <= k and tal[0, 0] == 0.0, f"T={T:.5f} vs {p:.5f} z={z:.2f} R={tal[0, 0]}")
+
+
+def check_layers_reduce_to_plane(paths=1 << 18, seed=20, k=3.0):
+    """Two identical isotropic layers, and a top layer too thin to interact
+    (d = 1e-7 mm with other optics), both reproduce 1 - H(1) sqrt(1 - alpha)."""
+    geo = O.Geometry(n_media=2, n_rel=1.0)
+    zs = []
+    for al, top, d in ((0.9, (2.0, 0.9, 0.0), 0.3), (0.7, (5.0, 0.2, 0.8), 1e-7)):
+        tal, _, _ = _layered(geo, top, (2.0, al, 0.0), d, 1.0, paths, seed)
+        m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+        zs.append((m - cf.R_plane(al)) / se)
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
+def check_absorbing_top_layer(paths=1 << 18, seed=21, k=3.0):
+    """Non-scattering absorbing top layer (albedo 0) of optical thickness tau
+    over an isotropic bottom, n = 1: R = e^-tau int dR/dmu e^(-tau/mu) dmu."""
+    geo = O.Geometry(n_media=2, n_rel=1.0)
+    zs = []
+    for tau, al in ((0.2, 0.95), (1.0, 0.8)):
+        d = 0.25
+        tal, _, _ = _layered(geo, (tau / d, 0.0, 0.0), (3.0, al, 0.0), d, 1.0, paths, seed)
+        m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+        zs.append((m - cf.R_absorbing_top(al, tau)) / se)
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
+def check_transparent_stack(paths=1 << 17, seed=22, k=3.5):
+    """Non-scattering stack outside | n0 | n1 | outside (slab bottom): top and
+    bottom exits against the incoherent adding of the three Fresnel
+    interfaces; normal and cosine incidence; n1 < n0 / ... includes total
+    internal reflection at the interface."""
+    zs = []
+    for n0, n1, inc in ((1.4, 1.6, 0), (1.4, 1.3, 1), (1.4, 0.8, 1)):
+        geo = O.Geometry(n_media=2, n_rel=n0, slab_mm=2.0, incidence=inc, rr_weight=0.0)
+        tal, _, _ = _layered(geo, (1e-12, 1.0, 0.0), (1e-12, 1.0, 0.0), 0.7, n1, paths, seed)
+        R_ref, T_ref = cf.stack_RT(n0, n1, "cosine" if inc else "normal")
+        mR, seR = mean_se(tal[0, 0], tal[0, 1], paths)
+        # T: a path leaves the bottom with its entry weight
+        W0 = ((1.0 - ((n0 - 1) / (n0 + 1)) ** 2) if not inc else None)
+        T = tal[0, 2] / paths
+        seT = math.sqrt(max(T * (1 - T), 1e-12) / paths) if inc else \
+            W0 * math.sqrt(max(T / W0 * (1 - T / W0), 1e-12) / paths)
+        zs += [(mR - R_ref) / max(seR, 1e-9), (T - T_ref) / max(seT, 1e-9)]
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
+def check_layers_analog_vs_weighted(paths=1 << 18, seed=23, k=3.0):
+    """Analog and weighted estimators agree on a scattering two-layer slab with
+    an index step at the interface; the analog one conserves energy exactly."""
+    base = dict(n_media=2, n_rel=1.45, slab_mm=2.0)
+    args = ((8.0, 0.7, 0.8), (2.0, 0.97, 0.6), 0.2, 1.35, paths)
+    ta, _, _ = _layered(O.Geometry(analog=True, **base), *args, seed)
+    tw, _, _ = _layered(O.Geometry(**base), *args, seed + 100)
+    pa = ta[0, 0] / paths
+    sa = math.sqrt(pa * (1 - pa) / paths)
+    mw, sw = mean_se(tw[0, 0], tw[0, 1], paths)
+    z = (pa - mw) / math.hypot(sa, sw)
+    energy = ta[0, 0] + ta[0, 2] + ta[0, 3] + ta[0, 4]
+    return _r(abs(z) <= k and energy == paths, f"z={z:.2f} analog energy {energy} of {paths}")
+
+
+def check_layer_trace_invariants(n_paths=3000, seed=24):
+    """Every interface crossing happens at z = d and obeys Snell's law
+    (n_from sin_from = n_to sin_to, azimuth kept, unit direction, the normal
+    component keeps its sign); interface reflections flip uz only; the layer
+    reported at the end matches the last depth."""
+    n0, n1, d = 1.45, 1.3, 0.15
+    geo = O.Geometry(n_media=2, n_rel=n0)
+    ev, out = O.layered_trace(geo, [6.0, 1.5], [0.9, 0.95], [0.7, 0.5], d, n1, n_paths=n_paths,
+                              n_blocks=1024, seed=seed)
+    nv = out[:, 5].astype(np.int64)
+    vidx = np.arange(1, ev.shape[1])[None, :]
+    live = vidx <= nv[:, None]
+    prev, cur = ev[:, :-1][live], ev[:, 1:][live]
+    code = cur[:, 0].astype(int)
+    fails = []
+    cr = code == O.EV_CROSS
+    if not np.all(cur[cr, 3] == d):
+        fails.append("crossing off the interface")
+    down = prev[cr, 6] > 0
+    n_from = np.where(down, n0, n1)
+    n_to = np.where(down, n1, n0)
+    s_from = np.hypot(prev[cr, 4], prev[cr, 5])
+    s_to = np.hypot(cur[cr, 4], cur[cr, 5])
+    if np.any(np.abs(n_from * s_from - n_to * s_to) > 1e-12):
+        fails.append("Snell")
+    if np.any(np.abs(np.arctan2(cur[cr, 5], cur[cr, 4]) - np.arctan2(prev[cr, 5], prev[cr, 4]))
+              > 1e-9 * (s_from > 1e-6)):
+        fails.append("azimuth at crossing")
+    if np.any(np.sign(cur[cr, 6]) != np.sign(prev[cr, 6])):
+        fails.append("crossing reversed")
+    if np.any(np.abs(np.linalg.norm(cur[cr, 4:7], axis=1) - 1.0) > 1e-12):
+        fails.append("direction not unit after crossing")
+    rf = (code == O.EV_REFLECT) & (cur[:, 3] == d)
+    if not (np.array_equal(cur[rf, 4], prev[rf, 4]) and np.array_equal(cur[rf, 6], -prev[rf, 6])):
+        fails.append("interface reflection law")
+    # the layer at the end: a path that ends by an exit or collision at depth z
+    last = ev[np.arange(n_paths), nv]
+    z_end = last[:, 3]
+    ended = out[:, 0] == O.END_RR_KILLED
+    exp_layer = (z_end[ended] > d).astype(float)
+    if not np.array_equal(out[ended, 1], exp_layer):
+        fails.append("layer index")
+    n_cross = int(cr.sum())
+    n_if_refl = int(rf.sum())
+    ok = not fails and n_cross > 100 and n_if_refl > 10
+    return _r(ok, f"fails={fails} crossings={n_cross} interface reflections={n_if_refl}")
+
+
 BATTERY_SMALL = [
     ("plane", lambda: check_plane_albedo(alphas=(0.5, 0.9), paths=1 << 16, k=4.0)),
     ("second_moment", lambda: check_second_moment(paths=1 << 16, k=4.0)),
@@ -367,4 +511,10 @@ BATTERY_SMALL = [
     ("adj_mixture", lambda: check_adjoint_mixture(paths=1 << 16, k=4.0)),
     ("spherical", lambda: check_spherical_albedo(paths=1 << 16, k=4.0)),
     ("analog_cosine", lambda: check_analog_vs_weighted_cosine(paths=1 << 16, k=4.0)),
+    ("layers_beer", lambda: check_two_layer_beer_lambert(paths=1 << 16, k=4.0)),
+    ("layers_plane", lambda: check_layers_reduce_to_plane(paths=1 << 16, k=4.0)),
+    ("layers_absorbing_top", lambda: check_absorbing_top_layer(paths=1 << 16, k=4.0)),
+    ("layers_stack", lambda: check_transparent_stack(paths=1 << 15, k=4.0)),
+    ("layers_analog", lambda: check_layers_analog_vs_weighted(paths=1 << 16, k=4.0)),
+    ("layers_trace", lambda: check_layer_trace_invariants(n_paths=1500)),
 ]

@@ -106,3 +106,28 @@ def test_H_first_moment_two_forms_and_spherical_albedo_limits():
         avg = float(np.sum(0.5 * w * 2 * mu * (1 - np.array([cf.H_explicit(m, a) for m in mu])
                                                      * np.sqrt(1 - a))))
         assert abs(avg - cf.R_spherical(a)) < 1e-9
+
+
+def test_two_layer_closed_forms_limits():
+    # Chandrasekhar's exit law integrates to the plane albedo
+    for a in (0.5, 0.9, 0.99):
+        val, _ = integrate.quad(lambda m: cf.exit_cosine_density(m, a), 0.0, 1.0, limit=200,
+                                epsabs=1e-13)
+        assert abs(val - cf.R_plane(a)) < 1e-10
+    # an absorbing top layer of vanishing thickness changes nothing; a thick one blocks
+    assert abs(cf.R_absorbing_top(0.9, 1e-10) - cf.R_plane(0.9)) < 1e-8
+    assert cf.R_absorbing_top(0.9, 30.0) < 1e-14
+    # stack: index-matched is fully transparent; equal layers are one slab,
+    # T = (1 - F)/(1 + F) at normal incidence; energy R + T + F = 1
+    assert cf.stack_RT(1.0, 1.0) == (0.0, 1.0)
+    F = (0.4 / 2.4) ** 2
+    R, T = cf.stack_RT(1.4, 1.4)
+    assert abs(T - (1 - F) / (1 + F)) < 1e-14 and abs(R + T + F - 1.0) < 1e-14
+    R, T = cf.stack_RT(1.4, 1.7)
+    assert abs(R + T + F - 1.0) < 1e-14
+    # cosine incidence: R + T + the lobe-averaged entry reflectance = 1
+    Fbar, _ = integrate.quad(
+        lambda m: 2 * m * cf.fresnel_hecht(math.sqrt(1 - (1 - m * m) / 1.96), 1.4), 0, 1)
+    for n1 in (1.3, 0.8):
+        R, T = cf.stack_RT(1.4, n1, "cosine")
+        assert abs(R + T + Fbar - 1.0) < 1e-9

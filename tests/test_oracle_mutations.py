@@ -35,11 +35,11 @@ MUTATIONS = [
     ("free_flight_scale", "double s = -log(u[0]) / sig;", "double s = -log(u[0]) * sig;"),
     ("boundary_distance_sign", "db = -p[2] / d[2];", "db = p[2] / d[2];"),
     ("no_absorption", "W *= alb;", "W *= 1.0;"),
-    ("absorbed_after_update", "res->absorbed += W * (1.0 - alb);\n      W *= alb;",
-     "W *= alb;\n      res->absorbed += W * (1.0 - alb);"),
+    ("absorbed_after_update", "res->absorbed += W * (1.0 - alb);\n    W *= alb;",
+     "W *= alb;\n    res->absorbed += W * (1.0 - alb);"),
     ("roulette_weight", "W /= geo->rr_survive;", "W *= geo->rr_survive;"),
     ("medium_choice_uncumulated", "if (u[0] < up->cum[j])", "if (u[0] < up->w[j])"),
-    ("entry_fresnel_dropped", "W = 1.0 - F_in;", "W = 1.0;"),
+    ("entry_fresnel_dropped", "*W = 1.0 - F_in;", "*W = 1.0;"),
     ("cosine_lobe_not_cosine", "(1.0 - u[1]) / (n * n)", "(1.0 - u[1] * u[1]) / (n * n)"),
     ("cosine_lobe_no_snell", "(1.0 - u[1]) / (n * n)", "(1.0 - u[1])"),
     ("cosine_entry_fresnel_angle", "F_in = fresnel(ct, n);", "F_in = fresnel(st, n);"),
@@ -53,6 +53,16 @@ MUTATIONS = [
     ("score_logit_no_baseline", "(j == k ? 1.0 : 0.0) - up.w[j]", "(j == k ? 1.0 : 0.0)"),
     ("boundary_segment_not_counted", "      res->L += db;\n", ""),
     ("hg_score_not_accumulated", "res->Sg += hg_dlog_dg(g, mu);", "res->Sg = hg_dlog_dg(g, mu);"),
+    ("interface_index_inverted", "const double rel = lp->n[layer] / lp->n[1 - layer];",
+     "const double rel = lp->n[1 - layer] / lp->n[layer];"),
+    ("refraction_sign_lost", "d[2] = d[2] > 0.0 ? ct : -ct;", "d[2] = ct;"),
+    ("layer_not_switched", "        layer = 1 - layer;\n", ""),
+    ("bottom_face_top_index", "const double F = fresnel(fabs(d[2]), lp->n[layer]);",
+     "const double F = fresnel(fabs(d[2]), lp->n[0]);"),
+    ("flight_top_sigma", "-log(u[0]) / lp->sigma_t[layer]", "-log(u[0]) / lp->sigma_t[0]"),
+    ("refraction_tangent_unscaled", "        d[1] *= rel;\n", ""),
+    ("interface_missed_upward", "if (d[2] < 0.0 && zn <= lp->d) { face = 2; zf = lp->d; }",
+     "if (d[2] < 0.0 && zn <= 0.0) { face = 2; zf = lp->d; }"),
 ]
 
 

@@ -1,6 +1,7 @@
 """The FP64 oracle's random walk against closed forms, invariants, brute force
 and finite differences (CPU only).  The checks live in tests/oracle_pins.py."""
 import json
+import math
 import os
 
 import numpy as np
@@ -131,3 +132,66 @@ def test_vertex_cap_scores_zero_and_counts():
     _, out, _ = O.trace(geo, [1.0], [1.0], [0.0], [1.0], n_paths=256, n_blocks=8, seed=1)
     capped = out[:, 0] == O.END_CAPPED
     assert capped.any() and np.all(out[capped, 3] == 0.0) and np.all(out[capped, 5] == 3)
+
+
+# ---- two-layer tissue (Sec. 3 geometry) --------------------------------------
+def test_two_layer_beer_lambert():
+    ok, detail = P.check_two_layer_beer_lambert()
+    assert ok, detail
+
+
+def test_layers_reduce_to_plane_albedo():
+    ok, detail = P.check_layers_reduce_to_plane()
+    assert ok, detail
+
+
+def test_absorbing_top_layer_exit_law():
+    ok, detail = P.check_absorbing_top_layer()
+    assert ok, detail
+
+
+def test_transparent_stack_fresnel_adding():
+    ok, detail = P.check_transparent_stack(paths=1 << 19)
+    assert ok, detail
+
+
+def test_layers_analog_vs_weighted_and_energy():
+    ok, detail = P.check_layers_analog_vs_weighted()
+    assert ok, detail
+
+
+def test_layer_trace_invariants():
+    ok, detail = P.check_layer_trace_invariants()
+    assert ok, detail
+
+
+def test_layers_identical_to_homogeneous_with_fresnel():
+    """Identical layers with a Fresnel surface (n = 1.4, g != 0) give the
+    homogeneous walk's R (the interface stops flights but does not change the
+    path density)."""
+    n = 1 << 18
+    geo1 = O.Geometry(n_media=1, n_rel=1.4)
+    t1, _, _ = O.forward(geo1, [2.0], [0.95], [0.8], [1.0], n, 30)
+    geo2 = O.Geometry(n_media=2, n_rel=1.4)
+    t2, _, _ = O.layered_forward(geo2, [[2.0], [2.0]], [[0.95], [0.95]], [[0.8], [0.8]], [0.1],
+                                 1.4, n, 31)
+    m1, s1 = mean_se(t1[0, 0], t1[0, 1], n)
+    m2, s2 = mean_se(t2[0, 0], t2[0, 1], n)
+    assert abs(m1 - m2) <= 3.0 * math.hypot(s1, s2), (m1, m2)
+
+
+def test_layered_invalid_parameters_are_rejected():
+    geo = O.Geometry(n_media=2, n_rel=1.4)
+    good = dict(s=[[1.0], [1.0]], a=[[0.5], [0.5]], g=[[0.0], [0.0]], d=[0.1], nb=1.4)
+    for key, val in (("d", [0.0]), ("d", [float("nan")]), ("s", [[0.0], [1.0]]),
+                     ("a", [[0.5], [1.2]]), ("g", [[0.0], [-1.0]]), ("nb", 0.0)):
+        kw = dict(good)
+        kw[key] = val
+        with pytest.raises(ValueError):
+            O.layered_forward(geo, kw["s"], kw["a"], kw["g"], kw["d"], kw["nb"], 16, 0)
+    with pytest.raises(ValueError):  # the top layer must end above a slab's bottom
+        O.layered_forward(O.Geometry(n_media=2, slab_mm=0.1), good["s"], good["a"], good["g"],
+                          [0.2], 1.4, 16, 0)
+    with pytest.raises(ValueError):  # two layers means n_media = 2
+        O.layered_forward(O.Geometry(n_media=3), good["s"], good["a"], good["g"], [0.1], 1.4,
+                          16, 0)
