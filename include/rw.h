@@ -196,6 +196,36 @@ rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geom
                            double* grad_sumsq, int64_t* vertices, int32_t* flags,
                            const rw_batch_opts* opts, void* stream);
 
+/* Two-layer tissue, the geometry of the paper's data generator (Sec. 3): a
+ * top layer (the epidermis, 50-350 um) of thickness d over a bottom layer that
+ * is semi-infinite (rw_geometry.slab_mm <= 0) or ends at slab_mm (tests), each
+ * with its own sigma_t, albedo and g.  DEVICE pointers, caller-owned, SoA
+ * [2][k_stride] FP32 (row 0 top, row 1 bottom).  The top layer's refractive
+ * index over the outside is rw_geometry.n_rel, the bottom layer's
+ * n_rel_bottom; rw_geometry.n_media must be 2. */
+typedef struct {
+  const float* sigma_t;      /* extinction, mm^-1, > 0 */
+  const float* albedo;       /* [0, 1] */
+  const float* g;            /* (-1, 1) */
+  const float* thickness_mm; /* [k_stride]: top-layer thickness d, 0 < d (< slab_mm) */
+  float n_rel_bottom;        /* bottom layer's index over the outside, > 0 */
+  int64_t n_units;
+  int64_t k_stride;          /* 0 means n_units */
+  int64_t unit_base;         /* random-number counter index of unit 0, as in rw_media */
+} rw_layers;
+
+/* Forward walk through two layers, batched persistent form (options and
+ * outputs as rw_batch_forward; the same exact integer tallies).  The path
+ * enters the top layer through the surface; a flight that reaches the
+ * interface stops there (a vertex), where the path is reflected with the
+ * unpolarised Fresnel reflectance of n_from / n_to or else crosses, refracted
+ * by Snell's law, and draws its next flight in the other layer.  Units whose
+ * layers are invalid (including d <= 0, or d >= slab_mm for a slab) keep zero
+ * tallies and raise RW_FLAG_BAD_PARAMS.  Forward only (no adjoint). */
+rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_geometry* geom,
+                             const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                             rw_tally* out, const rw_batch_opts* opts, void* stream);
+
 /* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
  * path count N (DEVICE int32 paths_per_unit [n_units], or NULL and
  * paths_uniform):
@@ -228,6 +258,13 @@ rw_status rw_debug_trace(rw_context* ctx, const rw_media* media, const rw_geomet
                          const uint32_t* words, int64_t n_paths, int64_t n_blocks, uint64_t seed,
                          uint32_t unit_index, float* events, float* path_out, float* path_adj,
                          void* stream);
+
+/* The same replay for one two-layer unit (layers->n_units == 1); path_out[1]
+ * is the layer the path ended in, event code 8 marks an interface crossing. */
+rw_status rw_debug_trace_layered(rw_context* ctx, const rw_layers* layers,
+                                 const rw_geometry* geom, const uint32_t* words, int64_t n_paths,
+                                 int64_t n_blocks, uint64_t seed, uint32_t unit_index,
+                                 float* events, float* path_out, void* stream);
 
 /* Philox4x32-10 blocks for tests: out[i][0..3] = Philox(ctr[i], key); DEVICE
  * uint32 arrays [n][4]. */

@@ -63,6 +63,15 @@ def forward(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, b
     return finalize(ctx, geom, tally, media.n_units, paths, paths_per_unit, stream=stream)
 
 
+def layered_forward(ctx: Context, layers, geom: Geometry, paths: int, seed: int,
+                    paths_per_unit=None, use_graph: bool = True, stream=None) -> ForwardResult:
+    """Two-layer forward walk (rw_layered_forward) + finalize."""
+    tally = Tally(layers.n_units, geom.n_bins, device=layers.sigma_t.device)
+    rw.rw_layered_forward(ctx, layers, geom, paths_per_unit, paths, seed, tally,
+                          use_graph=use_graph, stream=stream)
+    return finalize(ctx, geom, tally, layers.n_units, paths, paths_per_unit, stream=stream)
+
+
 def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, cot_R=None,
             cot_bins=None, batched: bool = True, paths_per_unit=None, use_graph: bool = True,
             stream=None):

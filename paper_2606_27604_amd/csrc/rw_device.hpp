@@ -258,6 +258,11 @@ struct Path {
   float x, y, z, ux, uy, uz, W, A;
   Medium m;
   int k;
+  // two-layer walk only: the other layer's medium (swapped with m at each
+  // crossing, so a path never needs its unit's table again) and the depth of
+  // the interface
+  Medium m2;
+  float d;
   // adjoint bookkeeping: collisions, D = sum over flights of (1/sigma_t - s)
   // for collisions and (-s) for boundary-terminated flights, which equals
   // n_coll / sigma_t - L without the cancellation of accumulating L; and the
@@ -266,15 +271,24 @@ struct Path {
   float D, Sg;
 };
 
+// Events of a vertex; the codes from EV_EXIT_TOP on end the path.  Traces
+// report them in the oracle's numbering (trace_code).
 enum VertexEvent : int {
   EV_START = 0,
   EV_COLLIDE = 1,
   EV_REFLECT = 2,
-  EV_EXIT_TOP = 3,
-  EV_EXIT_BOTTOM = 4,
-  EV_RR_KILL = 5,
-  EV_CAP = 6
+  EV_CROSS = 3,       // two-layer walk: transmitted through the interface
+  EV_EXIT_TOP = 4,
+  EV_EXIT_BOTTOM = 5,
+  EV_RR_KILL = 6,
+  EV_CAP = 7
 };
+
+__device__ __forceinline__ int trace_code(int ev) {
+  // start, collide, reflect, cross, exit top, exit bottom, roulette, cap
+  constexpr int kOracle[8] = {0, 1, 2, 8, 3, 4, 5, 6};
+  return kOracle[ev];
+}
 
 // vertex 0 after the medium k has been chosen: pencil beam entering at the
 // origin along +z with the transmitted weight 1 - F(0)
@@ -370,6 +384,9 @@ __device__ __forceinline__ void start_path_lds(Path& p, uint4 w, const float* ta
   if (geo.incidence) cosine_entry(p, w, geo);
 }
 
+template <bool ADJ>
+__device__ __forceinline__ int collide(Path& p, uint4 w, const WalkGeom& geo, float s, float zn);
+
 // vertex v >= 1: flight, then boundary interaction or collision.  Returns the
 // vertex event.  ADJ adds the score bookkeeping (collisions, flight length,
 // g score).
@@ -394,6 +411,14 @@ __device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo
     }
     return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
   }
+  return collide<ADJ>(p, w, geo, s, zn);
+}
+
+// Collision at the end of a flight of length s (new depth zn): implicit
+// capture (A += W (1 - alpha), W *= alpha), roulette, Henyey-Greenstein
+// scattering.
+template <bool ADJ>
+__device__ __forceinline__ int collide(Path& p, uint4 w, const WalkGeom& geo, float s, float zn) {
   p.x = fmaf(s, p.ux, p.x);
   p.y = fmaf(s, p.uy, p.y);
   p.z = zn;
@@ -415,6 +440,136 @@ __device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo
   if (ADJ) p.Sg = fmaf((mu - p.m.g) * den, p.m.gq, p.Sg);
   scatter(p.ux, p.uy, p.uz, mu, st, u01(w.z));
   return EV_COLLIDE;
+}
+
+// ---------------------------------------------------------------------------
+// Two-layer tissue (Sec. 3): a top layer of thickness d over a bottom layer
+// that is semi-infinite (or a slab, for tests).  A flight that reaches the
+// interface stops there; the interface reflects with the unpolarised Fresnel
+// reflectance of the relative index n_from / n_to, else the path crosses,
+// refracted by Snell's law, and the next flight is drawn afresh in the other
+// layer (free flights are memoryless).  Forward only.
+// ---------------------------------------------------------------------------
+struct LayerParams {
+  float sigma_t[2], alb[2], g[2];  // top, bottom
+  float d;
+  bool ok;
+};
+
+__device__ __forceinline__ LayerParams load_layers(const WalkArgs& a, int64_t u) {
+  LayerParams p;
+  const int64_t n = a.k_stride;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    p.sigma_t[k] = a.sigma_t[k * n + u];
+    p.alb[k] = a.albedo[k * n + u];
+    p.g[k] = a.g[k * n + u];
+    ok = ok && (p.sigma_t[k] > 0.0f) && (p.sigma_t[k] < 3.0e38f) && (p.alb[k] >= 0.0f) &&
+         (p.alb[k] <= 1.0f) && (fabsf(p.g[k]) < 1.0f);
+  }
+  p.d = a.layer_d[u];
+  ok = ok && (p.d > 0.0f) && (p.d < 3.0e38f) && (!a.geo.slab || p.d < a.geo.slab_mm);
+  p.ok = ok;
+  return p;
+}
+
+// LDS table of a two-layer unit: the two media as in stage_unit, the
+// interface depth in the spare fourth float of each entry's second word.
+__device__ __forceinline__ void stage_layers(const LayerParams& lp, float* tab, int lane) {
+  if (lane < 2) {
+    const float s = lane ? lp.sigma_t[1] : lp.sigma_t[0];
+    const float a = lane ? lp.alb[1] : lp.alb[0];
+    const float g = lane ? lp.g[1] : lp.g[0];
+    const Medium m = make_medium(s, a, g);
+    float4* e = reinterpret_cast<float4*>(tab + lane * kMediumFloats);
+    e[0] = make_float4(m.flight, m.alb, m.g, m.hq);
+    e[1] = make_float4(m.inv_sig, m.gq, m.gc, lp.d);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ Medium medium_from_table(const float* tab, int k, float& d) {
+  const float4* e = reinterpret_cast<const float4*>(tab + k * kMediumFloats);
+  const float4 e0 = e[0], e1 = e[1];
+  Medium m;
+  m.flight = e0.x; m.alb = e0.y; m.g = e0.z; m.hq = e0.w;
+  m.inv_sig = e1.x; m.gq = e1.y; m.gc = e1.z;
+  d = e1.w;
+  return m;
+}
+
+// vertex 0 of a two-layer path: the top layer, entered through the surface
+__device__ __forceinline__ void start_path_layers(Path& p, uint4 w, const float* tab,
+                                                  float entry_weight, const WalkGeom& geo) {
+  float d;
+  const Medium top = medium_from_table(tab, 0, d);
+  p.m2 = medium_from_table(tab, 1, d);
+  p.d = d;
+  init_path(p, 0, top, entry_weight);
+  if (geo.incidence) cosine_entry(p, w, geo);
+}
+
+// the same from parameters in registers (trace kernel)
+__device__ __forceinline__ void start_path_layers(Path& p, uint4 w, const LayerParams& lp,
+                                                  const WalkGeom& geo) {
+  p.m2 = make_medium(lp.sigma_t[1], lp.alb[1], lp.g[1]);
+  p.d = lp.d;
+  init_path(p, 0, make_medium(lp.sigma_t[0], lp.alb[0], lp.g[0]), geo.entry_weight);
+  if (geo.incidence) cosine_entry(p, w, geo);
+}
+
+// vertex v >= 1 of a two-layer path
+__device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkGeom& geo) {
+  const float s = -__builtin_amdgcn_logf(u01(w.x)) * p.m.flight;
+  const float zn = fmaf(s, p.uz, p.z);
+  const bool top_layer = p.k == 0;
+  // the face of the current layer this flight reaches: 1 surface, 2 interface,
+  // 3 the bottom of a slab
+  int face = 0;
+  if (top_layer) {
+    if (p.uz < 0.0f && zn <= 0.0f) face = 1;
+    else if (p.uz > 0.0f && zn >= p.d) face = 2;
+  } else {
+    if (p.uz < 0.0f && zn <= p.d) face = 2;
+    else if (geo.slab && p.uz > 0.0f && zn >= geo.slab_mm) face = 3;
+  }
+  if (face == 0) return collide<false>(p, w, geo, s, zn);
+  const float zf = face == 1 ? 0.0f : (face == 2 ? p.d : geo.slab_mm);
+  const float db = (zf - p.z) * __builtin_amdgcn_rcpf(p.uz);
+  p.x = fmaf(db, p.ux, p.x);
+  p.y = fmaf(db, p.uy, p.y);
+  p.z = zf;
+  if (face == 2) {
+    if (!geo.interface_matched) {
+      const float rel = top_layer ? geo.rel_down : geo.rel_up;
+      const float rel2 = top_layer ? geo.rel_down2 : geo.rel_up2;
+      if (u01(w.w) < fresnel(fabsf(p.uz), rel, rel2)) {
+        p.uz = -p.uz;
+        return EV_REFLECT;
+      }
+      // Snell: tangential components scale by rel, the normal one keeps its sign
+      const float ct = __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-rel2, fmaf(-p.uz, p.uz, 1.0f), 1.0f)));
+      p.ux *= rel;
+      p.uy *= rel;
+      p.uz = p.uz > 0.0f ? ct : -ct;
+    }
+    const Medium other = p.m2;
+    p.m2 = p.m;
+    p.m = other;
+    p.k ^= 1;
+    return EV_CROSS;
+  }
+  const bool top = face == 1;
+  if (!(top ? geo.index_matched : geo.bot_matched)) {
+    const float F = top ? fresnel(fabsf(p.uz), geo.n_rel, geo.n_rel2)
+                        : fresnel(fabsf(p.uz), geo.n_bot, geo.n_bot2);
+    if (u01(w.w) < F) {
+      p.uz = -p.uz;
+      return EV_REFLECT;
+    }
+  }
+  return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
 }
 
 }  // namespace rw

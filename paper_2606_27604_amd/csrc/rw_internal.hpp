@@ -8,6 +8,9 @@
 namespace rw {
 
 constexpr int kMaxMedia = 4;
+// model id of the two-layer walk in the launch switches (which otherwise take
+// the media count K of the mixture walk)
+constexpr int kLayeredModel = 16;
 constexpr int kWave = 64;
 constexpr uint32_t kForwardTag = 0;  // Philox stream tag shared by forward and adjoint replay
 // LDS table of the walk kernel's current unit: per medium 8 floats, then the
@@ -29,6 +32,12 @@ struct WalkGeom {
   float rr_weight, rr_survive, rr_boost;  // rr_boost = 1 / rr_survive
   uint32_t max_vertices;
   int32_t incidence;      // 1: cosine-weighted lobe at entry (else normal pencil beam)
+  // two-layer walk: the bottom layer's index over the outside (its slab face),
+  // the relative indices of the interface seen from the top (down) and from
+  // the bottom (up), and which faces are index-matched
+  float n_bot, n_bot2;
+  float rel_down, rel_down2, rel_up, rel_up2;
+  int32_t bot_matched, interface_matched;
 };
 
 // How work items map to (unit, path range).  Item i covers local unit
@@ -53,6 +62,7 @@ struct WalkArgs {
   const float* albedo;
   const float* g;
   const float* weight;
+  const float* layer_d;        // two-layer walk: top-layer thickness [k_stride], mm
   int32_t weights_are_logits;
   int64_t k_stride;            // elements between consecutive media in the SoA arrays
   uint32_t unit_base;          // counter index of unit 0 of the call

@@ -302,8 +302,43 @@ __device__ __forceinline__ void flush_unit(const WalkArgs& a, const WaveLds& L, 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-template <int K, bool ADJ>
+// The two walk variants behind one kernel: the mixture of K media (LAYERED
+// false) and the two-layer tissue (forward only).
+template <int K, bool LAYERED>
+__device__ __forceinline__ void start_any(Path& p, uint4 w, const float* tab, float entry_weight,
+                                          const WalkGeom& geo) {
+  if constexpr (LAYERED) start_path_layers(p, w, tab, entry_weight, geo);
+  else start_path_lds<K>(p, w, tab, entry_weight, geo);
+}
+
+template <bool ADJ, bool LAYERED>
+__device__ __forceinline__ int step_any(Path& p, uint4 w, const WalkGeom& geo) {
+  if constexpr (LAYERED) return vertex_step_layered(p, w, geo);
+  else return vertex_step<ADJ>(p, w, geo);
+}
+
+// Load, validate and stage the parameters of unit u; an invalid unit raises
+// the flag and returns false.  (The flag store sits in the else branch of the
+// staging: testing the returned value again at the call site cost the mixture
+// kernel 11-15 VGPRs and a wave of occupancy.)
+template <int K, bool LAYERED>
+__device__ __forceinline__ bool stage_any(const WalkArgs& a, int64_t u, float* tab, int lane) {
+  if constexpr (LAYERED) {
+    const LayerParams lp = load_layers(a, u);
+    if (lp.ok) stage_layers(lp, tab, lane);
+    else if (lane == 0) atomicOr(a.flags, RW_FLAG_BAD_PARAMS);
+    return lp.ok;
+  } else {
+    const UnitParams<K> up = load_unit<K>(a, u);
+    if (up.ok) stage_unit<K>(up, tab, lane);
+    else if (lane == 0) atomicOr(a.flags, RW_FLAG_BAD_PARAMS);
+    return up.ok;
+  }
+}
+
+template <int K, bool ADJ, bool LAYERED>
 __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
+  static_assert(!(ADJ && LAYERED), "the two-layer walk is forward only");
   extern __shared__ u64 lds[];
   const int lane = lane_id();
   // the wave index is uniform; say so, or every schedule value derived from it
@@ -324,7 +359,15 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-  const WalkGeom geo = step_geom_in_vgprs(a.geo);
+  WalkGeom geo = step_geom_in_vgprs(a.geo);
+  if constexpr (LAYERED) {
+    geo.rel_down = in_vgpr(a.geo.rel_down);
+    geo.rel_down2 = in_vgpr(a.geo.rel_down2);
+    geo.rel_up = in_vgpr(a.geo.rel_up);
+    geo.rel_up2 = in_vgpr(a.geo.rel_up2);
+    geo.n_bot = in_vgpr(a.geo.n_bot);
+    geo.n_bot2 = in_vgpr(a.geo.n_bot2);
+  }
 
   // wave-uniform schedule state: the current item's next path index and end,
   // the unit whose parameters are staged and whose sums sit in LDS, the slot
@@ -359,12 +402,9 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
           const int64_t u = a.map.unit_begin + ul;
           if (u != u_cur) {
             if (u_cur >= 0) flush_unit<K, ADJ>(a, L, head, tail, cur_slot, u_cur, lane);
-            const UnitParams<K> up = load_unit<K>(a, u);
             u_cur = u;
             cur_slot = (!ADJ && a.direct) ? u : item;
-            unit_ok = up.ok;
-            if (unit_ok) stage_unit<K>(up, L.media, lane);
-            else if (lane == 0) atomicOr(a.flags, RW_FLAG_BAD_PARAMS);
+            unit_ok = stage_any<K, LAYERED>(a, u, L.media, lane);
           }
           if (!unit_ok) continue;  // an invalid unit keeps zero tallies
           cursor = uint32_t(pb);
@@ -409,10 +449,10 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
     if (alive) {
       const uint4 w = philox(v, path, a.tag, lctr, ks);
       if (v == 0) {
-        start_path_lds<K>(p, w, L.media, L.cold->entry_weight, geo);
+        start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
         v = 1;
       } else {
-        ev = vertex_step<ADJ>(p, w, geo);
+        ev = step_any<ADJ, LAYERED>(p, w, geo);
         if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
           ev = EV_CAP;
           capped = true;
@@ -492,10 +532,10 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
           const uint4 w = blk[(rank << lg) + s];
           int ev = EV_COLLIDE;
           if (v == 0) {
-            start_path_lds<K>(p, w, L.media, L.cold->entry_weight, geo);
+            start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
             v = 1;
           } else {
-            ev = vertex_step<ADJ>(p, w, geo);
+            ev = step_any<ADJ, LAYERED>(p, w, geo);
             if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
               ev = EV_CAP;
               capped = true;
@@ -648,6 +688,14 @@ __device__ __forceinline__ float est_path_vertices(float alb, float g, const Wal
   return 2.0f + fminf(n_rr, 5.0f * sqrtf(n_rr / fmaxf(1.0f - g, 1e-3f)));
 }
 
+__device__ __forceinline__ void put_bucket(int64_t ul, float c, int32_t* bucket, uint32_t* hist) {
+  int b = int(4.0f * __log2f(c + 1.0f));
+  b = b < 0 ? 0 : (b > kOrderBuckets - 1 ? kOrderBuckets - 1 : b);
+  b = kOrderBuckets - 1 - b;  // descending cost
+  bucket[ul] = b;
+  atomicAdd(&hist[b], 1u);
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) unit_cost_kernel(const WalkArgs a, int32_t* bucket,
                                                         uint32_t* hist) {
@@ -660,11 +708,17 @@ __global__ void __launch_bounds__(256) unit_cost_kernel(const WalkArgs a, int32_
 #pragma unroll
     for (int k = 0; k < K; ++k) c += up.w[k] * est_path_vertices(up.alb[k], up.g[k], a.geo);
   }
-  int b = int(4.0f * __log2f(c + 1.0f));
-  b = b < 0 ? 0 : (b > kOrderBuckets - 1 ? kOrderBuckets - 1 : b);
-  b = kOrderBuckets - 1 - b;  // descending cost
-  bucket[ul] = b;
-  atomicAdd(&hist[b], 1u);
+  put_bucket(ul, c, bucket, hist);
+}
+
+// two-layer units: a path spends most of its vertices in the bottom layer
+__global__ void __launch_bounds__(256) unit_cost_layered_kernel(const WalkArgs a, int32_t* bucket,
+                                                                uint32_t* hist) {
+  const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (ul >= a.map.n_units) return;
+  const LayerParams lp = load_layers(a, a.map.unit_begin + ul);
+  const float c = lp.ok ? est_path_vertices(lp.alb[1], lp.g[1], a.geo) : 1.0f;
+  put_bucket(ul, c, bucket, hist);
 }
 
 // exclusive prefix of the bucket counts, in place (one wave)
@@ -738,25 +792,25 @@ __global__ void finalize_kernel(const WalkGeom geo, int64_t n_units, const int32
 }
 
 // Per-path replay (tests): one thread per path, same steps as the walk kernel.
-template <int K>
+// Event codes are written in the oracle's numbering.
+template <int K, bool LAYERED>
 __global__ void trace_kernel(const WalkArgs a, const uint32_t* words, int64_t n_paths,
                              int64_t n_blocks, uint32_t unit_index, float* events, float* path_out,
                              float* path_adj) {
   const int64_t pth = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (pth >= n_paths) return;
   const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-  const UnitParams<K> up = load_unit<K>(a, 0);
   const WalkGeom& geo = a.geo;
   float* ev = events ? events + pth * n_blocks * 8 : nullptr;
   Path p;
   int end = 7, slot = -1;
-  uint32_t nvert = 0;
+  uint32_t nvert = 0, ncoll = 0;  // the two-layer step keeps no collision count
   for (int64_t v = 0; v < n_blocks; ++v) {
     if (v > 0 && v > int64_t(geo.max_vertices)) {
       end = 4;
       if (ev) {
         float* e = ev + v * 8;
-        e[0] = EV_CAP; e[1] = p.x; e[2] = p.y; e[3] = p.z;
+        e[0] = float(trace_code(EV_CAP)); e[1] = p.x; e[2] = p.y; e[3] = p.z;
         e[4] = p.ux; e[5] = p.uy; e[6] = p.uz; e[7] = p.W;
       }
       break;
@@ -770,15 +824,18 @@ __global__ void trace_kernel(const WalkArgs a, const uint32_t* words, int64_t n_
     }
     int code;
     if (v == 0) {
-      start_path<K>(p, w, up, geo);
+      if constexpr (LAYERED) start_path_layers(p, w, load_layers(a, 0), geo);
+      else start_path<K>(p, w, load_unit<K>(a, 0), geo);
       code = EV_START;
     } else {
       nvert = uint32_t(v);
-      code = vertex_step<true>(p, w, geo);
+      if constexpr (LAYERED) code = vertex_step_layered(p, w, geo);
+      else code = vertex_step<true>(p, w, geo);
+      if (code == EV_COLLIDE || code == EV_RR_KILL) ++ncoll;
     }
     if (ev) {
       float* e = ev + v * 8;
-      e[0] = float(code); e[1] = p.x; e[2] = p.y; e[3] = p.z;
+      e[0] = float(trace_code(code)); e[1] = p.x; e[2] = p.y; e[3] = p.z;
       e[4] = p.ux; e[5] = p.uy; e[6] = p.uz; e[7] = code == EV_RR_KILL ? 0.0f : p.W;
     }
     if (code == EV_EXIT_TOP) { end = 1; slot = radial_slot(p.x, p.y, geo); break; }
@@ -792,9 +849,9 @@ __global__ void trace_kernel(const WalkArgs a, const uint32_t* words, int64_t n_
   o[3] = (end == 1 || end == 2) ? p.W : 0.0f;
   o[4] = end == 1 ? __builtin_amdgcn_sqrtf(fmaf(p.x, p.x, p.y * p.y)) : 0.0f;
   o[5] = float(nvert);
-  o[6] = float(p.ncoll);
+  o[6] = float(ncoll);
   o[7] = p.A;
-  if (path_adj) {
+  if (!LAYERED && path_adj) {
     path_adj[pth * 2 + 0] = p.D;
     path_adj[pth * 2 + 1] = fmaf(float(p.ncoll), p.m.gc, p.Sg);
   }
@@ -824,9 +881,11 @@ static hipError_t launch_walk_k(const WalkArgs& a, bool adjoint, int waves_per_w
                                 hipStream_t s) {
   const size_t lds = size_t(walk_lds_bytes(a, waves_per_wg));
   if (adjoint)
-    hipLaunchKernelGGL((walk_kernel<K, true>), dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
+    hipLaunchKernelGGL((walk_kernel<K, true, false>), dim3(grid), dim3(waves_per_wg * kWave), lds,
+                       s, a);
   else
-    hipLaunchKernelGGL((walk_kernel<K, false>), dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
+    hipLaunchKernelGGL((walk_kernel<K, false, false>), dim3(grid), dim3(waves_per_wg * kWave), lds,
+                       s, a);
   return hipGetLastError();
 }
 
@@ -837,16 +896,22 @@ hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg,
     case 2: return launch_walk_k<2>(a, adjoint, waves_per_wg, grid_wgs, stream);
     case 3: return launch_walk_k<3>(a, adjoint, waves_per_wg, grid_wgs, stream);
     case 4: return launch_walk_k<4>(a, adjoint, waves_per_wg, grid_wgs, stream);
+    case kLayeredModel:
+      if (adjoint) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((walk_kernel<2, false, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
+                         size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
+      return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
 }
 
 const void* walk_kernel_ptr(int K, bool adjoint) {
   switch (K) {
-    case 1: return adjoint ? (const void*)walk_kernel<1, true> : (const void*)walk_kernel<1, false>;
-    case 2: return adjoint ? (const void*)walk_kernel<2, true> : (const void*)walk_kernel<2, false>;
-    case 3: return adjoint ? (const void*)walk_kernel<3, true> : (const void*)walk_kernel<3, false>;
-    case 4: return adjoint ? (const void*)walk_kernel<4, true> : (const void*)walk_kernel<4, false>;
+    case 1: return adjoint ? (const void*)walk_kernel<1, true, false> : (const void*)walk_kernel<1, false, false>;
+    case 2: return adjoint ? (const void*)walk_kernel<2, true, false> : (const void*)walk_kernel<2, false, false>;
+    case 3: return adjoint ? (const void*)walk_kernel<3, true, false> : (const void*)walk_kernel<3, false, false>;
+    case 4: return adjoint ? (const void*)walk_kernel<4, true, false> : (const void*)walk_kernel<4, false, false>;
+    case kLayeredModel: return adjoint ? nullptr : (const void*)walk_kernel<2, false, true>;
     default: return nullptr;
   }
 }
@@ -855,6 +920,7 @@ const void* fill_u32_kernel_ptr() { return (const void*)fill_u32_kernel; }
 const void* fill_u64_kernel_ptr() { return (const void*)fill_u64_kernel; }
 const void* unit_cost_kernel_ptr(int K) {
   switch (K) {
+    case kLayeredModel: return (const void*)unit_cost_layered_kernel;
     case 1: return (const void*)unit_cost_kernel<1>;
     case 2: return (const void*)unit_cost_kernel<2>;
     case 3: return (const void*)unit_cost_kernel<3>;
@@ -885,6 +951,7 @@ hipError_t launch_unit_order(const WalkArgs& a, int K, int32_t* bucket, uint32_t
     case 2: hipLaunchKernelGGL(unit_cost_kernel<2>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
     case 3: hipLaunchKernelGGL(unit_cost_kernel<3>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
     case 4: hipLaunchKernelGGL(unit_cost_kernel<4>, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
+    case kLayeredModel: hipLaunchKernelGGL(unit_cost_layered_kernel, dim3(grid), dim3(256), 0, s, a, bucket, hist); break;
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist);
@@ -947,10 +1014,11 @@ hipError_t launch_trace(const WalkArgs& a, int K, const uint32_t* words, int64_t
                         float* path_adj, hipStream_t s) {
   const unsigned grid = unsigned((n_paths + 63) / 64);
   switch (K) {
-    case 1: hipLaunchKernelGGL(trace_kernel<1>, dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
-    case 2: hipLaunchKernelGGL(trace_kernel<2>, dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
-    case 3: hipLaunchKernelGGL(trace_kernel<3>, dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
-    case 4: hipLaunchKernelGGL(trace_kernel<4>, dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
+    case 1: hipLaunchKernelGGL((trace_kernel<1, false>), dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
+    case 2: hipLaunchKernelGGL((trace_kernel<2, false>), dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
+    case 3: hipLaunchKernelGGL((trace_kernel<3, false>), dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
+    case 4: hipLaunchKernelGGL((trace_kernel<4, false>), dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, path_adj); break;
+    case kLayeredModel: hipLaunchKernelGGL((trace_kernel<2, true>), dim3(grid), dim3(64), 0, s, a, words, n_paths, n_blocks, unit_index, events, path_out, nullptr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

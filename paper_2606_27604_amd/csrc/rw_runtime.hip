@@ -105,6 +105,19 @@ rw_status check_geom(rw_context* ctx, const rw_geometry* g) {
   return RW_OK;
 }
 
+// Indices of the two-layer walk: bottom layer n_bot over the outside, the
+// interface n_rel / n_bot seen from the top and n_bot / n_rel from the bottom.
+void set_bottom_index(WalkGeom& w, float n_bot) {
+  w.n_bot = n_bot;
+  w.n_bot2 = n_bot * n_bot;
+  w.bot_matched = n_bot == 1.0f;
+  w.interface_matched = n_bot == w.n_rel;
+  w.rel_down = float(double(w.n_rel) / double(n_bot));
+  w.rel_down2 = w.rel_down * w.rel_down;
+  w.rel_up = float(double(n_bot) / double(w.n_rel));
+  w.rel_up2 = w.rel_up * w.rel_up;
+}
+
 WalkGeom make_geom(const rw_geometry* g) {
   WalkGeom w{};
   w.n_bins = g->n_bins;
@@ -125,6 +138,7 @@ WalkGeom make_geom(const rw_geometry* g) {
   w.rr_boost = float(1.0 / double(w.rr_survive));
   w.max_vertices = uint32_t(std::min<int64_t>(g->max_vertices, int64_t(0xFFFFFFFFu)));
   w.incidence = g->incidence;
+  set_bottom_index(w, g->n_rel);  // one medium: no interface, same index below
   return w;
 }
 
@@ -141,6 +155,61 @@ rw_status check_media(rw_context* ctx, const rw_media* m, int64_t* n_units) {
   if (m->k_stride != 0 && m->k_stride < *n_units)
     return fail(ctx, RW_E_INVALID, "k_stride (%lld) < n_units (%lld)", (long long)m->k_stride,
                 (long long)*n_units);
+  return RW_OK;
+}
+
+// What a walk call reads of its media: the K-media mixture (rw_media) or the
+// two-layer tissue (rw_layers), with the model id of the launch switches.
+struct MediaView {
+  const float* sigma_t = nullptr;
+  const float* albedo = nullptr;
+  const float* g = nullptr;
+  const float* weight = nullptr;
+  const float* layer_d = nullptr;
+  int32_t logits = 0;
+  int64_t k_stride = 0;
+  int64_t unit_base = 0;
+  int model = 0;          // K of the mixture, or kLayeredModel
+  float n_bottom = 1.0f;  // two layers: the bottom layer's index
+};
+
+MediaView view_of(const rw_media* m, const rw_geometry* geom, int64_t n_units) {
+  MediaView v;
+  v.sigma_t = m->sigma_t;
+  v.albedo = m->albedo;
+  v.g = m->g;
+  v.weight = m->weight;
+  v.logits = m->weights_are_logits ? 1 : 0;
+  v.k_stride = m->k_stride ? m->k_stride : n_units;
+  v.unit_base = m->unit_base;
+  v.model = geom->n_media;
+  return v;
+}
+
+rw_status check_layers(rw_context* ctx, const rw_layers* l, const rw_geometry* geom,
+                       MediaView* v) {
+  if (!l) return fail(ctx, RW_E_INVALID, "layers is NULL");
+  if (!l->sigma_t || !l->albedo || !l->g || !l->thickness_mm)
+    return fail(ctx, RW_E_INVALID, "a layer parameter pointer is NULL");
+  if (geom->n_media != 2)
+    return fail(ctx, RW_E_INVALID, "the two-layer walk needs n_media = 2 (got %d)", geom->n_media);
+  if (!(l->n_rel_bottom > 0.0f) || !(l->n_rel_bottom < 1e30f))
+    return fail(ctx, RW_E_INVALID, "n_rel_bottom must be a positive finite index");
+  if (l->n_units < 0) return fail(ctx, RW_E_INVALID, "n_units must be >= 0");
+  if (l->n_units > (int64_t(1) << 32))
+    return fail(ctx, RW_E_UNSUPPORTED, "more than 2^32 units per call");
+  if (l->k_stride != 0 && l->k_stride < l->n_units)
+    return fail(ctx, RW_E_INVALID, "k_stride (%lld) < n_units (%lld)", (long long)l->k_stride,
+                (long long)l->n_units);
+  *v = MediaView{};
+  v->sigma_t = l->sigma_t;
+  v->albedo = l->albedo;
+  v->g = l->g;
+  v->layer_d = l->thickness_mm;
+  v->k_stride = l->k_stride ? l->k_stride : l->n_units;
+  v->unit_base = l->unit_base;
+  v->model = kLayeredModel;
+  v->n_bottom = l->n_rel_bottom;
   return RW_OK;
 }
 
@@ -208,7 +277,7 @@ SchedPtrs sched_ptrs(rw_context* ctx, int64_t n_units) {
 // Work description shared by the four walk entry points.
 struct Plan {
   WalkArgs a{};
-  int K = 0;
+  int K = 0;  // media count of the mixture walk, or kLayeredModel
   bool adjoint = false;
   TuneCfg cfg;
   int64_t n_window = 0;
@@ -216,24 +285,26 @@ struct Plan {
 
 int round_up(int64_t v, int64_t m) { return int((v + m - 1) / m * m); }
 
-rw_status build_plan(rw_context* ctx, Plan& P, const rw_media* media, const rw_geometry* geom,
+rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_geometry* geom,
                      int64_t n_units, const int32_t* paths, int64_t paths_uniform, uint64_t seed,
                      int64_t ub, int64_t ue, bool adjoint, const TuneCfg& cfg) {
   WalkArgs& a = P.a;
   a = WalkArgs{};
-  a.sigma_t = media->sigma_t;
-  a.albedo = media->albedo;
-  a.g = media->g;
-  a.weight = media->weight;
-  a.weights_are_logits = media->weights_are_logits ? 1 : 0;
+  a.sigma_t = media.sigma_t;
+  a.albedo = media.albedo;
+  a.g = media.g;
+  a.weight = media.weight;
+  a.layer_d = media.layer_d;
+  a.weights_are_logits = media.logits;
   a.n_units_total = n_units;
-  a.k_stride = media->k_stride ? media->k_stride : n_units;
-  a.unit_base = uint32_t(uint64_t(media->unit_base));
+  a.k_stride = media.k_stride;
+  a.unit_base = uint32_t(uint64_t(media.unit_base));
   a.geo = make_geom(geom);
+  if (media.model == kLayeredModel) set_bottom_index(a.geo, media.n_bottom);
   a.key0 = uint32_t(seed);
   a.key1 = uint32_t(seed >> 32);
   a.tag = kForwardTag;
-  P.K = geom->n_media;
+  P.K = media.model;
   P.adjoint = adjoint;
   P.cfg = cfg;
   P.n_window = ue - ub;
@@ -611,18 +682,12 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
 }
 
 // ---- shared body of the four walk entry points -----------------------------
-rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
-                   const int32_t* paths, int64_t paths_uniform, uint64_t seed, rw_tally* out,
-                   const float* cot_R, const float* cot_bins, double* grad, double* grad_sumsq,
-                   int64_t* adj_vertices, int32_t* flags, const rw_batch_opts* opts, bool batched,
-                   bool adjoint, void* stream) {
-  if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
-  rw_status st = check_geom(ctx, geom);
-  if (st != RW_OK) return st;
-  int64_t n_units = 0;
-  st = check_media(ctx, media, &n_units);
-  if (st != RW_OK) return st;
+rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
+                   const rw_geometry* geom, const int32_t* paths, int64_t paths_uniform,
+                   uint64_t seed, rw_tally* out, const float* cot_R, const float* cot_bins,
+                   double* grad, double* grad_sumsq, int64_t* adj_vertices, int32_t* flags,
+                   const rw_batch_opts* opts, bool batched, bool adjoint, void* stream) {
+  rw_status st;
   if (paths_uniform < 0 || paths_uniform > (int64_t(1) << 31))
     return fail(ctx, RW_E_INVALID, "path count must be in [0, 2^31] (got %lld)",
                 (long long)paths_uniform);
@@ -689,6 +754,24 @@ rw_status run_walk(rw_context* ctx, const rw_media* media, const rw_geometry* ge
   if (batched && use_graph)
     return enqueue_graph(ctx, P, out, grad, grad_sumsq, adj_vertices, flags, s);
   return enqueue(ctx, P, batched, out, grad, grad_sumsq, adj_vertices, flags, s);
+}
+
+// argument checks of the mixture entry points, then the shared body
+rw_status run_media(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                    const int32_t* paths, int64_t paths_uniform, uint64_t seed, rw_tally* out,
+                    const float* cot_R, const float* cot_bins, double* grad, double* grad_sumsq,
+                    int64_t* adj_vertices, int32_t* flags, const rw_batch_opts* opts, bool batched,
+                    bool adjoint, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  int64_t n_units = 0;
+  st = check_media(ctx, media, &n_units);
+  if (st != RW_OK) return st;
+  return run_walk(ctx, view_of(media, geom, n_units), n_units, geom, paths, paths_uniform, seed,
+                  out, cot_R, cot_bins, grad, grad_sumsq, adj_vertices, flags, opts, batched,
+                  adjoint, stream);
 }
 
 }  // namespace
@@ -768,7 +851,7 @@ const char* rw_last_error(const rw_context* ctx) { return ctx ? ctx->last_error.
 
 rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                      int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream) {
-  return run_walk(ctx, media, geom, nullptr, paths_per_unit, seed, out, nullptr, nullptr, nullptr,
+  return run_media(ctx, media, geom, nullptr, paths_per_unit, seed, out, nullptr, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, false, false, stream);
 }
 
@@ -776,7 +859,7 @@ rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geom
                            const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
                            rw_tally* out, const rw_batch_opts* opts, void* stream) {
   rw_batch_opts def{1, 0, 0, 0};
-  return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, out, nullptr, nullptr,
+  return run_media(ctx, media, geom, paths_per_unit, paths_uniform, seed, out, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false, stream);
 }
 
@@ -784,7 +867,7 @@ rw_status rw_adjoint(rw_context* ctx, const rw_media* media, const rw_geometry* 
                      int64_t paths_per_unit, uint64_t seed, const float* cot_R,
                      const float* cot_bins, double* grad, double* grad_sumsq, int64_t* vertices,
                      int32_t* flags, void* stream) {
-  return run_walk(ctx, media, geom, nullptr, paths_per_unit, seed, nullptr, cot_R, cot_bins, grad,
+  return run_media(ctx, media, geom, nullptr, paths_per_unit, seed, nullptr, cot_R, cot_bins, grad,
                   grad_sumsq, vertices, flags, nullptr, false, true, stream);
 }
 
@@ -794,8 +877,24 @@ rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geom
                            double* grad_sumsq, int64_t* vertices, int32_t* flags,
                            const rw_batch_opts* opts, void* stream) {
   rw_batch_opts def{1, 0, 0, 0};
-  return run_walk(ctx, media, geom, paths_per_unit, paths_uniform, seed, nullptr, cot_R, cot_bins,
+  return run_media(ctx, media, geom, paths_per_unit, paths_uniform, seed, nullptr, cot_R, cot_bins,
                   grad, grad_sumsq, vertices, flags, opts ? opts : &def, true, true, stream);
+}
+
+rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_geometry* geom,
+                             const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                             rw_tally* out, const rw_batch_opts* opts, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  MediaView v;
+  st = check_layers(ctx, layers, geom, &v);
+  if (st != RW_OK) return st;
+  rw_batch_opts def{1, 0, 0, 0};
+  return run_walk(ctx, v, layers->n_units, geom, paths_per_unit, paths_uniform, seed, out, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false,
+                  stream);
 }
 
 rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
@@ -864,6 +963,42 @@ rw_status rw_debug_trace(rw_context* ctx, const rw_media* media, const rw_geomet
   a.tag = kForwardTag;
   RW_HIP(ctx, launch_trace(a, geom->n_media, words, n_paths, n_blocks, unit_index, events,
                            path_out, path_adj, reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+rw_status rw_debug_trace_layered(rw_context* ctx, const rw_layers* layers,
+                                 const rw_geometry* geom, const uint32_t* words, int64_t n_paths,
+                                 int64_t n_blocks, uint64_t seed, uint32_t unit_index,
+                                 float* events, float* path_out, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  MediaView v;
+  st = check_layers(ctx, layers, geom, &v);
+  if (st != RW_OK) return st;
+  if (layers->n_units != 1)
+    return fail(ctx, RW_E_INVALID, "rw_debug_trace_layered takes exactly one unit");
+  if (n_paths < 0 || n_paths > (int64_t(1) << 24) || n_blocks < 1 || n_blocks > (int64_t(1) << 24))
+    return fail(ctx, RW_E_INVALID, "n_paths in [0, 2^24] and n_blocks in [1, 2^24] required");
+  if (!path_out) return fail(ctx, RW_E_INVALID, "path_out is NULL");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  if (n_paths == 0) return RW_OK;
+  WalkArgs a{};
+  a.sigma_t = v.sigma_t;
+  a.albedo = v.albedo;
+  a.g = v.g;
+  a.layer_d = v.layer_d;
+  a.n_units_total = 1;
+  a.k_stride = v.k_stride;
+  a.geo = make_geom(geom);
+  set_bottom_index(a.geo, v.n_bottom);
+  a.key0 = uint32_t(seed);
+  a.key1 = uint32_t(seed >> 32);
+  a.tag = kForwardTag;
+  RW_HIP(ctx, launch_trace(a, kLayeredModel, words, n_paths, n_blocks, unit_index, events,
+                           path_out, nullptr, reinterpret_cast<hipStream_t>(stream)));
   return RW_OK;
 }
 

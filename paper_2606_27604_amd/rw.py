@@ -62,6 +62,19 @@ class RwMediaC(ctypes.Structure):
     ]
 
 
+class RwLayersC(ctypes.Structure):
+    _fields_ = [
+        ("sigma_t", ctypes.c_void_p),
+        ("albedo", ctypes.c_void_p),
+        ("g", ctypes.c_void_p),
+        ("thickness_mm", ctypes.c_void_p),
+        ("n_rel_bottom", ctypes.c_float),
+        ("n_units", ctypes.c_int64),
+        ("k_stride", ctypes.c_int64),
+        ("unit_base", ctypes.c_int64),
+    ]
+
+
 class RwTallyC(ctypes.Structure):
     _fields_ = [
         ("R", ctypes.c_void_p),
@@ -83,7 +96,8 @@ class RwBatchOptsC(ctypes.Structure):
 EXPORTS = [
     "rw_create", "rw_destroy", "rw_last_error", "rw_status_string", "rw_forward",
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
-    "rw_debug_trace", "rw_debug_philox", "rw_version",
+    "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
+    "rw_debug_trace_layered",
 ]
 
 _lib = None
@@ -129,6 +143,12 @@ def load_library(path: str = LIB_PATH):
     L.rw_debug_trace.restype = ctypes.c_int
     L.rw_debug_philox.argtypes = [vp, vp, u64, i64, vp, vp]
     L.rw_debug_philox.restype = ctypes.c_int
+    L.rw_layered_forward.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, u64, P(RwTallyC),
+                                     P(RwBatchOptsC), vp]
+    L.rw_layered_forward.restype = ctypes.c_int
+    L.rw_debug_trace_layered.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, i64, u64,
+                                         ctypes.c_uint32, vp, vp, vp]
+    L.rw_debug_trace_layered.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -237,6 +257,31 @@ class Media:
                           self.g.data_ptr() + begin * es, self.weight.data_ptr() + begin * es,
                           int(self.logits), count, 1, None, stride, sub.unit_base)
         return sub
+
+
+class Layers:
+    """Device-resident two-layer tissue (rw_layers): sigma_t, albedo, g float32
+    [2, n_units] (row 0 top layer, row 1 bottom layer), thickness float32
+    [n_units] (top-layer thickness, mm); n_rel_bottom is the bottom layer's
+    index over the outside (the top layer's is Geometry.n_rel)."""
+
+    def __init__(self, sigma_t, albedo, g, thickness_mm, n_rel_bottom: float = 1.4,
+                 unit_base: int = 0):
+        n = sigma_t.shape[1]
+        for name, t in (("sigma_t", sigma_t), ("albedo", albedo), ("g", g)):
+            _need(t, torch.float32, (2, n), name)
+        _need(thickness_mm, torch.float32, (n,), "thickness_mm")
+        self.sigma_t, self.albedo, self.g, self.thickness_mm = sigma_t, albedo, g, thickness_mm
+        self.n_rel_bottom = float(n_rel_bottom)
+        self.n_units = n
+        self.unit_base = unit_base
+        self._c = RwLayersC(_ptr(sigma_t), _ptr(albedo), _ptr(g), _ptr(thickness_mm),
+                            self.n_rel_bottom, n, n, unit_base)
+
+    @classmethod
+    def from_numpy(cls, sigma_t, albedo, g, thickness_mm, n_rel_bottom=1.4, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)  # noqa: E731
+        return cls(f(sigma_t), f(albedo), f(g), f(thickness_mm), n_rel_bottom)
 
 
 class Tally:
@@ -379,6 +424,30 @@ def rw_debug_trace(ctx: Context, media: Media, geom: Geometry, words, n_paths: i
                                              _ptr(words), int(n_paths), int(n_blocks), int(seed),
                                              int(unit_index), _ptr(events), _ptr(path_out),
                                              _ptr(path_adj), _stream(stream)))
+
+
+def rw_layered_forward(ctx: Context, layers: Layers, geom: Geometry, paths_per_unit,
+                       paths_uniform: int, seed: int, out: Tally, use_graph=True, autotune=False,
+                       unit_begin=0, unit_end=0, stream=None):
+    if paths_per_unit is not None:
+        _need(paths_per_unit, torch.int32, (layers.n_units,), "paths_per_unit")
+    g = geom.c()
+    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    ctx._check(load_library().rw_layered_forward(ctx.h, ctypes.byref(layers._c), ctypes.byref(g),
+                                                 _ptr(paths_per_unit), int(paths_uniform),
+                                                 int(seed), ctypes.byref(out._c),
+                                                 ctypes.byref(o), _stream(stream)))
+
+
+def rw_debug_trace_layered(ctx: Context, layers: Layers, geom: Geometry, words, n_paths: int,
+                           n_blocks: int, seed: int, unit_index: int, events, path_out,
+                           stream=None):
+    g = geom.c()
+    ctx._check(load_library().rw_debug_trace_layered(ctx.h, ctypes.byref(layers._c),
+                                                     ctypes.byref(g), _ptr(words), int(n_paths),
+                                                     int(n_blocks), int(seed), int(unit_index),
+                                                     _ptr(events), _ptr(path_out),
+                                                     _stream(stream)))
 
 
 def rw_debug_philox(ctx: Context, ctr, key: int, out, stream=None):

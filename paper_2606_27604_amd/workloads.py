@@ -138,3 +138,76 @@ def random_words(n_paths: int, n_blocks: int, seed: int) -> np.ndarray:
     """Injected 32-bit random words [n_paths, n_blocks, 4] for per-path replays."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, 1 << 32, size=(n_paths, n_blocks, 4), dtype=np.uint64).astype(np.uint32)
+
+
+@dataclass
+class LayeredWorkload:
+    """Two-layer tissue units (Sec. 3 geometry): per (tone, wavelength) the
+    top and bottom layers' sigma_t, albedo, g ([2, n_units] float32) and the
+    tone's top-layer thickness ([n_units] float32, mm)."""
+    name: str
+    n_sets: int
+    n_wl: int
+    sigma_t: np.ndarray
+    albedo: np.ndarray
+    g: np.ndarray
+    thickness_mm: np.ndarray
+    wavelength_nm: np.ndarray
+    paths_per_unit: int
+    n_rel: float          # top layer over the outside
+    n_rel_bottom: float   # bottom layer over the outside
+    seed: int
+    n_bins: int = N_BINS
+    r_min_mm: float = R_MIN_MM
+    r_max_mm: float = R_MAX_MM
+
+    @property
+    def n_units(self) -> int:
+        return self.n_sets * self.n_wl
+
+    def subset(self, units) -> "LayeredWorkload":
+        units = np.asarray(units)
+        c = lambda a: np.ascontiguousarray(a[..., units])  # noqa: E731
+        return LayeredWorkload(f"{self.name}[subset {units.size}]", units.size, 1, c(self.sigma_t),
+                               c(self.albedo), c(self.g), c(self.thickness_mm),
+                               self.wavelength_nm, self.paths_per_unit, self.n_rel,
+                               self.n_rel_bottom, self.seed, self.n_bins, self.r_min_mm,
+                               self.r_max_mm)
+
+
+def layered_tones(n_tones: int = 64, paths: int = 1 << 16, seed: int = 6, n_rel: float = 1.4,
+                  n_rel_bottom: float = 1.4) -> LayeredWorkload:
+    """Synthetic two-layer "skin tones" x 81 wavelengths (380-780 nm).  The
+    paper's chromophore spectra are not available; these are smooth stand-ins
+    with the structure Sec. 3 describes: a thin top layer (thickness uniform in
+    [0.05, 0.35] mm) whose absorption is dominated by a melanin-like term
+    falling steeply with wavelength (scaled by a per-tone fraction), over a
+    bottom layer with a blood-like absorption (bands near 420 and 550 nm,
+    scaled by a per-tone fraction) and a small baseline; scattering falls as a
+    power of wavelength in both layers; g(lambda) = 0.62 + 0.00029 lambda/nm in
+    both layers (the paper's epidermal phase function)."""
+    rng = np.random.default_rng(seed)
+    wl = wavelengths_81().astype(np.float64)
+    n = n_tones * wl.size
+    d = rng.uniform(0.05, 0.35, n_tones)
+    f_mel = rng.uniform(0.01, 0.40, n_tones)
+    f_blood = rng.uniform(0.002, 0.07, n_tones)
+    s_top = rng.uniform(15.0, 40.0, n_tones)   # mm^-1 at 500 nm
+    s_bot = rng.uniform(8.0, 25.0, n_tones)
+    L = wl[None, :] / 500.0
+    mua_top = f_mel[:, None] * 40.0 * L ** -3.3 + 0.02
+    blood = 30.0 * np.exp(-((wl - 420.0) / 18.0) ** 2) + 3.5 * np.exp(-((wl - 555.0) / 28.0) ** 2)
+    mua_bot = f_blood[:, None] * (blood[None, :] + 0.3) + 0.01
+    mus_top = s_top[:, None] * L ** -1.1
+    mus_bot = s_bot[:, None] * L ** -1.4
+    g = np.broadcast_to(0.62 + 0.00029 * wl[None, :], (n_tones, wl.size))
+
+    def soa(top, bot):
+        return np.ascontiguousarray(np.stack([top.reshape(n), bot.reshape(n)]).astype(np.float32))
+
+    st = soa(mua_top + mus_top, mua_bot + mus_bot)
+    al = soa(mus_top / (mua_top + mus_top), mus_bot / (mua_bot + mus_bot))
+    gg = soa(g, g)
+    th = np.ascontiguousarray(np.repeat(d, wl.size).astype(np.float32))
+    return LayeredWorkload(f"layered-{n_tones}x81", n_tones, wl.size, st, al, gg, th,
+                           wl.astype(np.float32), paths, n_rel, n_rel_bottom, seed)

@@ -1,0 +1,164 @@
+"""GPU parity of the two-layer tissue walk (Sec. 3 geometry) against the FP64
+oracle and the layered closed forms, through the C ABI (rw_layered_forward,
+rw_debug_trace_layered).
+
+Both sides draw the same Philox streams, so besides statistical agreement
+(3 combined SE) the estimates on the same seed are compared to a fraction of
+their standard error, and injected-word replays event by event."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import oracle as O
+from paper_2606_27604_amd import api, rw, workloads
+from tests._stats import accept_histogram, histogram_z, mean_se
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from tests.gpu_common import ctx, np64  # noqa: E402
+from tests.test_gpu_parity import _compare_traces  # noqa: E402
+
+
+def _geoms(n_top, slab_mm=0.0, incidence=0, rr_weight=1e-4):
+    g = rw.Geometry(n_media=2, n_rel=n_top, slab_mm=slab_mm, incidence=incidence,
+                    rr_weight=rr_weight)
+    o = O.Geometry(n_media=2, n_rel=float(np.float32(n_top)), slab_mm=float(np.float32(slab_mm)),
+                   incidence=incidence, rr_weight=float(np.float32(rr_weight)),
+                   rr_survive=float(np.float32(0.1)))
+    return g, o
+
+
+def _layers(s, a, g, d, n_bot):
+    return rw.Layers.from_numpy(np.asarray(s, np.float32).reshape(2, -1),
+                                np.asarray(a, np.float32).reshape(2, -1),
+                                np.asarray(g, np.float32).reshape(2, -1),
+                                np.asarray(d, np.float32).reshape(-1), n_bot)
+
+
+def _forward(layers, geom, paths, seed, **kw):
+    res = api.layered_forward(ctx(), layers, geom, paths, seed, **kw)
+    return res, rw.rw_check(ctx(), res.tally.flags)
+
+
+@pytest.mark.parametrize("n_top,n_bot,inc", [(1.4, 1.4, 0), (1.45, 1.3, 0), (1.45, 1.6, 1)])
+def test_layered_trace_injected_words_match_oracle(n_top, n_bot, inc):
+    s, a, g, d = [6.0, 1.5], [0.9, 0.97], [0.7, 0.5], 0.15
+    L = _layers(s, a, g, [d], n_bot)
+    geo, ogeo = _geoms(n_top, incidence=inc)
+    words = workloads.random_words(2048, 200, seed=700 + inc + int(10 * n_bot))
+    ev = torch.zeros((2048, 200, 8), dtype=torch.float32, device="cuda")
+    out = torch.zeros((2048, 8), dtype=torch.float32, device="cuda")
+    w = torch.from_numpy(np.ascontiguousarray(words).view(np.int32)).cuda()
+    rw.rw_debug_trace_layered(ctx(), L, geo, w, 2048, 200, 0, 0, ev, out)
+    torch.cuda.synchronize()
+    ev_o, out_o = O.layered_trace(ogeo, np.float32(s), np.float32(a), np.float32(g),
+                                  float(np.float32(d)), float(np.float32(n_bot)), words=words)
+    same = _compare_traces(np64(ev), np64(out), ev_o, out_o)
+    assert same.mean() >= 0.995, f"only {same.mean():.4f} of replayed paths agree"
+    crosses = int((ev_o[:, :, 0] == O.EV_CROSS).sum())
+    assert crosses > 500
+    # the layer a path ended in agrees on the agreeing paths
+    assert np.array_equal(np64(out)[same, 1], out_o[same, 1])
+
+
+def test_layered_forward_tones_vs_oracle():
+    wl = workloads.layered_tones(n_tones=2, paths=1 << 14, seed=11)
+    L = rw.Layers.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm, wl.n_rel_bottom)
+    geo, ogeo = _geoms(wl.n_rel)
+    N = wl.paths_per_unit
+    res, flags = _forward(L, geo, N, 5)
+    assert flags == 0
+    tal, bins, vert = O.layered_forward(ogeo, wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm,
+                                        float(np.float32(wl.n_rel_bottom)), N, 5)
+    R, se = np64(res.R), np64(res.R_se)
+    oR, ose = mean_se(tal[:, 0], tal[:, 1], N)
+    assert np.all(np.abs(R - oR) <= 3.0 * np.hypot(se, ose))
+    # same random numbers: far closer than the standard error
+    assert np.all(np.abs(R - oR) <= 0.25 * se + 1e-12), np.max(np.abs(R - oR) / se)
+    # absorbed weight and vertex counts
+    A = np64(res.tally.R)[:, 3]
+    assert np.allclose(A, tal[:, 3], rtol=2e-3, atol=1e-3 * N)
+    assert np.all(np.abs(np64(res.vertices) - vert) <= 2e-3 * vert)
+    # radial histograms, slot by slot
+    gb = np64(res.tally.bins)
+    for u in range(0, wl.n_units, 7):
+        mg, sg = mean_se(gb[u, :, 0], gb[u, :, 1], N)
+        mo, so = mean_se(bins[u, :, 0], bins[u, :, 1], N)
+        hits = np.minimum(bins[u, :, 0] ** 2 / np.maximum(bins[u, :, 1], 1e-300),
+                          gb[u, :, 0] ** 2 / np.maximum(gb[u, :, 1], 1e-300))
+        ok, chi2, lim = accept_histogram(histogram_z(mg, sg, mo, so, mask=hits >= 30))
+        assert ok, f"unit {u}: chi2 {chi2:.1f} > {lim:.1f}"
+
+
+def test_layered_interface_step_vs_oracle_and_graph_forms():
+    wl = workloads.layered_tones(n_tones=1, paths=1 << 15, seed=12, n_rel=1.45, n_rel_bottom=1.36)
+    sub = wl.subset(np.arange(0, 81, 4))
+    L = rw.Layers.from_numpy(sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm, sub.n_rel_bottom)
+    geo, ogeo = _geoms(sub.n_rel)
+    N = sub.paths_per_unit
+    a, fa = _forward(L, geo, N, 9)
+    b, fb = _forward(L, geo, N, 9, use_graph=False)
+    assert fa == 0 and fb == 0
+    assert torch.equal(a.tally.R, b.tally.R) and torch.equal(a.tally.bins, b.tally.bins)
+    tal, _, vert = O.layered_forward(ogeo, sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm,
+                                     float(np.float32(sub.n_rel_bottom)), N, 9)
+    R, se = np64(a.R), np64(a.R_se)
+    oR, _ = mean_se(tal[:, 0], tal[:, 1], N)
+    assert np.all(np.abs(R - oR) <= 0.25 * se + 1e-12), np.max(np.abs(R - oR) / se)
+    assert np.all(np.abs(np64(a.vertices) - vert) <= 2e-3 * vert)
+
+
+def test_layered_closed_forms_on_gpu():
+    N = 1 << 20
+    # absorbing non-scattering top layer over an isotropic bottom, n = 1
+    geo, _ = _geoms(1.0)
+    taus, als, d = [0.2, 1.0], [0.95, 0.8], 0.25
+    L = _layers([[t / d for t in taus], [3.0, 3.0]], [[0.0, 0.0], als], [[0.0, 0.0], [0.0, 0.0]],
+                [d, d], 1.0)
+    res, flags = _forward(L, geo, N, 3)
+    assert flags == 0
+    ref = np.array([cf.R_absorbing_top(al, t) for t, al in zip(taus, als)])
+    z = (np64(res.R) - ref) / np64(res.R_se)
+    assert np.all(np.abs(z) <= 3.5), z
+    # Beer-Lambert through two absorbing layers of a slab
+    geo, _ = _geoms(1.0, slab_mm=1.0)
+    L = _layers([[1.7], [0.6]], [[0.0], [0.0]], [[0.0], [0.0]], [0.3], 1.0)
+    res, flags = _forward(L, geo, N, 4)
+    p = math.exp(-1.7 * 0.3 - 0.6 * 0.7)
+    T = float(res.tally.R[0, 2]) / N
+    assert abs(T - p) <= 3.5 * math.sqrt(p * (1 - p) / N) and float(res.tally.R[0, 0]) == 0.0
+    # non-scattering stack: incoherent adding of three Fresnel interfaces
+    for n0, n1, inc in ((1.4, 1.6, 0), (1.4, 1.3, 1), (1.4, 0.8, 1)):
+        geo, _ = _geoms(n0, slab_mm=2.0, incidence=inc, rr_weight=0.0)
+        L = _layers([[1e-12], [1e-12]], [[1.0], [1.0]], [[0.0], [0.0]], [0.7], n1)
+        res, flags = _forward(L, geo, N, 5)
+        assert flags == 0
+        R_ref, T_ref = cf.stack_RT(n0, n1, "cosine" if inc else "normal")
+        R, seR = float(res.R[0]), float(res.R_se[0])
+        T = float(res.tally.R[0, 2]) / N
+        assert abs(R - R_ref) <= 3.5 * max(seR, 1e-9), (n0, n1, inc, R, R_ref)
+        assert abs(T - T_ref) <= 3.5 * math.sqrt(max(T_ref * (1 - T_ref), 1e-12) / N) + 1e-6
+
+
+def test_layered_invalid_inputs():
+    geo, _ = _geoms(1.4)
+    L = _layers([[2.0, 2.0, 2.0], [1.0, 1.0, 1.0]], [[0.9] * 3, [0.9] * 3], [[0.5] * 3, [0.5] * 3],
+                [0.1, 0.0, -1.0], 1.4)
+    res, flags = _forward(L, geo, 256, 1)
+    assert flags & rw.RW_FLAG_BAD_PARAMS
+    assert float(res.tally.R[1, 0]) == 0.0 and float(res.tally.R[2, 0]) == 0.0
+    assert float(res.tally.R[0, 0]) > 0.0
+    # the top layer must end above a slab's bottom
+    geo_s, _ = _geoms(1.4, slab_mm=0.05)
+    res, flags = _forward(_layers([[2.0], [1.0]], [[0.9], [0.9]], [[0.5], [0.5]], [0.1], 1.4),
+                          geo_s, 256, 1)
+    assert flags & rw.RW_FLAG_BAD_PARAMS
+    # host-side checks: two layers means n_media = 2; a positive bottom index
+    with pytest.raises(rw.RwError, match="n_media"):
+        api.layered_forward(ctx(), L, rw.Geometry(n_media=3), 64, 0)
+    L_bad = _layers([[2.0], [1.0]], [[0.9], [0.9]], [[0.5], [0.5]], [0.1], 0.0)
+    with pytest.raises(rw.RwError, match="n_rel_bottom"):
+        api.layered_forward(ctx(), L_bad, geo, 64, 0)
