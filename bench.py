@@ -1,7 +1,7 @@
 """Benchmark of the mixture-of-media random walk on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3] [--no-c4]
-                    [--micro] [--lut N [--lut-photons P]]
+                    [--micro] [--lut N [--lut-photons P]] [--layers N [--layers-photons P]]
 
 One step is one pass of the whole path over the 81-wavelength three-medium
 workload (81 wavelengths 380-780 nm, per-medium sigma_t log-uniform in
@@ -180,6 +180,10 @@ def main():
                          "(alpha, g) lookup table (Sec. 4.2) and print its own JSON line")
     ap.add_argument("--lut-photons", type=int, default=1 << 14)
     ap.add_argument("--lut-cells-per-launch", type=int, default=1 << 17)
+    ap.add_argument("--layers", type=int, default=0,
+                    help="instead of the step benchmark, time the two-layer tissue walk over N "
+                         "synthetic tones x 81 wavelengths and print its own JSON line")
+    ap.add_argument("--layers-photons", type=int, default=1 << 16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the walk shards by unit with no communication, and "
@@ -196,6 +200,9 @@ def main():
         return
     if args.lut:
         lut_generation(rw, torch, args)
+        return
+    if args.layers:
+        layered_tones(rw, torch, args)
         return
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -500,6 +507,89 @@ def lut_generation(rw, torch, args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = lut_cpu_baseline(N)
     print(json.dumps(out), flush=True)
+
+
+def layered_tones(rw, torch, args):
+    """The two-layer tissue walk (Sec. 3 geometry, rw_layered_forward) over N
+    synthetic tones x 81 wavelengths at --layers-photons photons per
+    (tone, wavelength), n = 1.4 in both layers, timed with HIP events on the
+    launch stream (second of two calls).  The paper generates 30,000 tones x
+    376 wavelengths at 10^6 photons; the time for that is projected linearly
+    from the measured per-photon rate of these tones.  The FP64 oracle is
+    timed on a bounded sample of the same units."""
+    from paper_2606_27604_amd import workloads
+
+    ctx = rw.Context(0)
+    s = torch.cuda.current_stream()
+    P = args.layers_photons
+    wl = workloads.layered_tones(n_tones=args.layers, paths=P)
+    layers = rw.Layers.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm, wl.n_rel_bottom)
+    geom = rw.Geometry(n_media=2, n_rel=wl.n_rel, n_bins=wl.n_bins, r_min_mm=wl.r_min_mm,
+                       r_max_mm=wl.r_max_mm)
+    tally = rw.Tally(wl.n_units, wl.n_bins)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for rep in range(2):  # the first call builds the graph
+        ev[0].record(s)
+        rw.rw_layered_forward(ctx, layers, geom, None, P, 100 + rep, tally, stream=s)
+        ev[1].record(s)
+        torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    flags = rw.rw_check(ctx, tally.flags)
+    v = int(tally.vertices.sum().item())
+    paths = wl.n_units * P
+    slots = alg_slots_per_vertex(False)
+    achieved = slots * v / (ms * 1e-3) / 1e12
+    peak = ISSUE_PEAK / 1e12
+    out = {
+        "metric": "two-layer tissue walk: MC path vertices/s (forward)",
+        "value": v / (ms * 1e-3), "unit": "vertices/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic two-layer tones (no chromophore spectra)",
+        "config": {"workload": f"layered-{args.layers}x81: top layer 0.05-0.35 mm over a "
+                               f"semi-infinite bottom layer, n = 1.4, {P} photons per "
+                               "(tone, wavelength), 256 log bins [1e-3, 50] mm",
+                   "units": wl.n_units, "photons_per_unit": P},
+        "ms": ms, "vertices": v, "vertices_per_photon": v / paths,
+        "photons_per_s": paths / (ms * 1e-3), "spectra_per_s": args.layers / (ms * 1e-3),
+        "projected_hours_30000_tones_x_376_wl_at_1e6_photons":
+            30000 * 376 * 1e6 * (ms * 1e-3 / paths) / 3600.0,
+        "device_flags": flags,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                     "frac": achieved / peak,
+                     "traffic": load_traffic("walk_kernel<2, forward, layered>"),
+                     "kernel": "walk_kernel<2, forward, layered>", "slots_per_vertex": slots,
+                     "note": "slot model of the mixture forward vertex (the interface adds "
+                             "work only at crossing vertices)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = layered_cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+def layered_cpu_baseline(wl, max_seconds=30.0):
+    """The FP64 oracle on the first tone's 81 wavelengths, at a photon count
+    doubled from 2^10 until one pass takes 8 s."""
+    from oracle import oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    sub = wl.subset(np.arange(wl.n_wl))
+    geo = O.Geometry(n_media=2, n_rel=float(np.float32(wl.n_rel)), n_bins=wl.n_bins)
+    paths = 1 << 10
+    while True:
+        t0 = time.perf_counter()
+        _, _, vert = O.layered_forward(geo, sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm,
+                                       float(np.float32(wl.n_rel_bottom)), paths, 17,
+                                       n_threads=cores)
+        dt = time.perf_counter() - t0
+        if dt > 8.0 or dt * 2 > max_seconds:
+            break
+        paths *= 2
+    return {"value": float(vert.sum()) / dt, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "sample": f"one tone x 81 wavelengths x {paths} photons, FP64, "
+                      f"{int(vert.sum())} vertices in {dt:.2f} s"}
 
 
 def lut_cpu_baseline(N, n_cells=256, max_seconds=30.0):
