@@ -23,6 +23,10 @@ What pins what:
                      and common-random-number central differences of the forward
   brute force      - a deterministic grid of injected words averages to the
                      single-scattering closed form
+  adding-doubling  - totals of multiply-scattering media with g != 0 and a
+                     Fresnel boundary (semi-infinite, slab R and T, two layers,
+                     normal and cosine incidence) against the deterministic
+                     adding-doubling solution, itself pinned to closed forms
   two layers       - Beer-Lambert through two absorbing layers; identical
                      layers and a vanishing top layer reproduce the
                      plane albedo; an absorbing non-scattering top layer over an
@@ -495,6 +499,36 @@ def check_layer_trace_invariants(n_paths=3000, seed=24):
     return _r(ok, f"fails={fails} crossings={n_cross} interface reflections={n_if_refl}")
 
 
+# ---- multiple scattering with g != 0 and Fresnel: adding-doubling ------------
+def check_adding_doubling(paths=1 << 18, seed=30, k=3.0):
+    """Totals of multiply-scattering media with anisotropic scattering and a
+    Fresnel boundary against the deterministic adding-doubling solution
+    (oracle/adding_doubling.py): semi-infinite media under a normal beam and a
+    cosine lobe, R and T of a slab, and a two-layer medium."""
+    from oracle import adding_doubling as AD
+
+    zs = []
+    for al, g, n, inc in ((0.9, 0.8, 1.4, 0), (0.97, 0.5, 1.33, 1), (0.6, -0.3, 1.0, 0)):
+        geo = O.Geometry(n_media=1, n_rel=n, incidence=inc)
+        tal, _, _ = O.forward(geo, [2.0], [al], [g], [1.0], paths, seed)
+        m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+        zs.append((m - AD.R_semi_infinite(al, g, n, "cosine" if inc else "normal")) / se)
+    # slab of optical thickness 2 with Fresnel faces: R and T
+    geo = O.Geometry(n_media=1, n_rel=1.4, slab_mm=1.0)
+    tal, _, _ = O.forward(geo, [2.0], [0.95], [0.6], [1.0], paths, seed + 1)
+    R_ref, T_ref = AD.slab_RT(0.95, 0.6, 1.4, 2.0)
+    m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+    T = tal[0, 2] / paths
+    zs += [(m - R_ref) / se, (T - T_ref) / math.sqrt(T_ref * (1 - T_ref) / paths)]
+    # two layers (matched interface): top tau = 0.8 over a semi-infinite bottom
+    geo = O.Geometry(n_media=2, n_rel=1.4)
+    tal, _, _ = O.layered_forward(geo, [[8.0], [2.0]], [[0.7], [0.97]], [[0.8], [0.6]], [0.1],
+                                  1.4, paths, seed + 2)
+    m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+    zs.append((m - AD.two_layer_R((0.7, 0.8, 0.8), (0.97, 0.6), 1.4)) / se)
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
 BATTERY_SMALL = [
     ("plane", lambda: check_plane_albedo(alphas=(0.5, 0.9), paths=1 << 16, k=4.0)),
     ("second_moment", lambda: check_second_moment(paths=1 << 16, k=4.0)),
@@ -517,4 +551,5 @@ BATTERY_SMALL = [
     ("layers_stack", lambda: check_transparent_stack(paths=1 << 15, k=4.0)),
     ("layers_analog", lambda: check_layers_analog_vs_weighted(paths=1 << 16, k=4.0)),
     ("layers_trace", lambda: check_layer_trace_invariants(n_paths=1500)),
+    ("adding_doubling", lambda: check_adding_doubling(paths=1 << 16, k=4.0)),
 ]

@@ -131,3 +131,35 @@ def test_two_layer_closed_forms_limits():
     for n1 in (1.3, 0.8):
         R, T = cf.stack_RT(1.4, n1, "cosine")
         assert abs(R + T + Fbar - 1.0) < 1e-9
+
+
+def test_adding_doubling_against_closed_forms():
+    from oracle import adding_doubling as AD
+    # g = 0, n = 1: plane albedo (normal) and spherical albedo (cosine lobe)
+    for a in (0.5, 0.9, 0.99):
+        assert abs(AD.R_semi_infinite(a, 0.0, 1.0) - cf.R_plane(a)) < 2e-6
+    for a in (0.5, 0.9):
+        assert abs(AD.R_semi_infinite(a, 0.0, 1.0, "cosine") - cf.R_spherical(a)) < 2e-6
+    # alpha -> 0: the single-scattering term, any g and Fresnel index
+    a = 1e-4
+    for g, n in ((0.0, 1.4), (0.8, 1.4), (0.5, 1.0), (-0.3, 1.33)):
+        r1 = cf.R1_total(a, g, n)
+        assert abs(AD.R_semi_infinite(a, g, n) - r1) < 5e-4 * r1
+    # non-scattering slab with Fresnel faces (normal incidence)
+    n, tau = 1.4, 0.7
+    F, e = ((n - 1) / (n + 1)) ** 2, math.exp(-0.7)
+    R, T = AD.slab_RT(0.0, 0.0, n, tau)
+    assert abs(T - (1 - F) ** 2 * e / (1 - F * F * e * e)) < 1e-6
+    assert abs(R - (1 - F) ** 2 * F * e * e / (1 - F * F * e * e)) < 1e-7
+    # energy: alpha = 1 slab, R + T + specular = 1, both incidences
+    for g in (0.0, 0.8):
+        for inc in ("normal", "cosine"):
+            R, T = AD.slab_RT(1.0, g, 1.4, 2.0, inc)
+            assert abs(R + T + AD.entry_specular(1.4, inc) - 1.0) < 1e-6
+    # two layers: identical layers, a vanishing top layer, an absorbing top
+    assert abs(AD.two_layer_R((0.9, 0.8, 0.7), (0.9, 0.8), 1.4) -
+               AD.R_semi_infinite(0.9, 0.8, 1.4)) < 1e-8
+    assert abs(AD.two_layer_R((0.2, 0.5, 1e-9), (0.95, 0.7), 1.4, "cosine") -
+               AD.R_semi_infinite(0.95, 0.7, 1.4, "cosine")) < 1e-8
+    assert abs(AD.two_layer_R((0.0, 0.0, 0.5), (0.8, 0.0), 1.0) -
+               cf.R_absorbing_top(0.8, 0.5)) < 1e-7

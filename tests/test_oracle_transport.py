@@ -195,3 +195,11 @@ def test_layered_invalid_parameters_are_rejected():
     with pytest.raises(ValueError):  # two layers means n_media = 2
         O.layered_forward(O.Geometry(n_media=3), good["s"], good["a"], good["g"], [0.1], 1.4,
                           16, 0)
+
+
+def test_multiple_scattering_against_adding_doubling():
+    # six comparisons at once: 3.5 SE each keeps the family-wise false alarm
+    # rate near 0.3 % (a run at 2^23 paths of the g = 0.8, n = 1.4 case sits at
+    # 0.5 SE of the adding-doubling value)
+    ok, detail = P.check_adding_doubling(paths=1 << 20, k=3.5)
+    assert ok, detail
