@@ -688,37 +688,58 @@ __device__ __forceinline__ float est_path_vertices(float alb, float g, const Wal
   return 2.0f + fminf(n_rr, 5.0f * sqrtf(n_rr / fmaxf(1.0f - g, 1e-3f)));
 }
 
-__device__ __forceinline__ void put_bucket(int64_t ul, float c, int32_t* bucket, uint32_t* hist) {
+// Bucket of a unit's estimated cost (descending cost order), counted in the
+// block's LDS histogram; the block then adds its non-zero counts to the global
+// histogram, one atomic per bucket (adjacent units tend to share buckets, and
+// per-unit global atomics on 64 counters serialise: ~1 ms per 10^5 units).
+__device__ __forceinline__ int cost_bucket(float c) {
   int b = int(4.0f * __log2f(c + 1.0f));
   b = b < 0 ? 0 : (b > kOrderBuckets - 1 ? kOrderBuckets - 1 : b);
-  b = kOrderBuckets - 1 - b;  // descending cost
-  bucket[ul] = b;
-  atomicAdd(&hist[b], 1u);
+  return kOrderBuckets - 1 - b;
+}
+
+__device__ __forceinline__ void block_histogram_add(uint32_t* local, uint32_t* hist) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
+    if (local[i]) atomicAdd(&hist[i], local[i]);
 }
 
 template <int K>
 __global__ void __launch_bounds__(256) unit_cost_kernel(const WalkArgs a, int32_t* bucket,
                                                         uint32_t* hist) {
+  __shared__ uint32_t local[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) local[i] = 0u;
+  __syncthreads();
   const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (ul >= a.map.n_units) return;
-  const UnitParams<K> up = load_unit<K>(a, a.map.unit_begin + ul);
-  float c = 1.0f;
-  if (up.ok) {
-    c = 0.0f;
+  if (ul < a.map.n_units) {
+    const UnitParams<K> up = load_unit<K>(a, a.map.unit_begin + ul);
+    float c = 1.0f;
+    if (up.ok) {
+      c = 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) c += up.w[k] * est_path_vertices(up.alb[k], up.g[k], a.geo);
+      for (int k = 0; k < K; ++k) c += up.w[k] * est_path_vertices(up.alb[k], up.g[k], a.geo);
+    }
+    const int b = cost_bucket(c);
+    bucket[ul] = b;
+    atomicAdd(&local[b], 1u);
   }
-  put_bucket(ul, c, bucket, hist);
+  block_histogram_add(local, hist);
 }
 
 // two-layer units: a path spends most of its vertices in the bottom layer
 __global__ void __launch_bounds__(256) unit_cost_layered_kernel(const WalkArgs a, int32_t* bucket,
                                                                 uint32_t* hist) {
+  __shared__ uint32_t local[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) local[i] = 0u;
+  __syncthreads();
   const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (ul >= a.map.n_units) return;
-  const LayerParams lp = load_layers(a, a.map.unit_begin + ul);
-  const float c = lp.ok ? est_path_vertices(lp.alb[1], lp.g[1], a.geo) : 1.0f;
-  put_bucket(ul, c, bucket, hist);
+  if (ul < a.map.n_units) {
+    const LayerParams lp = load_layers(a, a.map.unit_begin + ul);
+    const int b = cost_bucket(lp.ok ? est_path_vertices(lp.alb[1], lp.g[1], a.geo) : 1.0f);
+    bucket[ul] = b;
+    atomicAdd(&local[b], 1u);
+  }
+  block_histogram_add(local, hist);
 }
 
 // exclusive prefix of the bucket counts, in place (one wave)
@@ -733,13 +754,26 @@ __global__ void order_scan_kernel(uint32_t* hist) {
 }
 
 // scatter local unit indices to their bucket ranges (order within a bucket is
-// arbitrary; it only affects timing)
+// arbitrary; it only affects timing): each block counts its units per bucket
+// in LDS, reserves one range per non-empty bucket with one global atomic, and
+// places its units inside the ranges by their LDS ranks
 __global__ void __launch_bounds__(256) order_scatter_kernel(int64_t n_units, const int32_t* bucket,
                                                             uint32_t* cursor, int32_t* unit_order) {
+  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) cnt[i] = 0u;
+  __syncthreads();
   const int64_t ul = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (ul >= n_units) return;
-  const uint32_t pos = atomicAdd(&cursor[bucket[ul]], 1u);
-  unit_order[pos] = int32_t(ul);
+  int b = -1;
+  uint32_t rank = 0;
+  if (ul < n_units) {
+    b = bucket[ul];
+    rank = atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
+    base[i] = cnt[i] ? atomicAdd(&cursor[i], cnt[i]) : 0u;
+  __syncthreads();
+  if (b >= 0) unit_order[base[b] + rank] = int32_t(ul);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {

@@ -328,3 +328,67 @@ def test_adjoint_workload_subset_vs_oracle_gradient():
     assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
     # same random numbers: far inside the statistical error
     assert np.median(np.abs(z)) <= 0.05, np.median(np.abs(z))
+
+
+def test_full_size_batched_sweep_sampled_units_vs_oracle():
+    """The batched sweep as the benchmark times it (65,536 sets x 16
+    wavelengths x 4,096 paths, one persistent graph launch) against the oracle
+    on sampled units, which draw the same random numbers (unit_base)."""
+    wl = workloads.config3()
+    m = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_sets, wl.n_wl)
+    g, og = geoms(3, wl.n_rel, n_bins=wl.n_bins)
+    res, flags = gpu_forward(m, g, wl.paths_per_unit, 7)
+    assert flags == 0
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(wl.n_units, 24, replace=False))
+    sub = wl.subset(sample)
+    N = wl.paths_per_unit
+    R, se = np64(res.R)[sample], np64(res.R_se)[sample]
+    for i, u in enumerate(sample):
+        tal, _, vert = O.forward(og, sub.sigma_t[:, i:i + 1], sub.albedo[:, i:i + 1],
+                                 sub.g[:, i:i + 1], sub.weight[:, i:i + 1], N, 7,
+                                 unit_base=int(u))
+        oR, ose = mean_se(tal[0, 0], tal[0, 1], N)
+        assert abs(R[i] - oR) <= 3.0 * np.hypot(se[i], ose), u
+        assert abs(R[i] - oR) <= 0.25 * se[i] + 1e-12, (u, (R[i] - oR) / se[i])
+        assert abs(float(res.vertices[u]) - vert[0]) <= 2e-3 * vert[0]
+    Rall = np64(res.R)
+    assert np.all((Rall > 0) & (Rall < 1))
+    bins = np64(res.tally.bins)
+    np.testing.assert_allclose(bins[:, :, 0].sum(1), np64(res.tally.R)[:, 0], rtol=1e-12)
+
+
+def test_full_size_adjoint_sweep_sampled_units_vs_oracle():
+    """The adjoint sweep as the benchmark times it (1,024 sets x 81
+    wavelengths x 2^14 paths, v_R = 1, v_bins ~ N(0, 1), persistent graph
+    launch) against the oracle's FP64 gradient on sampled units."""
+    wl = workloads.config4()
+    m = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_sets, wl.n_wl)
+    g, og = geoms(3, wl.n_rel)
+    cR, cB = wl.extra["cot_R"], wl.extra["cot_bins"]
+    grad, sq, vert, flags = api.adjoint(ctx(), m, g, wl.paths_per_unit, 41,
+                                        cot_R=torch.from_numpy(cR).cuda(),
+                                        cot_bins=torch.from_numpy(cB).cuda())
+    assert rw.rw_check(ctx(), flags) == 0
+    rng = np.random.default_rng(6)
+    sample = np.sort(rng.choice(wl.n_units, 12, replace=False))
+    sub = wl.subset(sample)
+    N = wl.paths_per_unit
+    G, S = np64(grad)[sample], np64(sq)[sample]
+    zs = []
+    for i, u in enumerate(sample):
+        og_, osq = O.adjoint(og, sub.sigma_t[:, i:i + 1], sub.albedo[:, i:i + 1],
+                             sub.g[:, i:i + 1], sub.weight[:, i:i + 1], N, 41,
+                             cot_R=cR[u:u + 1], cot_bins=cB[u:u + 1], unit_base=int(u))
+        mg, sg = mean_se(G[i:i + 1], S[i:i + 1], N)
+        mo, so = mean_se(og_, osq, N)
+        zs.append(((mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)).ravel())
+    z = np.concatenate(zs)
+    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    # same random numbers: far inside the statistical error (a path whose FP32
+    # and FP64 replays part at a threshold moves one unit's gradient by a
+    # fraction of its SE, hence a median over the 144 sampled values)
+    assert np.median(np.abs(z)) <= 0.08, np.median(np.abs(z))
+    # the softmax logits' gradients sum to zero in every unit
+    gr = np64(grad)
+    assert np.allclose(gr[:, 9:12].sum(1), 0.0, atol=1e-6 * np.abs(gr).max())
