@@ -240,6 +240,62 @@ rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
                       double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,
                       void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Lookup-table fit (Sec. 4.2): the K-media profile from the scale-independent
+ * tables R(alpha, g) and P_d(r | alpha, g) at sigma_t = 1 (eq. mixture, with
+ * eq. separability for sigma_t: P(r | alpha, g, sigma_t) =
+ * sigma_t^2 P_d(sigma_t r | alpha, g)), R bilinear in (alpha, g) and P
+ * trilinear in (alpha, g, log r) between bin centres, 0 off the table; the
+ * loss of eq. joint_loss per unit; its gradient; one Adam step.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* R;        /* DEVICE [n_alpha][n_g] total diffuse reflectance */
+  const float* Pd;       /* DEVICE [n_alpha][n_g][n_bins] profile, mm^-2 at sigma_t = 1 */
+  int32_t n_alpha, n_g, n_bins;   /* n_alpha, n_g >= 2, n_bins >= 2 */
+  float alpha_max, g_max;         /* uniform grids over [0, alpha_max] and [0, g_max] */
+  float r_min_mm, r_max_mm;       /* n_bins log-spaced bins over [r_min, r_max) */
+} rw_lut;
+
+typedef struct {
+  const float* R;        /* DEVICE [n_units] target total reflectance */
+  const float* Pd;       /* DEVICE [n_units][n_r] target normalised profile R(r)/R, mm^-2 */
+  const float* mass;     /* DEVICE [n_units][n_r] target exit probability per bin */
+  const float* r_mm;     /* DEVICE [n_r] evaluation radii (bin centres) */
+  int32_t n_r;           /* 1..512 */
+  float lambda_R;        /* weight of (R_hat - R_t)^2 (the paper's 5) */
+  float min_mass;        /* bins with mass < min_mass stay out of the shape term */
+  float shape_floor;     /* relative floor f: the shape term compares
+                            log(P + f P_t) with log(P_t + f P_t) */
+} rw_lut_targets;
+
+/* Loss and gradient of eq. joint_loss for K media per unit (K = 1..4):
+ *   L = sqrt(mean over bins with mass >= min_mass of
+ *            (log(P_hat + f P_t + 1e-12) - log(P_t + f P_t + 1e-12))^2 + 1e-30)
+ *       + lambda_R (R_hat - R_t)^2,
+ * R_hat = sum_k w_k R(alpha_k, g_k), P_hat = sum_k w_k R_k P_k / max(R_hat, 1e-12).
+ * params: DEVICE float [4K - 1][n_units] raw parameters (row-major by
+ * parameter): log sigma_t (K rows), logit alpha (K), logit(g / 0.99) (K) and
+ * the first K - 1 softmax logits of the weights (the last logit is 0).
+ * grad (DEVICE float, same layout, or NULL) receives dL/dparams; loss (DEVICE
+ * float [n_units], or NULL) receives L.  Interpolation follows the cell of the
+ * floor of the grid coordinate, clamped to the grid, as a piecewise-linear
+ * function is differentiated; coordinates outside a table's range clamp and
+ * pass no gradient.  Returns RW_E_INVALID for bad sizes or NULL tables. */
+rw_status rw_lut_loss_grad(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* targets,
+                           int64_t n_units, int32_t n_media, const float* params, float* grad,
+                           float* loss, void* stream);
+
+/* One Adam step (the paper's optimiser, Sec. 4.2 "Optimization") on the same
+ * loss, in place: m = b1 m + (1 - b1) grad, v = b2 v + (1 - b2) grad^2,
+ * params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps) with
+ * b1 = 0.9, b2 = 0.999, eps = 1e-8 and t = step (>= 1).  adam_m, adam_v:
+ * DEVICE float, same layout as params, zero before the first step.  loss
+ * (or NULL) receives the loss before the step.  A schedule passes its lr per
+ * step. */
+rw_status rw_lut_fit_step(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* targets,
+                          int64_t n_units, int32_t n_media, float* params, float* adam_m,
+                          float* adam_v, int32_t step, float lr, float* loss, void* stream);
+
 /* Synchronise `stream`, read flags[0] into *out_flags (may be NULL) and
  * return RW_E_DEVICE_FLAG when it is nonzero. */
 rw_status rw_check(rw_context* ctx, const int32_t* flags, int32_t* out_flags, void* stream);

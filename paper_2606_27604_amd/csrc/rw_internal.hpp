@@ -112,6 +112,32 @@ inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {
   return acc_words + kMediaTableWords + kColdConstWords + kExitRing * (adjoint ? 4 : 2);
 }
 
+// Lookup-table fit (rw_lut.hip): tables, targets, raw parameters [4K-1][n_units]
+struct LutArgs {
+  const float* R;              // [n_alpha][n_g]
+  const float* Pd;             // [n_alpha][n_g][n_bins]
+  int32_t n_alpha, n_g, n_bins;
+  float alpha_max, g_max;
+  float log_rmin, inv_step;    // ln r_min, n_bins / ln(r_max / r_min)
+  const float* t_R;            // [n_units]
+  const float* t_Pd;           // [n_units][n_r]
+  const float* t_mass;         // [n_units][n_r]
+  const float* r_mm;           // [n_r]
+  int32_t n_r;
+  float lambda_R, min_mass, shape_floor;
+  int64_t n_units;
+  const float* params;         // read
+  float* params_out;           // Adam writes here (the same array: in place)
+  float* grad;                 // or nullptr
+  float* loss;                 // or nullptr
+  float* adam_m;
+  float* adam_v;
+  int32_t adam;                // 1: take an Adam step
+  int32_t step;
+  float lr;
+};
+hipError_t launch_lut(const LutArgs& a, int K, hipStream_t stream);
+
 // launchers (rw_kernels.hip); all asynchronous on `stream`
 hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg, int grid_wgs,
                        hipStream_t stream);

@@ -27,6 +27,10 @@ using u64 = unsigned long long;
 
 // vertex count above which a path counts as long (priority boost)
 constexpr uint32_t kLongPath = 256;
+// vertex steps per pass of the walk loop's schedule (regeneration, ballots,
+// exit ring): more steps spread that bookkeeping over more vertices, at the
+// cost of lanes that end early in a pass idling for its remaining steps
+constexpr int kStepsPerIteration = 3;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -445,20 +449,26 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
       }
     }
 
+    // kStepsPerIteration vertices per pass of the schedule above; a lane whose
+    // path ends in an earlier step sits out the later ones (its end code and
+    // state stay as they were) and is tallied below with the others
     int ev = EV_COLLIDE;
-    if (alive) {
-      const uint4 w = philox(v, path, a.tag, lctr, ks);
-      if (v == 0) {
-        start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
-        v = 1;
-      } else {
-        ev = step_any<ADJ, LAYERED>(p, w, geo);
-        if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
-          ev = EV_CAP;
-          capped = true;
+#pragma unroll
+    for (int rep = 0; rep < kStepsPerIteration; ++rep) {
+      if (alive) {
+        const uint4 w = philox(v, path, a.tag, lctr, ks);
+        if (v == 0) {
+          start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
+          v = 1;
+        } else {
+          ev = step_any<ADJ, LAYERED>(p, w, geo);
+          if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+            ev = EV_CAP;
+            capped = true;
+          }
+          if (ev >= EV_EXIT_TOP) alive = false;
+          else ++v;
         }
-        if (ev >= EV_EXIT_TOP) alive = false;
-        else ++v;
       }
     }
     const bool ending = ev >= EV_EXIT_TOP;

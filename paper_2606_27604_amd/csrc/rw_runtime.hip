@@ -756,6 +756,46 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
   return enqueue(ctx, P, batched, out, grad, grad_sumsq, adj_vertices, flags, s);
 }
 
+rw_status lut_args(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* t, int64_t n_units,
+                   int32_t n_media, const float* params, LutArgs* a) {
+  if (!lut || !t) return fail(ctx, RW_E_INVALID, "lut and targets must be non-NULL");
+  if (!lut->R || !lut->Pd) return fail(ctx, RW_E_INVALID, "the tables must be non-NULL");
+  if (lut->n_alpha < 2 || lut->n_g < 2 || lut->n_bins < 2)
+    return fail(ctx, RW_E_INVALID, "tables need at least 2 points per axis");
+  if (!(lut->alpha_max > 0.0f) || !(lut->g_max > 0.0f) || !(lut->r_min_mm > 0.0f) ||
+      !(lut->r_max_mm > lut->r_min_mm))
+    return fail(ctx, RW_E_INVALID, "need alpha_max > 0, g_max > 0 and 0 < r_min < r_max");
+  if (!t->R || !t->Pd || !t->mass || !t->r_mm)
+    return fail(ctx, RW_E_INVALID, "target pointers must be non-NULL");
+  if (t->n_r < 1 || t->n_r > 512) return fail(ctx, RW_E_INVALID, "n_r must be in [1, 512]");
+  if (n_media < 1 || n_media > kMaxMedia)
+    return fail(ctx, RW_E_INVALID, "n_media must be in [1, %d]", kMaxMedia);
+  if (n_units < 0 || n_units > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "n_units must be in [0, 2^31]");
+  if (!params) return fail(ctx, RW_E_INVALID, "params is NULL");
+  *a = LutArgs{};
+  a->R = lut->R;
+  a->Pd = lut->Pd;
+  a->n_alpha = lut->n_alpha;
+  a->n_g = lut->n_g;
+  a->n_bins = lut->n_bins;
+  a->alpha_max = lut->alpha_max;
+  a->g_max = lut->g_max;
+  a->log_rmin = float(std::log(double(lut->r_min_mm)));
+  a->inv_step = float(double(lut->n_bins) / std::log(double(lut->r_max_mm) / double(lut->r_min_mm)));
+  a->t_R = t->R;
+  a->t_Pd = t->Pd;
+  a->t_mass = t->mass;
+  a->r_mm = t->r_mm;
+  a->n_r = t->n_r;
+  a->lambda_R = t->lambda_R;
+  a->min_mass = t->min_mass;
+  a->shape_floor = t->shape_floor;
+  a->n_units = n_units;
+  a->params = params;
+  return RW_OK;
+}
+
 // argument checks of the mixture entry points, then the shared body
 rw_status run_media(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                     const int32_t* paths, int64_t paths_uniform, uint64_t seed, rw_tally* out,
@@ -999,6 +1039,46 @@ rw_status rw_debug_trace_layered(rw_context* ctx, const rw_layers* layers,
   a.tag = kForwardTag;
   RW_HIP(ctx, launch_trace(a, kLayeredModel, words, n_paths, n_blocks, unit_index, events,
                            path_out, nullptr, reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+rw_status rw_lut_loss_grad(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* targets,
+                           int64_t n_units, int32_t n_media, const float* params, float* grad,
+                           float* loss, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  LutArgs a;
+  rw_status st = lut_args(ctx, lut, targets, n_units, n_media, params, &a);
+  if (st != RW_OK) return st;
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  a.grad = grad;
+  a.loss = loss;
+  RW_HIP(ctx, launch_lut(a, n_media, reinterpret_cast<hipStream_t>(stream)));
+  return RW_OK;
+}
+
+rw_status rw_lut_fit_step(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* targets,
+                          int64_t n_units, int32_t n_media, float* params, float* adam_m,
+                          float* adam_v, int32_t step, float lr, float* loss, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  LutArgs a;
+  rw_status st = lut_args(ctx, lut, targets, n_units, n_media, params, &a);
+  if (st != RW_OK) return st;
+  if (!adam_m || !adam_v) return fail(ctx, RW_E_INVALID, "Adam moments must be non-NULL");
+  if (step < 1) return fail(ctx, RW_E_INVALID, "step must be >= 1");
+  if (!(lr >= 0.0f) || !(lr < 1e30f)) return fail(ctx, RW_E_INVALID, "lr must be finite and >= 0");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  a.params_out = params;
+  a.adam_m = adam_m;
+  a.adam_v = adam_v;
+  a.adam = 1;
+  a.step = step;
+  a.lr = lr;
+  a.loss = loss;
+  RW_HIP(ctx, launch_lut(a, n_media, reinterpret_cast<hipStream_t>(stream)));
   return RW_OK;
 }
 

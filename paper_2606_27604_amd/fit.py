@@ -254,7 +254,8 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
     start = draw(n_targets, seed + 1, device)
     t1 = time.perf_counter()
     (s, a, g, w), hist = L.fit(table, tg["R_noisy"], tg["Pd_noisy"], tg["mass"], start, r,
-                                iters=iters, lr=lr, schedule=schedule, init_k1_iters=init_k1_iters)
+                                iters=iters, lr=lr, schedule=schedule, init_k1_iters=init_k1_iters,
+                                ctx=ctx)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t1
     with torch.no_grad():

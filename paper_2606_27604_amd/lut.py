@@ -14,8 +14,11 @@ profile is
     R_d_fit(r) = sum_k w_k R(alpha_k, g_k) P(r | alpha_k, g_k, sigma_t_k),
 with R bilinear in (alpha, g) and P trilinear in (alpha, g, log r), the radial
 coordinate scaled by sigma_t as above.  The loss is eq. joint_loss (lambda_R =
-5) and the optimiser Adam.  The interpolation and loss are differentiable torch
-code on the GPU; the tables come from the walk kernel.
+5) and the optimiser Adam.  Each optimisation step is one fused HIP kernel
+(rw_lut_fit_step: the lookups, the loss, its analytic gradient and the Adam
+update, one wavefront per unit); the tables come from the walk kernel.
+lookup_R, lookup_P and mixture_profile evaluate the same model with torch
+tensor operations (for inspection and plots).
 
 Readings: the grid is uniform in alpha over [0, alpha_max] and in g over
 [0, g_max] (the paper gives the size, not the spacing); radial interpolation is
@@ -164,31 +167,67 @@ def mixture_profile(lut: LUT, sigma_t, albedo, g, w, r):
 K1_SPREAD = (0.5, 1.0, 2.0, 4.0)
 
 
-def _adam(lut, P, R_t, Pd_t, mass_t, r, iters, lr, schedule, lambda_R, hist, tag):
-    from .fit import joint_loss
+def _native_tables(lut: LUT):
+    """rw_lut view of the tables (float32, contiguous; the tensors are kept in
+    the returned tuple)."""
+    R = lut.R.float().contiguous()
+    Pd = lut.Pd.float().contiguous()
+    c = rw.RwLutC(R.data_ptr(), Pd.data_ptr(), lut.alpha.numel(), lut.g.numel(), lut.n_bins,
+                  float(lut.alpha[-1]), float(lut.g[-1]), lut.r_min, lut.r_max)
+    return c, (R, Pd)
 
-    opt = torch.optim.Adam(P.parameters(), lr=lr)
+
+def _native_targets(R_t, Pd_t, mass_t, r, lambda_R: float):
+    from .fit import MIN_BIN_MASS, SHAPE_FLOOR
+
+    R = R_t.float().contiguous()
+    Pd = Pd_t.float().contiguous()
+    mass = mass_t.float().contiguous()
+    rr = r.float().contiguous()
+    c = rw.RwLutTargetsC(R.data_ptr(), Pd.data_ptr(), mass.data_ptr(), rr.data_ptr(), rr.numel(),
+                         float(lambda_R), MIN_BIN_MASS, SHAPE_FLOOR)
+    return c, (R, Pd, mass, rr)
+
+
+def raw_from_physical(sigma_t, albedo, g, w) -> torch.Tensor:
+    """Raw parameters [4K - 1, n] float32 of rw_lut_fit_step: log sigma_t,
+    logit alpha, logit(g / 0.99), K - 1 logits (the last is 0); the same
+    parameterisation and clamps as fit.Params."""
+    K = sigma_t.shape[0]
+    al = albedo.double().clamp(1e-4, 1 - 1e-4)
+    gg = (g.double() / 0.99).clamp(1e-4, 1 - 1e-4)
+    lw = torch.log(w.double().clamp_min(1e-8))
+    rows = [torch.log(sigma_t.double()), torch.log(al / (1 - al)), torch.log(gg / (1 - gg)),
+            lw[:K - 1] - lw[K - 1:]]
+    return torch.cat(rows, 0).float().contiguous()
+
+
+def physical_from_raw(params: torch.Tensor, K: int):
+    p = params.double()
+    logits = torch.cat([p[3 * K:], torch.zeros_like(p[:1])], 0)
+    return (torch.exp(p[:K]), torch.sigmoid(p[K:2 * K]), 0.99 * torch.sigmoid(p[2 * K:3 * K]),
+            torch.softmax(logits, 0))
+
+
+def _adam_native(ctx, tabs, tg, params, K, iters, lr, schedule, hist, tag):
+    n = params.shape[1]
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.empty(n, dtype=torch.float32, device=params.device)
     for it in range(iters):
-        if schedule == "cosine":
-            for grp in opt.param_groups:
-                grp["lr"] = 0.5 * lr * (1.0 + math.cos(math.pi * it / iters))
-        opt.zero_grad(set_to_none=True)
-        s, a, gg, lg = P.physical()
-        w = torch.softmax(lg, 0)
-        R_hat, Rd = mixture_profile(lut, s.float(), a.float(), gg.float(), w.float(), r)
-        Pd = Rd / R_hat.clamp_min(1e-12)[:, None]
-        loss_u = joint_loss(R_hat.double(), Pd.double(), R_t, Pd_t, mass_t, lambda_R=lambda_R)
-        loss_u.sum().backward()
-        opt.step()
+        lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * it / iters)) if schedule == "cosine" else lr
+        rw.rw_lut_fit_step(ctx, tabs[0], tg[0], n, K, params, m, v, it + 1, lr_t, loss)
         if it == 0 or it == iters - 1 or it % 20 == 0:
-            hist.append((tag, it, float(loss_u.detach().mean())))
+            hist.append((tag, it, float(loss.double().mean())))
 
 
 def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
         start, r: torch.Tensor, iters: int = 200, lr: float = 1e-2, schedule: str = "constant",
-        init_k1_iters: int = 0):
+        init_k1_iters: int = 0, ctx: rw.Context | None = None):
     """Adam over (log sigma_t, logit alpha, logit g / 0.99, K - 1 free logits)
-    per unit on eq. joint_loss with the LUT model (Sec. 4.2, "Optimization").
+    per unit on eq. joint_loss with the LUT model (Sec. 4.2, "Optimization"),
+    one fused HIP kernel launch per step (rw_lut_fit_step: lookups, loss,
+    analytic gradient and the Adam update).
 
     start: (sigma_t, albedo, g, w) [K, n], used as given when init_k1_iters = 0.
     schedule "cosine" anneals the learning rate as 0.5 lr (1 + cos(pi t / T)).
@@ -198,23 +237,25 @@ def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
     with sigma_t scaled by 0.5, 1, 2 (, 4) and equal weights, since identical
     components would stay identical under a symmetric loss.
     Returns the fitted physical parameters and the loss history
-    [(stage, iteration, mean loss)]."""
-    from .fit import LAMBDA_R, Params  # same parameterisation and loss
+    [(stage, iteration, mean loss before the step)]."""
+    from .fit import LAMBDA_R
 
     dev = R_t.device
+    if ctx is None:
+        ctx = rw.Context(dev.index or 0)
+    tabs = _native_tables(lut)
     hist = []
+    K, n = start[0].shape
     if init_k1_iters > 0:
-        K, n = start[0].shape
         one = torch.ones((1, n), dtype=torch.float64, device=dev)
-        P1 = Params(one, 0.9 * one, 0.5 * one, one).to(dev)
-        _adam(lut, P1, R_t, Pd_t, mass_t, r, init_k1_iters, lr, schedule, 0.0, hist, "k1")
-        with torch.no_grad():
-            s1, a1, g1, _ = P1.physical()
-            f = torch.tensor(K1_SPREAD[:K], dtype=torch.float64, device=dev)[:, None]
-            start = (s1 * f, a1.expand(K, n).clone(), g1.expand(K, n).clone(),
-                     torch.full((K, n), 1.0 / K, dtype=torch.float64, device=dev))
-    P = Params(*start).to(dev)
-    _adam(lut, P, R_t, Pd_t, mass_t, r, iters, lr, schedule, LAMBDA_R, hist, "mix")
-    with torch.no_grad():
-        s, a, gg, lg = P.physical()
-        return (s, a, gg, torch.softmax(lg, 0)), hist
+        p1 = raw_from_physical(one, 0.9 * one, 0.5 * one, one)
+        tg1 = _native_targets(R_t, Pd_t, mass_t, r, 0.0)
+        _adam_native(ctx, tabs, tg1, p1, 1, init_k1_iters, lr, schedule, hist, "k1")
+        s1, a1, g1, _ = physical_from_raw(p1, 1)
+        f = torch.tensor(K1_SPREAD[:K], dtype=torch.float64, device=dev)[:, None]
+        start = (s1 * f, a1.expand(K, n), g1.expand(K, n),
+                 torch.full((K, n), 1.0 / K, dtype=torch.float64, device=dev))
+    params = raw_from_physical(*start)
+    tg = _native_targets(R_t, Pd_t, mass_t, r, LAMBDA_R)
+    _adam_native(ctx, tabs, tg, params, K, iters, lr, schedule, hist, "mix")
+    return physical_from_raw(params, K), hist

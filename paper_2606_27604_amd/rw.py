@@ -75,6 +75,33 @@ class RwLayersC(ctypes.Structure):
     ]
 
 
+class RwLutC(ctypes.Structure):
+    _fields_ = [
+        ("R", ctypes.c_void_p),
+        ("Pd", ctypes.c_void_p),
+        ("n_alpha", ctypes.c_int32),
+        ("n_g", ctypes.c_int32),
+        ("n_bins", ctypes.c_int32),
+        ("alpha_max", ctypes.c_float),
+        ("g_max", ctypes.c_float),
+        ("r_min_mm", ctypes.c_float),
+        ("r_max_mm", ctypes.c_float),
+    ]
+
+
+class RwLutTargetsC(ctypes.Structure):
+    _fields_ = [
+        ("R", ctypes.c_void_p),
+        ("Pd", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("r_mm", ctypes.c_void_p),
+        ("n_r", ctypes.c_int32),
+        ("lambda_R", ctypes.c_float),
+        ("min_mass", ctypes.c_float),
+        ("shape_floor", ctypes.c_float),
+    ]
+
+
 class RwTallyC(ctypes.Structure):
     _fields_ = [
         ("R", ctypes.c_void_p),
@@ -97,7 +124,7 @@ EXPORTS = [
     "rw_create", "rw_destroy", "rw_last_error", "rw_status_string", "rw_forward",
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
     "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
-    "rw_debug_trace_layered",
+    "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
 ]
 
 _lib = None
@@ -149,6 +176,11 @@ def load_library(path: str = LIB_PATH):
     L.rw_debug_trace_layered.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, i64, u64,
                                          ctypes.c_uint32, vp, vp, vp]
     L.rw_debug_trace_layered.restype = ctypes.c_int
+    L.rw_lut_loss_grad.argtypes = [vp, P(RwLutC), P(RwLutTargetsC), i64, i32, vp, vp, vp, vp]
+    L.rw_lut_loss_grad.restype = ctypes.c_int
+    L.rw_lut_fit_step.argtypes = [vp, P(RwLutC), P(RwLutTargetsC), i64, i32, vp, vp, vp, i32,
+                                  ctypes.c_float, vp, vp]
+    L.rw_lut_fit_step.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -448,6 +480,33 @@ def rw_debug_trace_layered(ctx: Context, layers: Layers, geom: Geometry, words, 
                                                      int(n_blocks), int(seed), int(unit_index),
                                                      _ptr(events), _ptr(path_out),
                                                      _stream(stream)))
+
+
+def rw_lut_loss_grad(ctx: Context, lut: RwLutC, targets: RwLutTargetsC, n_units: int,
+                     n_media: int, params, grad=None, loss=None, stream=None):
+    P = 4 * n_media - 1
+    _need(params, torch.float32, (P, n_units), "params")
+    if grad is not None:
+        _need(grad, torch.float32, (P, n_units), "grad")
+    if loss is not None:
+        _need(loss, torch.float32, (n_units,), "loss")
+    ctx._check(load_library().rw_lut_loss_grad(ctx.h, ctypes.byref(lut), ctypes.byref(targets),
+                                               int(n_units), int(n_media), _ptr(params),
+                                               _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def rw_lut_fit_step(ctx: Context, lut: RwLutC, targets: RwLutTargetsC, n_units: int,
+                    n_media: int, params, adam_m, adam_v, step: int, lr: float, loss=None,
+                    stream=None):
+    P = 4 * n_media - 1
+    for name, t in (("params", params), ("adam_m", adam_m), ("adam_v", adam_v)):
+        _need(t, torch.float32, (P, n_units), name)
+    if loss is not None:
+        _need(loss, torch.float32, (n_units,), "loss")
+    ctx._check(load_library().rw_lut_fit_step(ctx.h, ctypes.byref(lut), ctypes.byref(targets),
+                                              int(n_units), int(n_media), _ptr(params),
+                                              _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                                              _ptr(loss), _stream(stream)))
 
 
 def rw_debug_philox(ctx: Context, ctr, key: int, out, stream=None):

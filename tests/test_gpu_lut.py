@@ -15,6 +15,7 @@ from oracle import closed_forms as cf
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+from paper_2606_27604_amd import rw  # noqa: E402
 from tests.gpu_common import ctx, np64  # noqa: E402
 
 
@@ -97,3 +98,92 @@ def test_mixture_one_hot_and_lut_fit_lowers_loss():
     k1 = [h for h in hist if h[0] == "k1"]
     mix = [h for h in hist if h[0] == "mix"]
     assert k1[-1][2] < k1[0][2] and mix[-1][2] < mix[0][2], hist
+
+
+def _smooth_problem(K=3, n=64, seed=4):
+    """A smooth synthetic table on the GPU, targets from its own model at
+    random parameters, and a random raw start (tests.test_lut_cpu's table)."""
+    from paper_2606_27604_amd import lut as L
+    from tests.test_lut_cpu import _smooth_table
+    t, r = _smooth_table()
+    t = L.LUT(t.alpha.cuda(), t.g.cuda(), t.R.cuda(), t.Pd.cuda(), t.r_min, t.r_max, t.n_rel,
+              t.paths)
+    r = r.cuda()
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    truth = (10 ** (torch.rand((K, n), generator=gen, device="cuda") - 0.5),
+             0.5 + 0.45 * torch.rand((K, n), generator=gen, device="cuda"),
+             0.8 * torch.rand((K, n), generator=gen, device="cuda"),
+             torch.softmax(torch.randn((K, n), generator=gen, device="cuda"), 0))
+    R_t, Rd_t = L.mixture_profile(t, *truth, r)
+    Pd_t = (Rd_t / R_t[:, None]).double()
+    lr_ = torch.log(r.double())
+    h = float(lr_[1] - lr_[0])
+    edges = torch.exp(torch.cat([lr_ - 0.5 * h, lr_[-1:] + 0.5 * h]))
+    mass = Pd_t * math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    start = (10 ** (torch.rand((K, n), generator=gen, device="cuda") - 0.5),
+             0.5 + 0.45 * torch.rand((K, n), generator=gen, device="cuda"),
+             0.8 * torch.rand((K, n), generator=gen, device="cuda"),
+             torch.softmax(torch.randn((K, n), generator=gen, device="cuda"), 0))
+    return t, r, R_t.double(), Pd_t, mass, start
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_lut_kernel_loss_and_gradient_match_autograd(K):
+    from paper_2606_27604_amd import lut as L
+    from tests.lut_reference import loss_reference
+    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=K)
+    n = R_t.numel()
+    params = L.raw_from_physical(*start)
+    tabs = L._native_tables(t)
+    tg = L._native_targets(R_t, Pd_t, mass, r, 5.0)
+    grad = torch.zeros_like(params)
+    loss = torch.zeros(n, dtype=torch.float32, device="cuda")
+    rw.rw_lut_loss_grad(ctx(), tabs[0], tg[0], n, K, params, grad, loss)
+    torch.cuda.synchronize()
+    p64 = params.double().clone().requires_grad_(True)
+    ref = loss_reference(t, p64, K, R_t, Pd_t, mass, r)
+    ref.sum().backward()
+    np.testing.assert_allclose(np64(loss), np64(ref.detach()), rtol=2e-4, atol=1e-6)
+    G, Gr = np64(grad), np64(p64.grad)
+    scale = np.abs(Gr).max(axis=0, keepdims=True)
+    np.testing.assert_allclose(G, Gr, rtol=3e-3, atol=1e-3 * float(scale.max()))
+
+
+def test_lut_kernel_adam_steps_match_torch_adam():
+    from paper_2606_27604_amd import lut as L
+    from tests.lut_reference import loss_reference
+    K = 3
+    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=K, n=32, seed=5)
+    n = R_t.numel()
+    params = L.raw_from_physical(*start)
+    ref = params.double().clone().requires_grad_(True)
+    opt = torch.optim.Adam([ref], lr=1e-2)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    tabs = L._native_tables(t)
+    tg = L._native_targets(R_t, Pd_t, mass, r, 5.0)
+    for step in (1, 2, 3):
+        rw.rw_lut_fit_step(ctx(), tabs[0], tg[0], n, K, params, m, v, step, 1e-2)
+        opt.zero_grad()
+        loss_reference(t, ref, K, R_t, Pd_t, mass, r).sum().backward()
+        opt.step()
+        torch.cuda.synchronize()
+        # each Adam step moves a parameter by at most ~lr; the two agree to a
+        # small fraction of that (tiny gradients, whose step is eps-limited,
+        # may differ)
+        d = np.abs(np64(params) - np64(ref.detach()))
+        assert np.quantile(d, 0.98) <= 1e-3 * step, np.quantile(d, 0.98)
+
+
+def test_native_fit_follows_the_reference_fit():
+    from paper_2606_27604_amd import lut as L
+    from tests.lut_reference import fit_reference
+    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=3, n=48, seed=6)
+    (s1, a1, g1, w1), h1 = L.fit(t, R_t, Pd_t, mass, start, r, iters=60, lr=2e-2,
+                                 schedule="cosine", init_k1_iters=30, ctx=ctx())
+    (s2, a2, g2, w2), h2 = fit_reference(t, R_t, Pd_t, mass, start, r, iters=60, lr=2e-2,
+                                         schedule="cosine", init_k1_iters=30)
+    l1 = np.array([h[2] for h in h1])
+    l2 = np.array([h[2] for h in h2])
+    assert [h[:2] for h in h1] == [h[:2] for h in h2]
+    np.testing.assert_allclose(l1, l2, rtol=5e-2)
+    assert l1[-1] < l1[[i for i, h in enumerate(h1) if h[0] == "mix"][0]]

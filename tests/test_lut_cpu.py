@@ -82,7 +82,9 @@ def _smooth_table(na=64, ng=32, nb=160):
 
 
 def test_fit_k1_start_and_cosine_schedule_lower_the_loss():
-    from paper_2606_27604_amd import fit as F
+    """The fit's schedule and K = 1 start, on the autograd reference that the
+    GPU kernel is checked against."""
+    from tests.lut_reference import fit_reference
 
     t, r = _smooth_table()
     gen = torch.Generator().manual_seed(4)
@@ -97,8 +99,8 @@ def test_fit_k1_start_and_cosine_schedule_lower_the_loss():
     edges = torch.exp(torch.cat([lr - 0.5 * h, lr[-1:] + 0.5 * h]))
     mass = Pd_t * math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
     start = tuple(x.clone() for x in truth)
-    (s, a, g, w), hist = L.fit(t, R_t.double(), Pd_t, mass, start, r, iters=80, lr=5e-2,
-                               schedule="cosine", init_k1_iters=40)
+    (s, a, g, w), hist = fit_reference(t, R_t.double(), Pd_t, mass, start, r, iters=80, lr=5e-2,
+                                       schedule="cosine", init_k1_iters=40)
     k1 = [h for h in hist if h[0] == "k1"]
     mix = [h for h in hist if h[0] == "mix"]
     assert k1[-1][2] < 0.5 * k1[0][2], hist
