@@ -100,6 +100,42 @@ def load_traffic(kernel_name: str):
     return e.get("bytes_per_launch")
 
 
+def load_counters(kernel_name: str):
+    """rocprofv3 VALU counters of the kernel (profiles/valu_counters.json): the
+    primary utilisation definition (issue-busy x active-lane fraction), used
+    only while the kernel sources still hash to the profiled version."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel_name)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return {k: e[k] for k in ("issue_busy", "active_lane_fraction", "exec_weighted_utilisation",
+                              "transcendental_share", "transcendental_rate_fraction")}
+
+
+def host_cpu():
+    """Cores this process may use (at most 16, the host share of one GPU) and
+    the CPU model."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, min(cores, 16)), model
+
+
 def micro(args):
     import ctypes
 
@@ -132,11 +168,7 @@ def cpu_baseline(wl, seed, max_seconds=30.0):
     pass takes 8 s (or reaches the workload's 2^20)."""
     from oracle import oracle as O
 
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))  # the host share of one GPU
+    cores, model = host_cpu()
     paths = 1 << 16
     geo = O.Geometry(n_media=3, n_rel=wl.n_rel, n_bins=wl.n_bins)
     total_v, total_t = 0, 0.0
@@ -154,6 +186,7 @@ def cpu_baseline(wl, seed, max_seconds=30.0):
             break
         paths *= 2
     return {"value": total_v / total_t, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "per_core": total_v / total_t / cores, "cpu_model": model,
             "sample": f"81 wavelengths x {paths} paths (forward + adjoint), FP64, "
                       f"{total_v} vertices in {total_t:.2f} s"}
 
@@ -322,10 +355,13 @@ def main():
         "device_flags": flags,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": traffic, "kernel": dom,
-                     "slots_per_vertex": slots,
-                     "note": "algorithmic VALU lane-slots (ops x measured issue cost) per second "
-                             "against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; traffic = HBM bytes "
-                             "per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated)"},
+                     "slots_per_vertex": slots, "counters": load_counters(dom),
+                     "note": "achieved = algorithmic VALU lane-slots (ops x measured issue cost) "
+                             "per second against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; traffic = "
+                             "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated); "
+                             "counters = rocprofv3 SQ counters of the same kernel (exec-weighted "
+                             "VALU utilisation = issue-busy x active-lane fraction; transcendental "
+                             "lane-ops/s over their measured peak)"},
     }
     if plain is not None:
         pv = sum(plain["vf"]) + sum(plain["va"])
@@ -570,11 +606,7 @@ def layered_cpu_baseline(wl, max_seconds=30.0):
     doubled from 2^10 until one pass takes 8 s."""
     from oracle import oracle as O
 
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores, model = host_cpu()
     sub = wl.subset(np.arange(wl.n_wl))
     geo = O.Geometry(n_media=2, n_rel=float(np.float32(wl.n_rel)), n_bins=wl.n_bins)
     paths = 1 << 10
@@ -588,6 +620,7 @@ def layered_cpu_baseline(wl, max_seconds=30.0):
             break
         paths *= 2
     return {"value": float(vert.sum()) / dt, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "per_core": float(vert.sum()) / dt / cores, "cpu_model": model,
             "sample": f"one tone x 81 wavelengths x {paths} photons, FP64, "
                       f"{int(vert.sum())} vertices in {dt:.2f} s"}
 
@@ -597,11 +630,7 @@ def lut_cpu_baseline(N, n_cells=256, max_seconds=30.0):
     count doubled from 2^10 until one pass takes 8 s."""
     from oracle import oracle as O
 
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores, model = host_cpu()
     rng = np.random.default_rng(123)
     ia, ig = rng.integers(0, N, n_cells), rng.integers(0, N, n_cells)
     al = np.float32(np.linspace(0.0, 0.999, N, dtype=np.float32)[ia])[None].astype(np.float64)
@@ -620,6 +649,7 @@ def lut_cpu_baseline(N, n_cells=256, max_seconds=30.0):
             break
         paths *= 2
     return {"value": float(vert.sum()) / dt, "unit": "vertices/s", "cores": cores, "kind": "oracle",
+            "per_core": float(vert.sum()) / dt / cores, "cpu_model": model,
             "sample": f"{n_cells} random cells of the {N}x{N} grid x {paths} photons, FP64, "
                       f"{int(vert.sum())} vertices in {dt:.2f} s"}
 
