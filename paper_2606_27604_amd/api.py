@@ -91,6 +91,25 @@ def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, c
     return grad, sumsq, vert, flags
 
 
+def jacobian(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int,
+             batched: bool = True, stream=None):
+    """Per-slot Jacobian of the forward sums: J[u][s][j] = d(sum of x over the
+    paths of unit u that exit in slot s)/d theta_j (raw sums, layout of
+    rw_adjoint's gradient), one path replay per slot with a one-hot bin
+    cotangent.  The total-R row is J.sum(1)."""
+    n, nb2, P = media.n_units, geom.n_bins + 2, 4 * geom.n_media
+    dev = media.sigma_t.device
+    J = torch.empty((n, nb2, P), dtype=torch.float64, device=dev)
+    cot = torch.zeros((n, nb2), dtype=torch.float32, device=dev)
+    for s in range(nb2):
+        cot.zero_()
+        cot[:, s] = 1.0
+        grad, _, _, flags = adjoint(ctx, media, geom, paths, seed, cot_bins=cot, batched=batched,
+                                    stream=stream)
+        J[:, s, :] = grad
+    return J
+
+
 class RWReflectance(torch.autograd.Function):
     """Differentiable mixture-of-media reflectance.
 

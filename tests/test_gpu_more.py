@@ -392,3 +392,26 @@ def test_full_size_adjoint_sweep_sampled_units_vs_oracle():
     # the softmax logits' gradients sum to zero in every unit
     gr = np64(grad)
     assert np.allclose(gr[:, 9:12].sum(1), 0.0, atol=1e-6 * np.abs(gr).max())
+
+
+def test_per_slot_jacobian_matches_oracle():
+    """The full per-slot Jacobian (n_bins + 2 slots x 12 parameters) from
+    one-hot-cotangent replays against the oracle's FP64 Jacobian on the same
+    streams; its slot sum is the total-R gradient."""
+    wl = workloads.config2(paths=1 << 16)
+    sub = wl.subset(np.array([3, 40]))
+    m = media(sub.sigma_t, sub.albedo, sub.g, sub.weight)
+    g, og = geoms(3, sub.n_rel, n_bins=32)
+    N = sub.paths_per_unit
+    J = np64(api.jacobian(ctx(), m, g, N, 17))
+    _, _, jR, jB = O.adjoint(og, sub.sigma_t, sub.albedo, sub.g, sub.weight, N, 17,
+                             cot_R=np.zeros(2), jacobian=True)
+    assert J.shape == jB.shape == (2, 34, 12)
+    # same random numbers: every entry agrees to a small fraction of the entry
+    # scale of its unit and parameter (a rare FP32/FP64 parting moves a few paths)
+    scale = np.abs(jB).max(axis=1, keepdims=True) + 1e-300
+    assert np.quantile(np.abs(J - jB) / scale, 0.99) <= 2e-3
+    np.testing.assert_allclose(J.sum(1), jR, rtol=2e-3, atol=2e-3 * np.abs(jR).max())
+    cR = torch.ones(2, dtype=torch.float32, device="cuda")
+    grad, _, _, _ = api.adjoint(ctx(), m, g, N, 17, cot_R=cR)
+    np.testing.assert_allclose(J.sum(1), np64(grad), rtol=1e-9, atol=1e-9 * np.abs(J).max())
