@@ -29,6 +29,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    "-Wshadow",
     "-Wno-unused-result",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # tally atomics come from one or two lanes at a time: plain atomics, not

@@ -230,9 +230,9 @@ __device__ __forceinline__ void exit_global_adjoint(const WalkArgs& a, const Wav
                                                     const Path& p, uint32_t nv) {
   if (ev == EV_EXIT_TOP) {
     const ColdConst cc = read_cold(L);
-    const int slot = radial_slot(p.x, p.y, cc);
+    const int b = radial_slot(p.x, p.y, cc);
     float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
-    if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + slot];
+    if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + b];
     const double c = double(p.W) * double(cot);
     if (c != 0.0) {
       const double css = c * double(p.D), csa = c * double(score_alpha(p)),

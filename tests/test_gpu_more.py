@@ -308,6 +308,44 @@ def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     assert np.all(np.abs(tot) <= 4 * tot_se + 1e-9), tot / tot_se
 
 
+def test_adjoint_paths_outliving_their_wave_visit():
+    """Many small units, so that each wave of the persistent launch takes
+    several of them and paths of a unit are still running when the wave moves
+    on to the next: those paths tally straight into their own unit's slot.
+    The batched gradient must equal the static launch's (one unit per wave,
+    no such paths) to FP64 rounding, unit by unit and with bin cotangents, and
+    sampled units must match the oracle on the same streams."""
+    rng = np.random.default_rng(61)
+    K, n = 3, 24576
+    s = rng.uniform(0.5, 5.0, (K, n))
+    a = rng.uniform(0.5, 0.999, (K, n))
+    gg = rng.uniform(0.0, 0.9, (K, n))
+    w = rng.dirichlet(np.ones(K), n).T
+    m = media(s, a, gg, w)
+    g, og = geoms(K, 1.4, n_bins=32)
+    cR = rng.standard_normal(n).astype(np.float32)
+    cB = rng.standard_normal((n, g.n_bins + 2)).astype(np.float32)
+    kw = dict(cot_R=torch.from_numpy(cR).cuda(), cot_bins=torch.from_numpy(cB).cuda())
+    N = 64
+    ref = api.adjoint(ctx(), m, g, N, 21, batched=False, **kw)
+    for use_graph in (True, False):
+        got = api.adjoint(ctx(), m, g, N, 21, use_graph=use_graph, **kw)
+        assert rw.rw_check(ctx(), got[3]) == 0
+        assert torch.equal(got[2], ref[2])
+        G, R = np64(got[0]), np64(ref[0])
+        ratio = np.abs(G - R) / (1e-9 * (np.abs(R) + np.abs(R).max(0)))
+        assert ratio.max() <= 1.0, (ratio.max(), np.unravel_index(ratio.argmax(), R.shape))
+        np.testing.assert_allclose(np64(got[1]), np64(ref[1]), rtol=1e-9)
+    f = lambda x: x.astype(np.float32)  # noqa: E731
+    for u in (0, 1, 777, 12345, n - 1):
+        og_, osq = O.adjoint(og, f(s[:, u]), f(a[:, u]), f(gg[:, u]), f(w[:, u]), N, 21,
+                             cot_R=cR[u:u + 1], cot_bins=cB[u:u + 1], unit_base=u)
+        mg, sg = mean_se(np64(ref[0])[u], np64(ref[1])[u], N)
+        mo, so = mean_se(og_[0], osq[0], N)
+        z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+        assert np.all(np.abs(z) <= 3.5), (u, z)
+
+
 def test_adjoint_workload_subset_vs_oracle_gradient():
     """Sets of the adjoint workload (K = 3, 81 wavelengths, 2^14 paths, v_R = 1,
     v_bins ~ N(0, 1)) against the oracle's FP64 score gradient, same streams."""
