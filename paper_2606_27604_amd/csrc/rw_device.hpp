@@ -82,7 +82,7 @@ __device__ __forceinline__ Medium make_medium(float sigma_t, float alb, float g)
   return m;
 }
 
-// Henyey-Greenstein cos(theta) from u, by inverting its CDF.  The textbook
+// Henyey-Greenstein 1 - cos(theta) from u, by inverting its CDF.  The textbook
 // inversion mu = (1 + g^2 - tau^2) / (2g), tau = (1 - g^2) / (1 + g t),
 // t = 2u - 1, cancels badly in FP32 for g near 1; factoring tau^2 - (1-g)^2
 // gives the equivalent
@@ -90,28 +90,22 @@ __device__ __forceinline__ Medium make_medium(float sigma_t, float alb, float g)
 // a product of positive terms (accurate to a few ulp for every g and u, exact
 // isotropic limit).  Also returns (1 + g t)^2, which equals
 // (1 - g^2)^2 / (1 + g^2 - 2 g mu) and feeds the g score without a division.
-__device__ __forceinline__ float hg_cos(const Medium& m, float u, float& den, float& sin_t) {
-  const float b = fmaf(m.g, fmaf(2.0f, u, -1.0f), 1.0f);
+__device__ __forceinline__ float hg_omm(float g, float hq, float u, float& den) {
+  const float b = fmaf(g, fmaf(2.0f, u, -1.0f), 1.0f);
   den = b * b;
-  const float omm = fminf(m.hq * (1.0f - u) * fmaf(m.g, u, 1.0f) * __builtin_amdgcn_rcpf(den), 2.0f);
-  // sin(theta) from (1 - mu)(1 + mu): no cancellation near mu = 1
-  sin_t = __builtin_amdgcn_sqrtf(omm * (2.0f - omm));
-  return 1.0f - omm;
+  return fminf(hq * (1.0f - u) * fmaf(g, u, 1.0f) * __builtin_amdgcn_rcpf(den), 2.0f);
 }
 
-// New direction at polar cosine mu (sin_t = sin(theta)) about (ux, uy, uz)
-// and azimuth 2*pi*u2 measured from the first tangent of the Duff et al.
-// (JCGT 2017) frame: t1 = (1 + s ux^2 a, s ux uy a, -s ux),
-// t2 = (ux uy a, s + uy^2 a, -uy) with s = sign(uz), a = -1/(s + uz).
-// Renormalised in FP32.
-__device__ __forceinline__ void scatter(float& ux, float& uy, float& uz, float mu, float st,
-                                        float u2) {
-  const float cp = __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
-  const float sp = __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
+// New direction mu u + p t1 + q t2 about u = (ux, uy, uz): polar cosine mu,
+// (p, q) = sin(theta) (cos phi, sin phi) with the azimuth phi measured from the
+// first tangent of the Duff et al. (JCGT 2017) frame:
+// t1 = (1 + s ux^2 a, s ux uy a, -s ux), t2 = (ux uy a, s + uy^2 a, -uy) with
+// s = sign(uz), a = -1/(s + uz).  Renormalised in FP32.
+__device__ __forceinline__ void rotate(float& ux, float& uy, float& uz, float mu, float p,
+                                       float q) {
   const float s = copysignf(1.0f, uz);
   const float a = -__builtin_amdgcn_rcpf(s + uz);
   const float b = ux * uy * a;
-  const float p = st * cp, q = st * sp;
   const float t1x = fmaf(s * ux * ux, a, 1.0f), t1y = s * b, t1z = -s * ux;
   const float t2x = b, t2y = fmaf(uy * uy, a, s), t2z = -uy;
   float nx = fmaf(p, t1x, fmaf(q, t2x, mu * ux));
@@ -384,15 +378,39 @@ __device__ __forceinline__ void start_path_lds(Path& p, uint4 w, const float* ta
   if (geo.incidence) cosine_entry(p, w, geo);
 }
 
+// The parts of a vertex fixed by its random words and the path's medium
+// alone, not by the path's position or direction: the flight length s, the
+// Henyey-Greenstein cosine mu with the g-score factor den, the components
+// (p, q) = sin(theta) (cos phi, sin phi) of the new direction in the plane
+// normal to the old one, and the word of the Fresnel / roulette decision.
+struct VertexDraw {
+  float s, mu, p, q, den;
+  uint32_t w3;
+};
+
+__device__ __forceinline__ VertexDraw draw_vertex(float flight, float g, float hq, uint4 w) {
+  VertexDraw d;
+  d.s = -__builtin_amdgcn_logf(u01(w.x)) * flight;
+  const float omm = hg_omm(g, hq, u01(w.y), d.den);
+  // sin(theta) from (1 - mu)(1 + mu): no cancellation near mu = 1
+  const float st = __builtin_amdgcn_sqrtf(omm * (2.0f - omm));
+  d.mu = 1.0f - omm;
+  const float u2 = u01(w.z);
+  d.p = st * __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
+  d.q = st * __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
+  d.w3 = w.w;
+  return d;
+}
+
 template <bool ADJ>
-__device__ __forceinline__ int collide(Path& p, uint4 w, const WalkGeom& geo, float s, float zn);
+__device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkGeom& geo, float zn);
 
 // vertex v >= 1: flight, then boundary interaction or collision.  Returns the
 // vertex event.  ADJ adds the score bookkeeping (collisions, flight length,
 // g score).
 template <bool ADJ>
-__device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo) {
-  const float s = -__builtin_amdgcn_logf(u01(w.x)) * p.m.flight;
+__device__ __forceinline__ int vertex_step_drawn(Path& p, const VertexDraw& d, const WalkGeom& geo) {
+  const float s = d.s;
   const float zn = fmaf(s, p.uz, p.z);
   const bool top = (p.uz < 0.0f) && (zn <= 0.0f);
   const bool bottom = geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
@@ -404,21 +422,27 @@ __device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo
     if (ADJ) p.D -= db;
     if (!geo.index_matched) {
       const float F = fresnel(fabsf(p.uz), geo.n_rel, geo.n_rel2);
-      if (u01(w.w) < F) {
+      if (u01(d.w3) < F) {
         p.uz = -p.uz;
         return EV_REFLECT;
       }
     }
     return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
   }
-  return collide<ADJ>(p, w, geo, s, zn);
+  return collide<ADJ>(p, d, geo, zn);
+}
+
+template <bool ADJ>
+__device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo) {
+  return vertex_step_drawn<ADJ>(p, draw_vertex(p.m.flight, p.m.g, p.m.hq, w), geo);
 }
 
 // Collision at the end of a flight of length s (new depth zn): implicit
 // capture (A += W (1 - alpha), W *= alpha), roulette, Henyey-Greenstein
 // scattering.
 template <bool ADJ>
-__device__ __forceinline__ int collide(Path& p, uint4 w, const WalkGeom& geo, float s, float zn) {
+__device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkGeom& geo, float zn) {
+  const float s = d.s;
   p.x = fmaf(s, p.ux, p.x);
   p.y = fmaf(s, p.uy, p.y);
   p.z = zn;
@@ -429,16 +453,14 @@ __device__ __forceinline__ int collide(Path& p, uint4 w, const WalkGeom& geo, fl
   p.A = fmaf(p.W, 1.0f - p.m.alb, p.A);
   p.W *= p.m.alb;
   if (p.W < geo.rr_weight) {
-    if (u01(w.w) < geo.rr_survive) {
+    if (u01(d.w3) < geo.rr_survive) {
       p.W *= geo.rr_boost;
     } else {
       return EV_RR_KILL;
     }
   }
-  float den, st;
-  const float mu = hg_cos(p.m, u01(w.y), den, st);
-  if (ADJ) p.Sg = fmaf((mu - p.m.g) * den, p.m.gq, p.Sg);
-  scatter(p.ux, p.uy, p.uz, mu, st, u01(w.z));
+  if (ADJ) p.Sg = fmaf((d.mu - p.m.g) * d.den, p.m.gq, p.Sg);
+  rotate(p.ux, p.uy, p.uz, d.mu, d.p, d.q);
   return EV_COLLIDE;
 }
 
@@ -521,7 +543,8 @@ __device__ __forceinline__ void start_path_layers(Path& p, uint4 w, const LayerP
 
 // vertex v >= 1 of a two-layer path
 __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkGeom& geo) {
-  const float s = -__builtin_amdgcn_logf(u01(w.x)) * p.m.flight;
+  const VertexDraw d = draw_vertex(p.m.flight, p.m.g, p.m.hq, w);
+  const float s = d.s;
   const float zn = fmaf(s, p.uz, p.z);
   const bool top_layer = p.k == 0;
   // the face of the current layer this flight reaches: 1 surface, 2 interface,
@@ -534,7 +557,7 @@ __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkG
     if (p.uz < 0.0f && zn <= p.d) face = 2;
     else if (geo.slab && p.uz > 0.0f && zn >= geo.slab_mm) face = 3;
   }
-  if (face == 0) return collide<false>(p, w, geo, s, zn);
+  if (face == 0) return collide<false>(p, d, geo, zn);
   const float zf = face == 1 ? 0.0f : (face == 2 ? p.d : geo.slab_mm);
   const float db = (zf - p.z) * __builtin_amdgcn_rcpf(p.uz);
   p.x = fmaf(db, p.ux, p.x);

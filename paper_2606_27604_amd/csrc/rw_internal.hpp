@@ -100,8 +100,16 @@ struct WalkArgs {
 // per-wave LDS of the walk kernel (8-byte words): accumulators (forward:
 // (x, x^2) per slot + T, A, vertices; adjoint: K media x 8 FP64 sums +
 // vertices), the media table, the cold constants, the exit ring (kExitRing
-// records of 16 bytes forward, 32 bytes adjoint; a power of two, >= 64)
+// records of 16 bytes forward, 32 bytes adjoint; a power of two, >= 64).  The
+// end of the walk reuses the ring for kWave vertex draws of kTailDrawFloats
+// floats each, stored as arrays of one field.
 constexpr int kExitRing = 64;
+constexpr int kTailDrawFloats(bool adjoint) { return adjoint ? 6 : 5; }
+constexpr int walk_ring_words(bool adjoint) {
+  return kExitRing * (adjoint ? 4 : 2) > kWave * kTailDrawFloats(adjoint) / 2
+             ? kExitRing * (adjoint ? 4 : 2)
+             : kWave * kTailDrawFloats(adjoint) / 2;
+}
 constexpr int kMediaTableWords = (kMediaTableFloats + 1) / 2;
 constexpr int kColdConstWords = 4;  // 32 bytes after the media table
 // bound on the forward slot workspace of one call (bytes)
@@ -109,7 +117,7 @@ constexpr int64_t kMaxSlotBytes = int64_t(1) << 30;
 inline int forward_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
 inline int adjoint_acc_words(int K) { return 8 * K + 2; }
 inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {
-  return acc_words + kMediaTableWords + kColdConstWords + kExitRing * (adjoint ? 4 : 2);
+  return acc_words + kMediaTableWords + kColdConstWords + walk_ring_words(adjoint);
 }
 
 // Lookup-table fit (rw_lut.hip): tables, targets, raw parameters [4K-1][n_units]

@@ -340,6 +340,19 @@ __device__ __forceinline__ bool stage_any(const WalkArgs& a, int64_t u, float* t
   }
 }
 
+// Draw i of the tail's LDS arrays (field f at dr[f * kWave + i]).
+template <bool ADJ>
+__device__ __forceinline__ VertexDraw load_draw(const float* dr, uint32_t i) {
+  VertexDraw d;
+  d.s = dr[i];
+  d.mu = dr[kWave + i];
+  d.p = dr[2 * kWave + i];
+  d.q = dr[3 * kWave + i];
+  d.w3 = __float_as_uint(dr[4 * kWave + i]);
+  d.den = ADJ ? dr[5 * kWave + i] : 0.0f;
+  return d;
+}
+
 template <int K, bool ADJ, bool LAYERED>
 __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
   static_assert(!(ADJ && LAYERED), "the two-layer walk is forward only");
@@ -501,15 +514,19 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
   }
 
   // ---- tail: the paths still running after the last one was handed out ----
-  // A wave here holds a few long paths and little else, and one iteration of
-  // it is bound by the latency of its dependent chain (Philox rounds, then the
-  // vertex step).  The idle lanes take the Philox blocks off that chain: each
-  // round, lane l computes the block of vertex v + (l mod d) of the
-  // (l / d)-th running path (d = 64 / running paths, rounded to a power of
-  // two) into LDS, and every running path then takes d steps, reading one
-  // block per step.  Ending paths tally directly (few lanes).
+  // A wave here holds at most kWave / 2 running paths (the loop above hands
+  // over at half occupancy) and little else, and one iteration of it is bound
+  // by the latency of a vertex's dependent chain.  The idle lanes take off
+  // that chain what does not depend on the path's state: each round, lane l
+  // draws vertex v + (l mod d) of the (l / d)-th running path (d = 64 / running
+  // paths, rounded to a power of two) into LDS, and every running path then
+  // takes d steps, reading one draw per step.  In the mixture walk, whose
+  // medium is fixed from the start, a draw is the whole VertexDraw (flight
+  // length, scattering cosine and azimuth); the two-layer walk, whose medium
+  // changes at the interface, stores the Philox block.  Ending paths tally
+  // directly (few lanes).
   if (__ballot(alive) != 0) {
-    while (head != tail) {  // the ring's LDS is reused for the blocks
+    while (head != tail) {  // the ring's LDS is reused for the draws
       const uint32_t n = (tail - head) < uint32_t(kWave) ? (tail - head) : uint32_t(kWave);
       if (!ADJ) tally_forward(L, head, n, lane);
       else tally_adjoint<K>(a, L, uint32_t(u_cur), head, n, lane);
@@ -517,7 +534,16 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
     }
     __builtin_amdgcn_s_setprio(3);
     boosted = true;
-    uint4* blk = reinterpret_cast<uint4*>(L.ring);  // kWave blocks of 16 bytes
+    // a path handed out just before the loop above ended starts here, so that
+    // every running path has its medium
+    if (alive && v == 0) {
+      start_any<K, LAYERED>(p, philox(0u, path, a.tag, lctr, ks), L.media, L.cold->entry_weight,
+                            geo);
+      v = 1;
+    }
+    uint4* blk = reinterpret_cast<uint4*>(L.ring);
+    // draws as arrays of one field: field f of draw i at dr[f * kWave + i]
+    float* dr = reinterpret_cast<float*>(L.ring);
     for (;;) {
       const uint64_t am = __ballot(alive);
       if (am == 0) break;
@@ -526,34 +552,53 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
                         : na <= 16 ? 2u : na <= 32 ? 1u : 0u;
       const uint32_t rank = lane_rank(am);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (alive) blk[rank] = make_uint4(path, v, lctr, 0u);
+      if (alive) {
+        blk[rank] = make_uint4(path, v, lctr, __float_as_uint(p.m.flight));
+        if constexpr (!LAYERED)
+          blk[kWave / 2 + rank] = make_uint4(__float_as_uint(p.m.g), __float_as_uint(p.m.hq), 0u, 0u);
+      }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       const uint32_t j = uint32_t(lane) >> lg;
       const uint32_t t = uint32_t(lane) & ((1u << lg) - 1u);
-      uint4 q = make_uint4(0u, 0u, 0u, 0u);
-      if (j < na) q = blk[j];
+      uint4 q = make_uint4(0u, 0u, 0u, 0u), mq = q;
+      if (j < na) {
+        q = blk[j];
+        if constexpr (!LAYERED) mq = blk[kWave / 2 + j];
+      }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (j < na) blk[lane] = philox(q.y + t, q.x, a.tag, q.z, ks);
+      if (j < na) {
+        const uint4 w = philox(q.y + t, q.x, a.tag, q.z, ks);
+        if constexpr (LAYERED) {
+          blk[lane] = w;
+        } else {
+          const VertexDraw d = draw_vertex(__uint_as_float(q.w), __uint_as_float(mq.x),
+                                           __uint_as_float(mq.y), w);
+          dr[lane] = d.s;
+          dr[kWave + lane] = d.mu;
+          dr[2 * kWave + lane] = d.p;
+          dr[3 * kWave + lane] = d.q;
+          dr[4 * kWave + lane] = __uint_as_float(d.w3);
+          if (ADJ) dr[5 * kWave + lane] = d.den;
+        }
+      }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       const uint32_t depth = 1u << lg;
       for (uint32_t s = 0; s < depth; ++s) {
         if (__ballot(alive) == 0) break;
         if (alive) {
-          const uint4 w = blk[(rank << lg) + s];
-          int ev = EV_COLLIDE;
-          if (v == 0) {
-            start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
-            v = 1;
+          const uint32_t i = (rank << lg) + s;
+          int ev;
+          if constexpr (LAYERED) {
+            ev = step_any<ADJ, LAYERED>(p, blk[i], geo);
           } else {
-            ev = step_any<ADJ, LAYERED>(p, w, geo);
-            if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
-              ev = EV_CAP;
-              capped = true;
-            }
-            if (ev >= EV_EXIT_TOP) alive = false;
-            else ++v;
+            ev = vertex_step_drawn<ADJ>(p, load_draw<ADJ>(dr, i), geo);
+          }
+          if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+            ev = EV_CAP;
+            capped = true;
           }
           if (ev >= EV_EXIT_TOP) {
+            alive = false;
             if (lslot == uint32_t(cur_slot)) {
               if (!ADJ) {
                 tally_forward_record(L, read_cold(L), forward_record(ev, p, v));
@@ -566,6 +611,8 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
               if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
               else exit_global_adjoint<K>(a, L, lslot, lunit, ev, p, v);
             }
+          } else {
+            ++v;
           }
         }
       }
