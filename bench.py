@@ -57,16 +57,17 @@ ISSUE_PEAK = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ  # lane-slots / s
 #   free flight: log, 1 mul, 1 fma; surface test: 2 compares;
 #   collision: position 2 fma, absorbed-weight fma + sub, weight mul, roulette
 #     compare; Henyey-Greenstein inversion ~12 ops + rcp; scattering frame and
-#     rotation ~30 ops + sqrt, sin, cos, rsq;
-#   surface hit (about 1 vertex in 20): distance rcp + 3 ops, Fresnel ~12 ops +
-#     sqrt + 2 rcp.
+#     rotation ~30 ops + sqrt, sin, cos and the frame's rcp, renormalised by one
+#     Newton fma;
+#   surface hit (about 1 vertex in 20): distance rcp + 3 ops, Fresnel ~15 ops +
+#     sqrt + rcp.
 # The adjoint adds the score bookkeeping: flight-length sum (2), collision
 # count (1), g-score fma chain (2).
 ALG_MAD64_PER_VERTEX = 20
 ALG_XOR3_PER_VERTEX = 20
-ALG_FP32_PER_VERTEX = 65          # add/mul/fma/compare/select/convert, incl. word->float
+ALG_FP32_PER_VERTEX = 66          # add/mul/fma/compare/select/convert, incl. word->float
 ALG_FP32_ADJ_EXTRA = 5
-ALG_TRANS_PER_VERTEX = 6.2        # log, rcp, sqrt, sin, cos, rsq + 1/20 x (3 at a surface hit)
+ALG_TRANS_PER_VERTEX = 6.15       # log, 2 rcp, sqrt, sin, cos + 1/20 x (3 at a surface hit)
 COST_MAD64, COST_XOR3, COST_TRANS = 1.21, 1.07, 2.33   # measured issue costs (FMA = 1)
 
 

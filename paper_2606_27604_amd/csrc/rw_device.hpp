@@ -111,7 +111,9 @@ __device__ __forceinline__ void rotate(float& ux, float& uy, float& uz, float mu
   float nx = fmaf(p, t1x, fmaf(q, t2x, mu * ux));
   float ny = fmaf(p, t1y, fmaf(q, t2y, mu * uy));
   float nz = fmaf(p, t1z, fmaf(q, t2z, mu * uz));
-  const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+  // |n|^2 = mu^2 + sin^2(theta) = 1 up to rounding for a unit u, so one
+  // Newton step of 1/sqrt from 1 renormalises to second order
+  const float inv = fmaf(-0.5f, fmaf(nx, nx, fmaf(ny, ny, nz * nz)), 1.5f);
   ux = nx * inv;
   uy = ny * inv;
   uz = nz * inv;
@@ -125,8 +127,11 @@ __device__ __forceinline__ float fresnel(float ci, float n, float n2) {
   if (st2 >= 1.0f) return 1.0f;
   const float ct = __builtin_amdgcn_sqrtf(1.0f - st2);
   const float nci = n * ci, nct = n * ct;
-  const float rs = (nci - ct) * __builtin_amdgcn_rcpf(nci + ct);
-  const float rp = (ci - nct) * __builtin_amdgcn_rcpf(ci + nct);
+  // one reciprocal for both ratios (both denominators lie in (0, 2n + 2])
+  const float ds = nci + ct, dp = ci + nct;
+  const float inv = __builtin_amdgcn_rcpf(ds * dp);
+  const float rs = (nci - ct) * dp * inv;
+  const float rp = (ci - nct) * ds * inv;
   return 0.5f * fmaf(rs, rs, rp * rp);
 }
 
