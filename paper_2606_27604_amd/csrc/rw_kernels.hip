@@ -398,6 +398,94 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
   bool alive = false, capped = false;
   uint32_t path = 0, v = 0, lunit = 0, lslot = 0, lctr = 0;
 
+  // A look-ahead round for the lanes with `sel` set (running paths, at most
+  // kWave / 2 of them, vertex >= 1), used where one path's dependent chain
+  // sets the pace.  The idle lanes take off that chain what does not depend
+  // on the path's state: lane l draws vertex v + (l mod d) of the (l / d)-th
+  // selected path (d = 64 / selected paths, rounded to a power of two) into
+  // LDS, and every selected path then takes d steps, reading one draw per
+  // step.  In the mixture walk, whose medium is fixed from the start, a draw
+  // is the whole VertexDraw (flight length, scattering cosine and azimuth);
+  // the two-layer walk, whose medium changes at the interface, stores the
+  // Philox block.  Ending paths tally directly (few lanes).  The exit ring
+  // must be empty: its LDS holds the draws.
+  auto lookahead_round = [&](bool sel) {
+    uint4* blk = reinterpret_cast<uint4*>(L.ring);
+    // draws as arrays of one field: field f of draw i at dr[f * kWave + i]
+    float* dr = reinterpret_cast<float*>(L.ring);
+    const uint64_t am = __ballot(sel);
+    const uint32_t na = uint32_t(__popcll(am));
+    const uint32_t lg = na <= 1 ? 6u : na <= 2 ? 5u : na <= 4 ? 4u : na <= 8 ? 3u
+                      : na <= 16 ? 2u : na <= 32 ? 1u : 0u;
+    const uint32_t rank = lane_rank(am);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (sel) {
+      blk[rank] = make_uint4(path, v, lctr, __float_as_uint(p.m.flight));
+      if constexpr (!LAYERED)
+        blk[kWave / 2 + rank] = make_uint4(__float_as_uint(p.m.g), __float_as_uint(p.m.hq), 0u, 0u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t j = uint32_t(lane) >> lg;
+    const uint32_t t = uint32_t(lane) & ((1u << lg) - 1u);
+    uint4 q = make_uint4(0u, 0u, 0u, 0u), mq = q;
+    if (j < na) {
+      q = blk[j];
+      if constexpr (!LAYERED) mq = blk[kWave / 2 + j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (j < na) {
+      const uint4 w = philox(q.y + t, q.x, a.tag, q.z, ks);
+      if constexpr (LAYERED) {
+        blk[lane] = w;
+      } else {
+        const VertexDraw d = draw_vertex(__uint_as_float(q.w), __uint_as_float(mq.x),
+                                         __uint_as_float(mq.y), w);
+        dr[lane] = d.s;
+        dr[kWave + lane] = d.mu;
+        dr[2 * kWave + lane] = d.p;
+        dr[3 * kWave + lane] = d.q;
+        dr[4 * kWave + lane] = __uint_as_float(d.w3);
+        if (ADJ) dr[5 * kWave + lane] = d.den;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t depth = 1u << lg;
+    for (uint32_t s = 0; s < depth; ++s) {
+      if (__ballot(sel) == 0) break;
+      if (sel) {
+        const uint32_t i = (rank << lg) + s;
+        int ev;
+        if constexpr (LAYERED) {
+          ev = step_any<ADJ, LAYERED>(p, blk[i], geo);
+        } else {
+          ev = vertex_step_drawn<ADJ>(p, load_draw<ADJ>(dr, i), geo);
+        }
+        if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+          ev = EV_CAP;
+          capped = true;
+        }
+        if (ev >= EV_EXIT_TOP) {
+          sel = false;
+          alive = false;
+          if (lslot == uint32_t(cur_slot)) {
+            if (!ADJ) {
+              tally_forward_record(L, read_cold(L), forward_record(ev, p, v));
+            } else {
+              float4 r0, r1;
+              adjoint_record(ev, p, v, r0, r1);
+              tally_adjoint_record(a, L, lunit, r0, r1);
+            }
+          } else {
+            if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
+            else exit_global_adjoint<K>(a, L, lslot, lunit, ev, p, v);
+          }
+        } else {
+          ++v;
+        }
+      }
+    }
+  };
+
   for (;;) {
     // Idle lanes take the next path indices of the current item.  When the
     // item is used up, the wave moves to the next item of a valid unit (paths
@@ -515,16 +603,9 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
 
   // ---- tail: the paths still running after the last one was handed out ----
   // A wave here holds at most kWave / 2 running paths (the loop above hands
-  // over at half occupancy) and little else, and one iteration of it is bound
-  // by the latency of a vertex's dependent chain.  The idle lanes take off
-  // that chain what does not depend on the path's state: each round, lane l
-  // draws vertex v + (l mod d) of the (l / d)-th running path (d = 64 / running
-  // paths, rounded to a power of two) into LDS, and every running path then
-  // takes d steps, reading one draw per step.  In the mixture walk, whose
-  // medium is fixed from the start, a draw is the whole VertexDraw (flight
-  // length, scattering cosine and azimuth); the two-layer walk, whose medium
-  // changes at the interface, stores the Philox block.  Ending paths tally
-  // directly (few lanes).
+  // over at half occupancy) and little else, so its iterations are bound by
+  // the latency of a vertex's dependent chain: it finishes them in look-ahead
+  // rounds.
   if (__ballot(alive) != 0) {
     while (head != tail) {  // the ring's LDS is reused for the draws
       const uint32_t n = (tail - head) < uint32_t(kWave) ? (tail - head) : uint32_t(kWave);
@@ -541,82 +622,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
                             geo);
       v = 1;
     }
-    uint4* blk = reinterpret_cast<uint4*>(L.ring);
-    // draws as arrays of one field: field f of draw i at dr[f * kWave + i]
-    float* dr = reinterpret_cast<float*>(L.ring);
-    for (;;) {
-      const uint64_t am = __ballot(alive);
-      if (am == 0) break;
-      const uint32_t na = uint32_t(__popcll(am));
-      const uint32_t lg = na <= 1 ? 6u : na <= 2 ? 5u : na <= 4 ? 4u : na <= 8 ? 3u
-                        : na <= 16 ? 2u : na <= 32 ? 1u : 0u;
-      const uint32_t rank = lane_rank(am);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (alive) {
-        blk[rank] = make_uint4(path, v, lctr, __float_as_uint(p.m.flight));
-        if constexpr (!LAYERED)
-          blk[kWave / 2 + rank] = make_uint4(__float_as_uint(p.m.g), __float_as_uint(p.m.hq), 0u, 0u);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      const uint32_t j = uint32_t(lane) >> lg;
-      const uint32_t t = uint32_t(lane) & ((1u << lg) - 1u);
-      uint4 q = make_uint4(0u, 0u, 0u, 0u), mq = q;
-      if (j < na) {
-        q = blk[j];
-        if constexpr (!LAYERED) mq = blk[kWave / 2 + j];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (j < na) {
-        const uint4 w = philox(q.y + t, q.x, a.tag, q.z, ks);
-        if constexpr (LAYERED) {
-          blk[lane] = w;
-        } else {
-          const VertexDraw d = draw_vertex(__uint_as_float(q.w), __uint_as_float(mq.x),
-                                           __uint_as_float(mq.y), w);
-          dr[lane] = d.s;
-          dr[kWave + lane] = d.mu;
-          dr[2 * kWave + lane] = d.p;
-          dr[3 * kWave + lane] = d.q;
-          dr[4 * kWave + lane] = __uint_as_float(d.w3);
-          if (ADJ) dr[5 * kWave + lane] = d.den;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      const uint32_t depth = 1u << lg;
-      for (uint32_t s = 0; s < depth; ++s) {
-        if (__ballot(alive) == 0) break;
-        if (alive) {
-          const uint32_t i = (rank << lg) + s;
-          int ev;
-          if constexpr (LAYERED) {
-            ev = step_any<ADJ, LAYERED>(p, blk[i], geo);
-          } else {
-            ev = vertex_step_drawn<ADJ>(p, load_draw<ADJ>(dr, i), geo);
-          }
-          if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
-            ev = EV_CAP;
-            capped = true;
-          }
-          if (ev >= EV_EXIT_TOP) {
-            alive = false;
-            if (lslot == uint32_t(cur_slot)) {
-              if (!ADJ) {
-                tally_forward_record(L, read_cold(L), forward_record(ev, p, v));
-              } else {
-                float4 r0, r1;
-                adjoint_record(ev, p, v, r0, r1);
-                tally_adjoint_record(a, L, lunit, r0, r1);
-              }
-            } else {
-              if (!ADJ) exit_global_forward(a, L, lslot, ev, p, v);
-              else exit_global_adjoint<K>(a, L, lslot, lunit, ev, p, v);
-            }
-          } else {
-            ++v;
-          }
-        }
-      }
-    }
+    while (__ballot(alive) != 0) lookahead_round(alive);
   }
   if (boosted) __builtin_amdgcn_s_setprio(0);
   if (u_cur >= 0) flush_unit<K, ADJ>(a, L, head, tail, cur_slot, u_cur, lane);
