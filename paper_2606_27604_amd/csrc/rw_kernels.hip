@@ -30,9 +30,19 @@ constexpr uint32_t kLongPath = 256;
 // vertex steps per pass of the walk loop's schedule (regeneration, ballots,
 // exit ring): more steps spread that bookkeeping over more vertices, at the
 // cost of lanes that end early in a pass idling for its remaining steps
-constexpr int kStepsPerIteration = 3;
+constexpr int kStepsPerIteration = 4;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// The stream tag is Philox's third counter word and the same for every vertex
+// of a launch, so the compiler hoists its first-round product out of the walk
+// loop; that 64-bit value is then spilled and reloaded with v_readlane at
+// every block.  An empty asm makes the tag opaque at each call: the product
+// is recomputed with two scalar multiplies instead.
+__device__ __forceinline__ uint32_t opaque_tag(uint32_t tag) {
+  asm volatile("" : "+s"(tag));
+  return tag;
+}
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
@@ -434,7 +444,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (j < na) {
-      const uint4 w = philox(q.y + t, q.x, a.tag, q.z, ks);
+      const uint4 w = philox(q.y + t, q.x, opaque_tag(a.tag), q.z, ks);
       if constexpr (LAYERED) {
         blk[lane] = w;
       } else {
@@ -557,7 +567,7 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
 #pragma unroll
     for (int rep = 0; rep < kStepsPerIteration; ++rep) {
       if (alive) {
-        const uint4 w = philox(v, path, a.tag, lctr, ks);
+        const uint4 w = philox(v, path, opaque_tag(a.tag), lctr, ks);
         if (v == 0) {
           start_any<K, LAYERED>(p, w, L.media, L.cold->entry_weight, geo);
           v = 1;
