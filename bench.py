@@ -53,7 +53,8 @@ ISSUE_PEAK = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ  # lane-slots / s
 # FP32 FMA, as measured by `bench.py --micro` on the MI355X
 # (profiles/issue_rates_micro.md).
 #   random numbers: one Philox4x32-10 block = 10 rounds x (2 32x32->64
-#     multiply-adds + 2 three-input XORs); 4 word->float conversions (2 ops each);
+#     multiply-adds + 2 three-input XORs, one v_bitop3_b32 each); 4 word->float
+#     conversions (2 ops each);
 #   free flight: log, 1 mul, 1 fma; surface test: 2 compares;
 #   collision: position 2 fma, absorbed-weight fma + sub, weight mul, roulette
 #     compare; Henyey-Greenstein inversion ~12 ops + rcp; scattering frame and
@@ -68,7 +69,7 @@ ALG_XOR3_PER_VERTEX = 20
 ALG_FP32_PER_VERTEX = 66          # add/mul/fma/compare/select/convert, incl. word->float
 ALG_FP32_ADJ_EXTRA = 5
 ALG_TRANS_PER_VERTEX = 6.15       # log, 2 rcp, sqrt, sin, cos + 1/20 x (3 at a surface hit)
-COST_MAD64, COST_XOR3, COST_TRANS = 1.21, 1.07, 2.33   # measured issue costs (FMA = 1)
+COST_MAD64, COST_XOR3, COST_TRANS = 1.18, 1.15, 2.27   # measured issue costs (FMA = 1)
 
 
 def alg_slots_per_vertex(adjoint: bool) -> float:

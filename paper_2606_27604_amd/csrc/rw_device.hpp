@@ -16,7 +16,8 @@ namespace rw {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round is two
-// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs.  The
+// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs (one
+// v_bitop3_b32 each).  The
 // key schedule k + r * (0x9E3779B9, 0xBB67AE85) is wave-uniform; it is
 // recomputed with scalar adds inside every call (the empty asm makes the base
 // key opaque, so the compiler cannot hoist the ten round keys out of the walk
@@ -30,6 +31,15 @@ __device__ __forceinline__ PhiloxKey philox_schedule(uint32_t k0, uint32_t k1) {
   return PhiloxKey{k0, k1};
 }
 
+// a ^ b ^ k in one instruction: gfx950's three-input bitwise operation with
+// the truth table of a three-way XOR (0x96).  Left to itself the compiler
+// emits two v_xor_b32 per three-way XOR, twenty per Philox block.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         const PhiloxKey& key) {
   uint32_t k0 = key.k0, k1 = key.k1;
@@ -38,8 +48,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
     const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
-    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3(uint32_t(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3(uint32_t(p0 >> 32), c3, k1);
     c1 = uint32_t(p1);
     c3 = uint32_t(p0);
     c0 = n0;

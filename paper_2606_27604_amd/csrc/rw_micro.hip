@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) micro_kernel(int iters, uint32_t seed, ui
         const uint64_t t = uint64_t(uint32_t(q[c])) * 0xD2511F53u + q[c];
         q[c] = uint64_t(uint32_t(t)) * 0xCD9E8D57u + t;
       }
-      if (OP == OP_XOR3) w[c] = w[c] ^ w[(c + 3) & (kChains - 1)] ^ 0x9E3779B9u;
+      if (OP == OP_XOR3) w[c] = rw::xor3(w[c], w[(c + 3) & (kChains - 1)], ks.k0);
       if (OP == OP_LOG) f[c] = __builtin_amdgcn_logf(f[c]);
       if (OP == OP_SIN) f[c] = __builtin_amdgcn_sinf(f[c]);
       if (OP == OP_RCP) f[c] = __builtin_amdgcn_rcpf(f[c]);
