@@ -24,7 +24,8 @@ enum Op : int {
   OP_RSQ = 7,
   OP_MULHI = 8,
   OP_PHILOX = 9,
-  OP_COUNT = 10
+  OP_LOG_MIX = 10,  // four FMAs then one log per chain: a transcendental amid VALU work
+  OP_COUNT = 11
 };
 
 template <int OP>
@@ -57,6 +58,9 @@ __global__ void __launch_bounds__(256) micro_kernel(int iters, uint32_t seed, ui
       if (OP == OP_SQRT) f[c] = __builtin_amdgcn_sqrtf(f[c]);
       if (OP == OP_RSQ) f[c] = __builtin_amdgcn_rsqf(f[c]);
       if (OP == OP_MULHI) w[c] = __umulhi(w[c], 0xCD9E8D57u);
+      if (OP == OP_LOG_MIX)
+        f[c] = __builtin_amdgcn_logf(
+            fmaf(fmaf(fmaf(fmaf(f[c], 0.999f, 1e-3f), 0.999f, 1e-3f), 0.999f, 1e-3f), 0.999f, 2.0f));
       if (OP == OP_PHILOX && c == 0) {
         const uint4 r = rw::philox(w[0], w[1], w[2], w[3], ks);
         w[0] = r.x; w[1] = r.y; w[2] = r.z; w[3] = r.w;
@@ -94,6 +98,7 @@ float rw_micro_run(int op, int grid, int iters, uint32_t* out) {
     MICRO_CASE(OP_RSQ)
     MICRO_CASE(OP_MULHI)
     MICRO_CASE(OP_PHILOX)
+    MICRO_CASE(OP_LOG_MIX)
 #undef MICRO_CASE
     default: return -2.0f;
   }
