@@ -6,15 +6,15 @@
 // longest-first unit order) and its lanes regenerate: a lane whose path ended
 // takes the next path index, from the current item or, once that is used up,
 // from the next item, so lanes never wait for the slowest path of an item.
-// Each loop iteration draws one Philox block per lane and processes one
-// vertex.
+// Each pass of the loop takes kStepsPerIteration vertex steps per lane, one
+// Philox block per vertex.
 //
 // Tallies.  The forward sums are exact integers (32-bit fixed point per
 // path, 64-bit counters), so they are bit-identical whatever the schedule,
 // the launch shape or the order of atomics; the adjoint sums are FP64.  The
-// wave's current unit accumulates in LDS (flushed to global memory with
-// atomics when the wave moves to another unit); paths of an earlier unit
-// still in flight add straight to global memory.
+// wave's current unit accumulates in LDS, stored into a slot of global memory
+// that only this wave writes when the wave moves to another unit; paths of an
+// earlier unit still in flight add straight to that unit's slot.
 #include <hip/hip_runtime.h>
 
 #include "../../include/rw.h"
