@@ -308,6 +308,24 @@ def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     assert np.all(np.abs(tot) <= 4 * tot_se + 1e-9), tot / tot_se
 
 
+@pytest.mark.parametrize("n,paths", [(24576, 64), (12288, 4096)])
+def test_forward_paths_outliving_their_wave_visit(n, paths):
+    """Forward counterpart of the test below: many units per wave, so that
+    paths end after their wave moved on and add to their own unit's slot
+    from global memory (one item per unit: the output rows themselves; two
+    items per unit: the slot workspace).  Batched tallies must equal the static
+    launch's bit for bit, unit by unit."""
+    rng = np.random.default_rng(62 + paths)
+    K = 3
+    m = media(rng.uniform(0.5, 5.0, (K, n)), rng.uniform(0.5, 0.999, (K, n)),
+              rng.uniform(0.0, 0.9, (K, n)), rng.dirichlet(np.ones(K), n).T)
+    g, _ = geoms(K, 1.4, n_bins=32)
+    ref = _run(m, g, paths, 23, batched=False)
+    for use_graph in (True, False):
+        got = _run(m, g, paths, 23, use_graph=use_graph)
+        assert _same_tally(got, ref)
+
+
 def test_adjoint_paths_outliving_their_wave_visit():
     """Many small units, so that each wave of the persistent launch takes
     several of them and paths of a unit are still running when the wave moves
