@@ -33,7 +33,8 @@ __device__ __forceinline__ PhiloxKey philox_schedule(uint32_t k0, uint32_t k1) {
 
 // a ^ b ^ k in one instruction: gfx950's three-input bitwise operation with
 // the truth table of a three-way XOR (0x96).  Left to itself the compiler
-// emits two v_xor_b32 per three-way XOR, twenty per Philox block.
+// emits two v_xor_b32 per three-way XOR, twenty per Philox block.  k must be
+// wave-uniform (it is a round key): the operand is a scalar register.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
   uint32_t r;
   asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
