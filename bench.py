@@ -73,6 +73,16 @@ ALG_TRANS_PER_VERTEX = 6.15       # log, 2 rcp, sqrt, sin, cos + 1/20 x (3 at a 
 COST_MAD64, COST_XOR3, COST_TRANS = 1.19, 1.16, 1.84
 
 
+# Secondary measure: algorithmic FP32 FLOP per collision vertex, an FMA
+# counting 2: 18 FMA, 23 mul, 10 add/sub/min and 6 transcendentals (counted 1
+# each) in the flight, capture, Henyey-Greenstein inversion and rotation, plus
+# about 1/20 of a surface hit's 15 ops.  Against the FP32 vector peak (which
+# assumes packed FMAs) the Philox integer work, which is not FLOPs, keeps this
+# low whatever the kernel does.
+ALG_FLOP_PER_VERTEX = 76.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
 def alg_slots_per_vertex(adjoint: bool) -> float:
     return (ALG_MAD64_PER_VERTEX * COST_MAD64 + ALG_XOR3_PER_VERTEX * COST_XOR3 +
             ALG_FP32_PER_VERTEX + (ALG_FP32_ADJ_EXTRA if adjoint else 0) +
@@ -361,6 +371,13 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": traffic, "kernel": dom,
                      "slots_per_vertex": slots, "counters": load_counters(dom),
+                     "secondary": {
+                         "measure": "algorithmic FP32 FLOP/s over the FP32 vector peak",
+                         "flop_per_vertex": ALG_FLOP_PER_VERTEX,
+                         "achieved_tflops": ALG_FLOP_PER_VERTEX * dom_v / (dom_ms * 1e-3) / 1e12,
+                         "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                         "frac": ALG_FLOP_PER_VERTEX * dom_v / (dom_ms * 1e-3) / 1e12
+                                 / FP32_VECTOR_PEAK_TFLOPS},
                      "note": "achieved = algorithmic VALU lane-slots (ops x measured issue cost) "
                              "per second against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; traffic = "
                              "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated); "
