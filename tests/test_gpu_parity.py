@@ -127,6 +127,23 @@ def test_forward_homogeneous_closed_form_and_oracle():
     assert np.all(np.abs(np64(res.vertices) - vert) <= 1e-3 * vert)
 
 
+def test_forward_homogeneous_bias_run_2_22_paths():
+    """The 16 homogeneous units (K = 1, g = 0, n = 1) at 2^22 paths each, a
+    standard error about 8x smaller than at 2^16: the estimates must still sit
+    on the closed-form plane albedo (Chandrasekhar's H function), so any bias
+    of the FP32 walk above ~1e-4 would show."""
+    wl = workloads.config1()
+    m = media(wl.sigma_t, wl.albedo, wl.g, wl.weight)
+    g, _ = geoms(1, 1.0)
+    res, flags = gpu_forward(m, g, 1 << 22, 1234)
+    assert flags == 0
+    R, se = np64(res.R), np64(res.R_se)
+    ref = np.array([cf.R_plane(float(a)) for a in wl.albedo[0]])
+    z = (R - ref) / se
+    assert np.all(np.abs(z) <= 3.5), z
+    assert np.all(se < 3e-4)
+
+
 def test_forward_mixture_81_wavelengths_vs_oracle():
     wl = workloads.config2(paths=1 << 16)
     m = media(wl.sigma_t, wl.albedo, wl.g, wl.weight)
