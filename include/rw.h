@@ -80,7 +80,9 @@ const char* rw_status_string(rw_status s);
 /* Geometry and estimator constants, copied by value into kernel arguments. */
 typedef struct {
   int32_t n_media;      /* K, 1..4 */
-  int32_t n_bins;       /* radial bins, 1..4096 (plus under/overflow slots) */
+  int32_t n_bins;       /* radial bins, 1..4096 (plus under/overflow slots); the
+                           walk keeps a per-wave histogram in LDS, so with many
+                           bins it runs fewer waves per workgroup */
   float n_rel;          /* refractive index of the medium over the outside, > 0;
                            1 = index-matched */
   float slab_mm;        /* <= 0: semi-infinite; > 0: slab of this thickness (T tallied) */

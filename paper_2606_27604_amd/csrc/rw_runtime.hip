@@ -45,6 +45,7 @@ struct GraphEntry {
 struct rw_context {
   int device = -1;          // -1: validation-only context (no device)
   int n_cu = 0;
+  int max_lds = 0;          // bytes of LDS a workgroup may allocate
   std::string last_error;
   void* workspace = nullptr;      // adjoint sums (128-bit) and vertex counts
   size_t workspace_bytes = 0;
@@ -346,6 +347,15 @@ rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_
   a.fix_cap = float(x_max * (1.0 - 0x1p-20));
   a.acc_words = adjoint ? adjoint_acc_words(P.K) : forward_acc_words(geom->n_bins);
   a.lds_words_per_wave = walk_lds_words_per_wave(a.acc_words, adjoint);
+  // fewer waves per workgroup when the per-wave LDS (mostly the radial
+  // histogram) would not fit a workgroup's allocation
+  if (ctx->device >= 0) {
+    while (P.cfg.waves_per_wg > 1 && walk_lds_bytes(a, P.cfg.waves_per_wg) > ctx->max_lds)
+      P.cfg.waves_per_wg /= 2;
+    if (walk_lds_bytes(a, 1) > ctx->max_lds)
+      return fail(ctx, RW_E_UNSUPPORTED, "%d bins need %d bytes of LDS per wave (device: %d)",
+                  geom->n_bins, walk_lds_bytes(a, 1), ctx->max_lds);
+  }
   return RW_OK;
 }
 
@@ -514,6 +524,7 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
   for (int chunk : chunks) {
     for (int wpw : wpws) {
       Plan P = base;
+      if (walk_lds_bytes(P.a, wpw) > ctx->max_lds) continue;
       P.cfg.chunk = chunk;
       P.cfg.waves_per_wg = wpw;
       P.cfg.wgs_per_cu = 0;
@@ -861,6 +872,12 @@ rw_status rw_create(rw_context** out, int hip_device) {
     return RW_E_HIP;
   }
   ctx->n_cu = prop.multiProcessorCount;
+  if (hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            hip_device) != hipSuccess ||
+      ctx->max_lds <= 0) {
+    delete ctx;
+    return RW_E_HIP;
+  }
   if (hipMalloc(&ctx->queue, 256) != hipSuccess) {
     delete ctx;
     return RW_E_NOMEM;

@@ -308,6 +308,33 @@ def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     assert np.all(np.abs(tot) <= 4 * tot_se + 1e-9), tot / tot_se
 
 
+def test_maximum_bin_count():
+    """4 096 bins, the largest the ABI accepts: the per-wave histogram then
+    exceeds a four-wave workgroup's LDS and the launch uses fewer waves per
+    workgroup.  The totals are exact integer sums of the same per-path values
+    as with 256 bins, so they agree bit for bit, and the slots add up to them."""
+    wl = workloads.config2(paths=1 << 14)
+    sub = wl.subset(np.arange(0, 81, 10))
+    m = media(sub.sigma_t, sub.albedo, sub.g, sub.weight)
+    g256, _ = geoms(3, sub.n_rel, n_bins=256)
+    g4k, _ = geoms(3, sub.n_rel, n_bins=4096)
+    for use_graph in (True, False):
+        a = _run(m, g256, sub.paths_per_unit, 31, use_graph=use_graph)
+        b = _run(m, g4k, sub.paths_per_unit, 31, use_graph=use_graph)
+        assert rw.rw_check(ctx(), a.flags) == 0 and rw.rw_check(ctx(), b.flags) == 0
+        assert torch.equal(a.R, b.R) and torch.equal(a.vertices, b.vertices)
+        bins = np64(b.bins)
+        np.testing.assert_allclose(bins[:, :, 0].sum(1), np64(b.R)[:, 0], rtol=1e-12)
+    plain = _run(m, g4k, sub.paths_per_unit, 31, batched=False)
+    assert _same_tally(plain, b)
+    # the adjoint's LDS does not grow with the bins: same gradient of R
+    cR = torch.ones(sub.n_units, dtype=torch.float32, device="cuda")
+    ga = api.adjoint(ctx(), m, g256, sub.paths_per_unit, 31, cot_R=cR)
+    gb = api.adjoint(ctx(), m, g4k, sub.paths_per_unit, 31, cot_R=cR)
+    ref = np64(ga[0])
+    np.testing.assert_allclose(np64(gb[0]), ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("n,paths", [(24576, 64), (12288, 4096)])
 def test_forward_paths_outliving_their_wave_visit(n, paths):
     """Forward counterpart of the test below: many units per wave, so that
