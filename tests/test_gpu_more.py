@@ -308,16 +308,18 @@ def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     assert np.all(np.abs(tot) <= 4 * tot_se + 1e-9), tot / tot_se
 
 
-def test_maximum_bin_count():
-    """4 096 bins, the largest the ABI accepts: the per-wave histogram then
-    exceeds a four-wave workgroup's LDS and the launch uses fewer waves per
-    workgroup.  The totals are exact integer sums of the same per-path values
-    as with 256 bins, so they agree bit for bit, and the slots add up to them."""
+@pytest.mark.parametrize("n_bins", [1, 4096])
+def test_extreme_bin_counts(n_bins):
+    """1 and 4 096 bins, the range the ABI accepts; at 4 096 the per-wave
+    histogram exceeds a four-wave workgroup's LDS and the launch uses fewer
+    waves per workgroup.  The totals are exact integer sums of the same
+    per-path values as with 256 bins, so they agree bit for bit, and the slots
+    add up to them."""
     wl = workloads.config2(paths=1 << 14)
     sub = wl.subset(np.arange(0, 81, 10))
     m = media(sub.sigma_t, sub.albedo, sub.g, sub.weight)
     g256, _ = geoms(3, sub.n_rel, n_bins=256)
-    g4k, _ = geoms(3, sub.n_rel, n_bins=4096)
+    g4k, _ = geoms(3, sub.n_rel, n_bins=n_bins)
     for use_graph in (True, False):
         a = _run(m, g256, sub.paths_per_unit, 31, use_graph=use_graph)
         b = _run(m, g4k, sub.paths_per_unit, 31, use_graph=use_graph)
