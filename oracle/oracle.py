@@ -151,6 +151,10 @@ def _bind(L):
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_int, dp, dp, i64p]
     L.orc_layered_forward.restype = ctypes.c_int
+    L.orc_layered_adjoint.argtypes = [gp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64, i64p,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_int, dp, dp, dp, dp]
+    L.orc_layered_adjoint.restype = ctypes.c_int
     L.orc_layered_trace.argtypes = [gp, dp, dp, dp, ctypes.c_double, ctypes.c_double, u32p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_uint32, dp, dp]
@@ -309,6 +313,34 @@ def layered_forward(geo: Geometry, sigma_t, albedo, g, thickness, n_bottom: floa
     if rc != 0:
         raise ValueError(f"orc_layered_forward failed with code {rc}")
     return tally, bins, vert
+
+
+def layered_adjoint(geo: Geometry, sigma_t, albedo, g, thickness, n_bottom: float, paths,
+                    seed: int, cot_R=None, cot_bins=None, tag: int = 0,
+                    n_threads: int | None = None, unit_base: int = 0):
+    """Score-function gradient sums of the two-layer walk (see
+    orc_layered_adjoint).  Returns (grad, sumsq) of shape [n_units, 8]:
+    sigma_t (top, bottom), albedo (top, bottom), g (top, bottom), 0, 0."""
+    sigma_t = np.asarray(sigma_t)
+    n_units = sigma_t.size // 2
+    s, a, gg = (_soa(v, 2, n_units) for v in (sigma_t, albedo, g))
+    d = np.ascontiguousarray(np.asarray(thickness, np.float64).reshape(n_units))
+    p = _paths(paths, n_units)
+    cR = None if cot_R is None else np.ascontiguousarray(np.asarray(cot_R, np.float64).reshape(n_units))
+    cB = None if cot_bins is None else np.ascontiguousarray(
+        np.asarray(cot_bins, np.float64).reshape(n_units, geo.n_bins + 2))
+    grad = np.zeros((n_units, 8))
+    sumsq = np.zeros((n_units, 8))
+    cg = geo.c()
+    rc = lib().orc_layered_adjoint(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(d),
+                                   float(n_bottom), n_units, _i64ptr(p), seed, tag, unit_base,
+                                   n_threads or default_threads(),
+                                   _dptr(cR) if cR is not None else None,
+                                   _dptr(cB) if cB is not None else None, _dptr(grad),
+                                   _dptr(sumsq))
+    if rc != 0:
+        raise ValueError(f"orc_layered_adjoint failed with code {rc}")
+    return grad, sumsq
 
 
 def layered_trace(geo: Geometry, sigma_t, albedo, g, thickness: float, n_bottom: float,

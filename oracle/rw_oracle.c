@@ -46,7 +46,10 @@
  * The same estimator also runs in the two-layer tissue of the paper's data
  * generator (Sec. 3: a top layer of given thickness over a semi-infinite
  * bottom layer, per-layer sigma_t, albedo, g and refractive index), see
- * walk_layers() for its readings at the interface.
+ * walk_layers() for its readings at the interface.  Its adjoint scores each
+ * layer with the flights, collisions and scatterings a path had in that
+ * layer (the path density factorises over the vertices, and each factor
+ * depends on one layer's parameters only).
  *
  * Everything is FP64.  Threads split the paths of a unit into fixed ranges;
  * partial sums are merged in range order, so results do not depend on the
@@ -257,6 +260,10 @@ typedef struct {
   int64_t n_coll;
   double L;        /* total length of all flight segments */
   double Sg;       /* sum of d ln p_HG / d g over the scattering vertices */
+  /* two-layer walk: the same three sums per layer (0 top, 1 bottom) */
+  int64_t n_coll_l[2];
+  double L_l[2];
+  double Sg_l[2];
 } path_result;
 
 /* fetch block v; returns 0 when an injected source has run out */
@@ -447,8 +454,8 @@ typedef struct {
  * law, and the next flight is drawn afresh in the other layer (the free-flight
  * distribution is memoryless, so stopping at the interface does not change
  * the path density).  The bottom layer's lower face (slab tests) has index
- * n[1] over the outside.  Forward only: no flight lengths are kept for an
- * adjoint. */
+ * n[1] over the outside.  For the adjoint the flight lengths, collisions and
+ * g-score terms are also kept per layer (n_coll_l, L_l, Sg_l). */
 static void walk_layers(const layer_params* lp, const orc_geometry* geo,
                         const block_source* src, path_result* res,
                         double* events, int64_t max_events) {
@@ -494,6 +501,7 @@ static void walk_layers(const layer_params* lp, const orc_geometry* geo,
 
     if (face) {
       const double db = (zf - p[2]) / d[2];
+      res->L_l[layer] += db;
       p[0] += db * d[0];
       p[1] += db * d[1];
       p[2] = zf;
@@ -536,7 +544,12 @@ static void walk_layers(const layer_params* lp, const orc_geometry* geo,
     }
 
     for (int i = 0; i < 3; ++i) p[i] += flight * d[i];
+    res->L_l[layer] += flight;
+    const int64_t nc0 = res->n_coll;
+    const double sg0 = res->Sg;
     const int end = collide(geo, lp->albedo[layer], lp->g[layer], u, d, &W, res);
+    res->n_coll_l[layer] += res->n_coll - nc0;
+    res->Sg_l[layer] += res->Sg - sg0;
     if (end != END_NONE) {
       res->end = end;
       put_event(events, max_events, v, end == END_ABSORBED ? EV_ABSORB : EV_RR_KILL, p, d,
@@ -673,11 +686,21 @@ static void run_task(job_t* job, int64_t t) {
     } else {
       if (!tallied_top || r.x == 0.0) continue;
       for (int j = 0; j < P; ++j) score[j] = 0.0;
-      int k = r.k;
-      score[k] = (double)r.n_coll / up.sigma_t[k] - r.L;
-      score[K + k] = (r.n_coll == 0) ? 0.0 : (double)r.n_coll / up.albedo[k];
-      score[2 * K + k] = r.Sg;
-      for (int j = 0; j < K; ++j) score[3 * K + j] = (j == k ? 1.0 : 0.0) - up.w[j];
+      if (job->layered) {
+        /* each layer scores the flights, collisions and scatterings the path
+         * had in it; no mixture weights */
+        for (int l = 0; l < 2; ++l) {
+          score[l] = (double)r.n_coll_l[l] / lp.sigma_t[l] - r.L_l[l];
+          score[K + l] = (r.n_coll_l[l] == 0) ? 0.0 : (double)r.n_coll_l[l] / lp.albedo[l];
+          score[2 * K + l] = r.Sg_l[l];
+        }
+      } else {
+        int k = r.k;
+        score[k] = (double)r.n_coll / up.sigma_t[k] - r.L;
+        score[K + k] = (r.n_coll == 0) ? 0.0 : (double)r.n_coll / up.albedo[k];
+        score[2 * K + k] = r.Sg;
+        for (int j = 0; j < K; ++j) score[3 * K + j] = (j == k ? 1.0 : 0.0) - up.w[j];
+      }
       double cot = job->cot_R ? job->cot_R[u] : 0.0;
       if (job->cot_bins) cot += job->cot_bins[u * (nb + 2) + r.slot];
       double* grad = part;
@@ -938,6 +961,45 @@ int orc_layered_forward(const orc_geometry* geo, const double* sigma_t, const do
     for (int i = 0; i < T_NSLOTS; ++i) tally[u * T_NSLOTS + i] += part[i];
     for (int i = 0; i < (nb + 2) * 2; ++i) bins[u * (nb + 2) * 2 + i] += part[T_NSLOTS + i];
     vertices[u] += (int64_t)part[T_NSLOTS + (nb + 2) * 2];
+  }
+  free_job(&job);
+  return rc;
+}
+
+/* Score-function gradient of the two-layer walk, the layered counterpart of
+ * orc_adjoint: grad[n_units][8] = (sigma_t top, bottom, albedo top, bottom,
+ * g top, bottom, 0, 0), raw sums over the paths leaving the top of
+ * x * (cot_R + cot_bins[slot]) * score, each layer scored with the flights,
+ * collisions and scatterings the path had in it. */
+int orc_layered_adjoint(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                        const double* g, const double* thickness, double n_bottom,
+                        int64_t n_units, const int64_t* paths, uint64_t seed, uint32_t tag,
+                        uint32_t unit_base, int n_threads, const double* cot_R,
+                        const double* cot_bins, double* grad, double* grad_sumsq) {
+  if (check_geometry(geo) || geo->n_media != 2 || !(n_bottom > 0.0) || !sigma_t || !albedo ||
+      !g || !thickness || !paths || n_units < 0 || !grad || !grad_sumsq)
+    return -1;
+  const int P = 8;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = 2;
+  job.layered = 1; job.thickness = thickness; job.n_bottom = n_bottom;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g;
+  job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
+  job.adjoint = 1; job.cot_R = cot_R; job.cot_bins = cot_bins;
+  job.part_len = 2 * P;
+  int rc = run_job(&job, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(grad, 0, sizeof(double) * (size_t)n_units * P);
+  memset(grad_sumsq, 0, sizeof(double) * (size_t)n_units * P);
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    int64_t u = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int j = 0; j < P; ++j) {
+      grad[u * P + j] += part[j];
+      grad_sumsq[u * P + j] += part[P + j];
+    }
   }
   free_job(&job);
   return rc;

@@ -416,6 +416,73 @@ def check_absorbing_top_layer(paths=1 << 18, seed=21, k=3.0):
     return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
 
 
+def check_layered_adjoint_absorbing_top(paths=1 << 18, seed=26, k=3.0):
+    """Two-layer adjoint against the derivatives of the absorbing-top closed
+    form (non-scattering top layer of optical thickness tau = sigma_top d over
+    an isotropic bottom of albedo alpha, n = 1): dR/dsigma_top = d dR/dtau,
+    dR/dalpha_bottom = dR/dalpha, and dR/dsigma_bottom = 0 (the bottom's
+    reflectance does not depend on its length scale).  The derivatives of the
+    closed form are central differences of the quadrature, far below the
+    statistical error."""
+    geo = O.Geometry(n_media=2, n_rel=1.0)
+    zs = []
+    for tau, al in ((0.3, 0.95), (1.0, 0.8)):
+        d = 0.25
+        s = np.array([[tau / d], [3.0]])
+        a = np.array([[0.0], [al]])
+        g = np.zeros((2, 1))
+        grad, sq = O.layered_adjoint(geo, s, a, g, [d], 1.0, paths, seed, cot_R=[1.0])
+        m, se = mean_se(grad[0], sq[0], paths)
+        h = 1e-5
+        dtau = (cf.R_absorbing_top(al, tau + h) - cf.R_absorbing_top(al, tau - h)) / (2 * h)
+        dal = (cf.R_absorbing_top(al + h, tau) - cf.R_absorbing_top(al - h, tau)) / (2 * h)
+        zs += [(m[0] - d * dtau) / se[0], (m[3] - dal) / se[3], m[1] / se[1]]
+        if np.any(grad[0, 6:] != 0.0):
+            return _r(False, "logit columns of the two-layer adjoint must be 0")
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
+def check_layered_adjoint_vs_crn_fd(paths=1 << 14, reps=8, seed=27, k=3.5):
+    """Two-layer VJP with random bin cotangents against central differences
+    of the cotangent-weighted forward tallies on common random numbers (each
+    layer's sigma_t, albedo and g, an index step at the interface), replica
+    means for the SE."""
+    geo = O.Geometry(n_media=2, n_rel=1.4, n_bins=32, r_min_mm=1e-2, r_max_mm=20.0)
+    sig = np.array([6.0, 1.5])
+    alb = np.array([0.85, 0.95])
+    gg = np.array([0.7, 0.5])
+    d, n_bot = 0.15, 1.36
+    rng = np.random.default_rng(seed)
+    cotB = rng.standard_normal(geo.n_bins + 2)
+
+    def J(s, a, g_, sd):
+        tal, bins, _ = O.layered_forward(geo, s[:, None], a[:, None], g_[:, None], [d], n_bot,
+                                         paths, sd)
+        return (tal[0, 0] + bins[0, :, 0] @ cotB) / paths
+
+    adj = np.zeros((reps, 6))
+    fd = np.zeros((reps, 6))
+    for r in range(reps):
+        sd = seed * 1000 + r
+        grad, _ = O.layered_adjoint(geo, sig[:, None], alb[:, None], gg[:, None], [d], n_bot,
+                                    paths, sd, cot_R=[1.0], cot_bins=cotB[None, :])
+        adj[r] = grad[0, :6] / paths
+        for j in range(6):
+            s, a, g_ = sig.copy(), alb.copy(), gg.copy()
+            grp, i = divmod(j, 2)
+            v = (s, a, g_)[grp]
+            h = 1e-3 * (v[i] if grp < 2 else 1.0)
+            v[i] += h
+            Jp = J(s, a, g_, sd)
+            v[i] -= 2 * h
+            Jm = J(s, a, g_, sd)
+            fd[r, j] = (Jp - Jm) / (2 * h)
+    ma, sa = adj.mean(0), adj.std(0, ddof=1) / math.sqrt(reps)
+    mf, sf = fd.mean(0), fd.std(0, ddof=1) / math.sqrt(reps)
+    z = (ma - mf) / np.sqrt(sa ** 2 + sf ** 2 + 1e-30)
+    return _r(np.all(np.abs(z) <= k), f"z={np.round(z, 2)}")
+
+
 def check_transparent_stack(paths=1 << 17, seed=22, k=3.5):
     """Non-scattering stack outside | n0 | n1 | outside (slab bottom): top and
     bottom exits against the incoherent adding of the three Fresnel
@@ -548,6 +615,8 @@ BATTERY_SMALL = [
     ("layers_beer", lambda: check_two_layer_beer_lambert(paths=1 << 16, k=4.0)),
     ("layers_plane", lambda: check_layers_reduce_to_plane(paths=1 << 16, k=4.0)),
     ("layers_absorbing_top", lambda: check_absorbing_top_layer(paths=1 << 16, k=4.0)),
+    ("layers_adj_absorbing_top",
+     lambda: check_layered_adjoint_absorbing_top(paths=1 << 16, k=4.0)),
     ("layers_stack", lambda: check_transparent_stack(paths=1 << 15, k=4.0)),
     ("layers_analog", lambda: check_layers_analog_vs_weighted(paths=1 << 16, k=4.0)),
     ("layers_trace", lambda: check_layer_trace_invariants(n_paths=1500)),

@@ -60,6 +60,10 @@ MUTATIONS = [
     ("bottom_face_top_index", "const double F = fresnel(fabs(d[2]), lp->n[layer]);",
      "const double F = fresnel(fabs(d[2]), lp->n[0]);"),
     ("flight_top_sigma", "-log(u[0]) / lp->sigma_t[layer]", "-log(u[0]) / lp->sigma_t[0]"),
+    ("layer_score_face_length_dropped", "      res->L_l[layer] += db;\n", ""),
+    ("layer_score_flight_wrong_layer", "res->L_l[layer] += flight;", "res->L_l[0] += flight;"),
+    ("layer_score_collisions_wrong_layer", "res->n_coll_l[layer] += res->n_coll - nc0;",
+     "res->n_coll_l[0] += res->n_coll - nc0;"),
     ("refraction_tangent_unscaled", "        d[1] *= rel;\n", ""),
     ("interface_missed_upward", "if (d[2] < 0.0 && zn <= lp->d) { face = 2; zf = lp->d; }",
      "if (d[2] < 0.0 && zn <= 0.0) { face = 2; zf = lp->d; }"),

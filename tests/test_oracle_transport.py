@@ -150,6 +150,16 @@ def test_absorbing_top_layer_exit_law():
     assert ok, detail
 
 
+def test_layered_adjoint_absorbing_top_closed_form():
+    ok, detail = P.check_layered_adjoint_absorbing_top()
+    assert ok, detail
+
+
+def test_layered_adjoint_against_crn_finite_differences():
+    ok, detail = P.check_layered_adjoint_vs_crn_fd()
+    assert ok, detail
+
+
 def test_transparent_stack_fresnel_adding():
     ok, detail = P.check_transparent_stack(paths=1 << 19)
     assert ok, detail
