@@ -223,10 +223,29 @@ typedef struct {
  * unpolarised Fresnel reflectance of n_from / n_to or else crosses, refracted
  * by Snell's law, and draws its next flight in the other layer.  Units whose
  * layers are invalid (including d <= 0, or d >= slab_mm for a slab) keep zero
- * tallies and raise RW_FLAG_BAD_PARAMS.  Forward only (no adjoint). */
+ * tallies and raise RW_FLAG_BAD_PARAMS.  rw_layered_adjoint replays it. */
 rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_geometry* geom,
                              const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
                              rw_tally* out, const rw_batch_opts* opts, void* stream);
+
+/* Adjoint of the two-layer walk by path replay (not in the paper): the same
+ * random numbers as rw_layered_forward (same seed and path counts), and the
+ * score-function gradient of sum_u (cot_R[u] R_sum[u] + sum_s cot_bins[u][s]
+ * bins[u][s][0]) with respect to each layer's sigma_t, albedo and g (not the
+ * thickness, which moves the interface).  A path scores each layer with the
+ * flights, collisions and scatterings it had there:
+ *   sigma_t_l: n_coll_l / sigma_t_l - L_l   (L_l = length travelled in layer l),
+ *   alpha_l:   n_coll_l / alpha_l,
+ *   g_l:       sum over scatterings in layer l of d ln p_HG(mu) / d g.
+ * Output layout as rw_batch_adjoint with K = 2 layers, grad[n_units][8] =
+ * (sigma_t[2], alpha[2], g[2], 0, 0) (top, bottom; the last two columns, the
+ * mixture logits of rw_adjoint, are 0), raw FP64 sums; grad_sumsq, vertices
+ * and flags as there.  Options as rw_batch_forward. */
+rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_geometry* geom,
+                             const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                             const float* cot_R, const float* cot_bins, double* grad,
+                             double* grad_sumsq, int64_t* vertices, int32_t* flags,
+                             const rw_batch_opts* opts, void* stream);
 
 /* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
  * path count N (DEVICE int32 paths_per_unit [n_units], or NULL and

@@ -72,6 +72,22 @@ def layered_forward(ctx: Context, layers, geom: Geometry, paths: int, seed: int,
     return finalize(ctx, geom, tally, layers.n_units, paths, paths_per_unit, stream=stream)
 
 
+def layered_adjoint(ctx: Context, layers, geom: Geometry, paths: int, seed: int, cot_R=None,
+                    cot_bins=None, paths_per_unit=None, use_graph: bool = True, stream=None):
+    """Gradient sums of the two-layer walk (raw, see rw_layered_adjoint): columns
+    (sigma_t top, bottom, albedo top, bottom, g top, bottom, 0, 0).  Returns
+    (grad, grad_sumsq, vertices, flags)."""
+    dev = layers.sigma_t.device
+    n = layers.n_units
+    grad = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    sumsq = torch.empty_like(grad)
+    vert = torch.empty(n, dtype=torch.int64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    rw.rw_layered_adjoint(ctx, layers, geom, paths_per_unit, paths, seed, cot_R, cot_bins, grad,
+                          sumsq, vert, flags, use_graph=use_graph, stream=stream)
+    return grad, sumsq, vert, flags
+
+
 def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, cot_R=None,
             cot_bins=None, batched: bool = True, paths_per_unit=None, use_graph: bool = True,
             stream=None):

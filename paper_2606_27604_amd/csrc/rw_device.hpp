@@ -279,6 +279,10 @@ struct Path {
   // part of the g score that depends on the sampled cosines
   uint32_t ncoll;
   float D, Sg;
+  // two-layer adjoint: the same sums for the other layer (swapped with the
+  // above at each crossing, like m and m2)
+  uint32_t ncoll2;
+  float D2, Sg2;
 };
 
 // Events of a vertex; the codes from EV_EXIT_TOP on end the path.  Traces
@@ -312,6 +316,9 @@ __device__ __forceinline__ void init_path(Path& p, int k, const Medium& m, float
   p.ncoll = 0;
   p.D = 0.0f;
   p.Sg = 0.0f;
+  p.ncoll2 = 0;
+  p.D2 = 0.0f;
+  p.Sg2 = 0.0f;
 }
 
 // Entry through a cosine-weighted lobe (Sec. 8): cos(theta_i) = sqrt(u1) and
@@ -486,7 +493,9 @@ __device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkG
 // interface stops there; the interface reflects with the unpolarised Fresnel
 // reflectance of the relative index n_from / n_to, else the path crosses,
 // refracted by Snell's law, and the next flight is drawn afresh in the other
-// layer (free flights are memoryless).  Forward only.
+// layer (free flights are memoryless).  The adjoint keeps the score sums of
+// each layer: those of the current layer in (ncoll, D, Sg), the other's in
+// (ncoll2, D2, Sg2), swapped at each crossing.
 // ---------------------------------------------------------------------------
 struct LayerParams {
   float sigma_t[2], alb[2], g[2];  // top, bottom
@@ -558,6 +567,7 @@ __device__ __forceinline__ void start_path_layers(Path& p, uint4 w, const LayerP
 }
 
 // vertex v >= 1 of a two-layer path
+template <bool ADJ>
 __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkGeom& geo) {
   const VertexDraw d = draw_vertex(p.m.flight, p.m.g, p.m.hq, w);
   const float s = d.s;
@@ -573,12 +583,13 @@ __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkG
     if (p.uz < 0.0f && zn <= p.d) face = 2;
     else if (geo.slab && p.uz > 0.0f && zn >= geo.slab_mm) face = 3;
   }
-  if (face == 0) return collide<false>(p, d, geo, zn);
+  if (face == 0) return collide<ADJ>(p, d, geo, zn);
   const float zf = face == 1 ? 0.0f : (face == 2 ? p.d : geo.slab_mm);
   const float db = (zf - p.z) * __builtin_amdgcn_rcpf(p.uz);
   p.x = fmaf(db, p.ux, p.x);
   p.y = fmaf(db, p.uy, p.y);
   p.z = zf;
+  if (ADJ) p.D -= db;
   if (face == 2) {
     if (!geo.interface_matched) {
       const float rel = top_layer ? geo.rel_down : geo.rel_up;
@@ -597,6 +608,17 @@ __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkG
     p.m2 = p.m;
     p.m = other;
     p.k ^= 1;
+    if (ADJ) {
+      const uint32_t n = p.ncoll2;
+      p.ncoll2 = p.ncoll;
+      p.ncoll = n;
+      const float D = p.D2;
+      p.D2 = p.D;
+      p.D = D;
+      const float Sg = p.Sg2;
+      p.Sg2 = p.Sg;
+      p.Sg = Sg;
+    }
     return EV_CROSS;
   }
   const bool top = face == 1;

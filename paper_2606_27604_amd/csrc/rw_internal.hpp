@@ -116,6 +116,9 @@ constexpr int kColdConstWords = 4;  // 32 bytes after the media table
 constexpr int64_t kMaxSlotBytes = int64_t(1) << 30;
 inline int forward_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
 inline int adjoint_acc_words(int K) { return 8 * K + 2; }
+// media of the adjoint sums: K for the mixture, the two layers for the
+// two-layer walk
+inline int adjoint_media(int model) { return model == kLayeredModel ? 2 : model; }
 inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {
   return acc_words + kMediaTableWords + kColdConstWords + walk_ring_words(adjoint);
 }

@@ -261,6 +261,62 @@ __device__ __forceinline__ void exit_global_adjoint(const WalkArgs& a, const Wav
   atomicAdd(reinterpret_cast<u64*>(&a.adj_vertices[slot]), u64(nv));
 }
 
+// Two-layer adjoint: a path scores both layers (the flights, collisions and
+// scatterings it had in each), so it adds to the sums of both.  It tallies
+// directly, into the wave's LDS sums when its unit is the wave's current one,
+// else into its slot (no exit ring: the record would not fit 32 bytes).
+__device__ __forceinline__ void layer_scores(const Path& p, int j, float& D, float& sa,
+                                             float& sg) {
+  const bool cur = j == p.k;
+  const uint32_t n = cur ? p.ncoll : p.ncoll2;
+  const float alb = cur ? p.m.alb : p.m2.alb;
+  const float gc = cur ? p.m.gc : p.m2.gc;
+  D = cur ? p.D : p.D2;
+  sa = n ? float(n) * __builtin_amdgcn_rcpf(alb) : 0.0f;
+  sg = fmaf(float(n), gc, cur ? p.Sg : p.Sg2);
+}
+
+__device__ __forceinline__ void exit_adjoint_layered(const WalkArgs& a, const WaveLds& L,
+                                                     bool local, uint32_t slot, uint32_t unit,
+                                                     int ev, const Path& p, uint32_t nv) {
+  if (local) atomicAdd(&L.ctr[0], u64(nv));
+  else atomicAdd(reinterpret_cast<u64*>(&a.adj_vertices[slot]), u64(nv));
+  if (ev != EV_EXIT_TOP) return;
+  const ColdConst cc = read_cold(L);
+  const int b = radial_slot(p.x, p.y, cc);
+  float cot = a.cot_R ? a.cot_R[unit] : 0.0f;
+  if (a.cot_bins) cot += a.cot_bins[int64_t(unit) * (cc.n_bins + 2) + b];
+  const double c = double(p.W) * double(cot);
+  if (c == 0.0) return;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    float D, sa, sg;
+    layer_scores(p, j, D, sa, sg);
+    const double css = c * double(D), csa = c * double(sa), csg = c * double(sg);
+    if (local) {
+      double* t = reinterpret_cast<double*>(L.acc) + 8 * j;
+      atomicAdd(&t[0], c);
+      atomicAdd(&t[1], c * c);
+      atomicAdd(&t[2], css);
+      atomicAdd(&t[3], css * css);
+      atomicAdd(&t[4], csa);
+      atomicAdd(&t[5], csa * csa);
+      atomicAdd(&t[6], csg);
+      atomicAdd(&t[7], csg * csg);
+    } else {
+      double* t = a.adj + (int64_t(slot) * 2 + j) * 8;
+      unsafeAtomicAdd(&t[0], c);
+      unsafeAtomicAdd(&t[1], c * c);
+      unsafeAtomicAdd(&t[2], css);
+      unsafeAtomicAdd(&t[3], css * css);
+      unsafeAtomicAdd(&t[4], csa);
+      unsafeAtomicAdd(&t[5], csa * csa);
+      unsafeAtomicAdd(&t[6], csg);
+      unsafeAtomicAdd(&t[7], csg * csg);
+    }
+  }
+}
+
 // Tally what is left in the ring, then store the wave's sums of the visit
 // (unit u) into its slot and clear them.  The slot belongs to this wave alone,
 // so plain stores do; paths of the visit still in flight add to it afterwards.
@@ -327,7 +383,7 @@ __device__ __forceinline__ void start_any(Path& p, uint4 w, const float* tab, fl
 
 template <bool ADJ, bool LAYERED>
 __device__ __forceinline__ int step_any(Path& p, uint4 w, const WalkGeom& geo) {
-  if constexpr (LAYERED) return vertex_step_layered(p, w, geo);
+  if constexpr (LAYERED) return vertex_step_layered<ADJ>(p, w, geo);
   else return vertex_step<ADJ>(p, w, geo);
 }
 
@@ -365,7 +421,6 @@ __device__ __forceinline__ VertexDraw load_draw(const float* dr, uint32_t i) {
 
 template <int K, bool ADJ, bool LAYERED>
 __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
-  static_assert(!(ADJ && LAYERED), "the two-layer walk is forward only");
   extern __shared__ u64 lds[];
   const int lane = lane_id();
   // the wave index is uniform; say so, or every schedule value derived from it
@@ -477,7 +532,9 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
         if (ev >= EV_EXIT_TOP) {
           sel = false;
           alive = false;
-          if (lslot == uint32_t(cur_slot)) {
+          if constexpr (ADJ && LAYERED) {
+            exit_adjoint_layered(a, L, lslot == uint32_t(cur_slot), lslot, lunit, ev, p, v);
+          } else if (lslot == uint32_t(cur_slot)) {
             if (!ADJ) {
               tally_forward_record(L, read_cold(L), forward_record(ev, p, v));
             } else {
@@ -583,7 +640,9 @@ __global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
       }
     }
     const bool ending = ev >= EV_EXIT_TOP;
-    if (__ballot(ending) != 0) {
+    if constexpr (ADJ && LAYERED) {
+      if (ending) exit_adjoint_layered(a, L, lslot == uint32_t(cur_slot), lslot, lunit, ev, p, v);
+    } else if (__ballot(ending) != 0) {
       const bool local = lslot == uint32_t(cur_slot);
       const uint64_t lm = __ballot(ending && local);
       const uint32_t n_new = uint32_t(__popcll(lm));
@@ -679,9 +738,10 @@ __global__ void __launch_bounds__(kConvWords * kConvGroups) convert_forward_kern
 // Adjoint: per unit, the sums of its slots (fixed order: by group, groups
 // combined in group order), then the [K][8] sums (C, Q, Ss, Ss2, Sa, Sa2, Sg,
 // Sg2) to gradients: sigma_t_k, alpha_k, g_k directly; logit_j = C_j - w_j C
-// with sum of squares (1 - w_j)^2 Q_j + w_j^2 (Q - Q_j).  One block per unit
-// (grid-stride), kConvWords x kConvGroups threads.
-template <int K>
+// with sum of squares (1 - w_j)^2 Q_j + w_j^2 (Q - Q_j).  The two-layer walk
+// (LAYERED, K = 2 layers) has no mixture weights: its logit columns are 0.
+// One block per unit (grid-stride), kConvWords x kConvGroups threads.
+template <int K, bool LAYERED = false>
 __global__ void __launch_bounds__(kConvWords * kConvGroups) convert_adjoint_kernel(
     const WalkArgs a, double* grad, double* grad_sumsq, int64_t* vertices_out) {
   static_assert(8 * K + 1 <= kConvWords, "adjoint slot wider than a block row");
@@ -714,7 +774,15 @@ __global__ void __launch_bounds__(kConvWords * kConvGroups) convert_adjoint_kern
         for (int g = 0; g < kConvGroups; ++g) nv += vpart[g];
         vertices_out[u] = nv;
       }
-      const UnitParams<K> up = load_unit<K>(a, u);
+      double wts[K];
+      if constexpr (LAYERED) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) wts[k] = 0.0;
+      } else {
+        const UnitParams<K> up = load_unit<K>(a, u);
+#pragma unroll
+        for (int k = 0; k < K; ++k) wts[k] = double(up.w[k]);
+      }
       double C = 0.0, Q = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -725,16 +793,18 @@ __global__ void __launch_bounds__(kConvWords * kConvGroups) convert_adjoint_kern
       double* S = grad_sumsq ? grad_sumsq + u * (4 * K) : nullptr;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double wk = double(up.w[k]);
+        const double wk = wts[k];
         G[k] = s[8 * k + 2];
         G[K + k] = s[8 * k + 4];
         G[2 * K + k] = s[8 * k + 6];
-        G[3 * K + k] = s[8 * k + 0] - wk * C;
+        G[3 * K + k] = LAYERED ? 0.0 : s[8 * k + 0] - wk * C;
         if (S) {
           S[k] = s[8 * k + 3];
           S[K + k] = s[8 * k + 5];
           S[2 * K + k] = s[8 * k + 7];
-          S[3 * K + k] = (1.0 - wk) * (1.0 - wk) * s[8 * k + 1] + wk * wk * (Q - s[8 * k + 1]);
+          S[3 * K + k] = LAYERED ? 0.0
+                                 : (1.0 - wk) * (1.0 - wk) * s[8 * k + 1] +
+                                       wk * wk * (Q - s[8 * k + 1]);
         }
       }
     }
@@ -936,7 +1006,7 @@ __global__ void trace_kernel(const WalkArgs a, const uint32_t* words, int64_t n_
       code = EV_START;
     } else {
       nvert = uint32_t(v);
-      if constexpr (LAYERED) code = vertex_step_layered(p, w, geo);
+      if constexpr (LAYERED) code = vertex_step_layered<false>(p, w, geo);
       else code = vertex_step<true>(p, w, geo);
       if (code == EV_COLLIDE || code == EV_RR_KILL) ++ncoll;
     }
@@ -1004,9 +1074,12 @@ hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg,
     case 3: return launch_walk_k<3>(a, adjoint, waves_per_wg, grid_wgs, stream);
     case 4: return launch_walk_k<4>(a, adjoint, waves_per_wg, grid_wgs, stream);
     case kLayeredModel:
-      if (adjoint) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((walk_kernel<2, false, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
-                         size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
+      if (adjoint)
+        hipLaunchKernelGGL((walk_kernel<2, true, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
+                           size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
+      else
+        hipLaunchKernelGGL((walk_kernel<2, false, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
+                           size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
       return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
@@ -1018,7 +1091,7 @@ const void* walk_kernel_ptr(int K, bool adjoint) {
     case 2: return adjoint ? (const void*)walk_kernel<2, true, false> : (const void*)walk_kernel<2, false, false>;
     case 3: return adjoint ? (const void*)walk_kernel<3, true, false> : (const void*)walk_kernel<3, false, false>;
     case 4: return adjoint ? (const void*)walk_kernel<4, true, false> : (const void*)walk_kernel<4, false, false>;
-    case kLayeredModel: return adjoint ? nullptr : (const void*)walk_kernel<2, false, true>;
+    case kLayeredModel: return adjoint ? (const void*)walk_kernel<2, true, true> : (const void*)walk_kernel<2, false, true>;
     default: return nullptr;
   }
 }
@@ -1044,6 +1117,7 @@ const void* convert_adjoint_kernel_ptr(int K) {
     case 2: return (const void*)convert_adjoint_kernel<2>;
     case 3: return (const void*)convert_adjoint_kernel<3>;
     case 4: return (const void*)convert_adjoint_kernel<4>;
+    case kLayeredModel: return (const void*)convert_adjoint_kernel<2, true>;
     default: return nullptr;
   }
 }
@@ -1100,6 +1174,7 @@ hipError_t launch_convert_adjoint(const WalkArgs& a, int K, double* grad, double
     case 2: hipLaunchKernelGGL(convert_adjoint_kernel<2>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
     case 3: hipLaunchKernelGGL(convert_adjoint_kernel<3>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
     case 4: hipLaunchKernelGGL(convert_adjoint_kernel<4>, dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
+    case kLayeredModel: hipLaunchKernelGGL((convert_adjoint_kernel<2, true>), dim3(grid), dim3(kConvWords * kConvGroups), 0, s, a, grad, grad_sumsq, vertices_out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -345,7 +345,7 @@ rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_
   const int frac_bits = 31 - int(std::ceil(std::log2(x_max)));
   a.fix_scale32 = float(std::ldexp(1.0, frac_bits));
   a.fix_cap = float(x_max * (1.0 - 0x1p-20));
-  a.acc_words = adjoint ? adjoint_acc_words(P.K) : forward_acc_words(geom->n_bins);
+  a.acc_words = adjoint ? adjoint_acc_words(adjoint_media(P.K)) : forward_acc_words(geom->n_bins);
   a.lds_words_per_wave = walk_lds_words_per_wave(a.acc_words, adjoint);
   // fewer waves per workgroup when the per-wave LDS (mostly the radial
   // histogram) would not fit a workgroup's allocation
@@ -408,11 +408,12 @@ rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, std::vector<Reg
       clear.push_back({reinterpret_cast<uint64_t*>(a.tb), ni * (nb2 + 5)});
     }
   } else {
-    rw_status st = ensure_workspace(ctx, size_t(ni) * size_t(8 * P.K + 1) * sizeof(double));
+    const int km = adjoint_media(P.K);
+    rw_status st = ensure_workspace(ctx, size_t(ni) * size_t(8 * km + 1) * sizeof(double));
     if (st != RW_OK) return st;
     a.adj = reinterpret_cast<double*>(ctx->workspace);
-    a.adj_vertices = reinterpret_cast<int64_t*>(a.adj + ni * (8 * P.K));
-    clear.push_back({reinterpret_cast<uint64_t*>(a.adj), ni * (8 * P.K + 1)});
+    a.adj_vertices = reinterpret_cast<int64_t*>(a.adj + ni * (8 * km));
+    clear.push_back({reinterpret_cast<uint64_t*>(a.adj), ni * (8 * km + 1)});
   }
   return RW_OK;
 }
@@ -952,6 +953,24 @@ rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_
   return run_walk(ctx, v, layers->n_units, geom, paths_per_unit, paths_uniform, seed, out, nullptr,
                   nullptr, nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false,
                   stream);
+}
+
+rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_geometry* geom,
+                             const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
+                             const float* cot_R, const float* cot_bins, double* grad,
+                             double* grad_sumsq, int64_t* vertices, int32_t* flags,
+                             const rw_batch_opts* opts, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error.clear();
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  MediaView v;
+  st = check_layers(ctx, layers, geom, &v);
+  if (st != RW_OK) return st;
+  rw_batch_opts def{1, 0, 0, 0};
+  return run_walk(ctx, v, layers->n_units, geom, paths_per_unit, paths_uniform, seed, nullptr,
+                  cot_R, cot_bins, grad, grad_sumsq, vertices, flags, opts ? opts : &def, true,
+                  true, stream);
 }
 
 rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,

@@ -124,7 +124,7 @@ EXPORTS = [
     "rw_create", "rw_destroy", "rw_last_error", "rw_status_string", "rw_forward",
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
     "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
-    "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
+    "rw_layered_adjoint", "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
 ]
 
 _lib = None
@@ -173,6 +173,9 @@ def load_library(path: str = LIB_PATH):
     L.rw_layered_forward.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, u64, P(RwTallyC),
                                      P(RwBatchOptsC), vp]
     L.rw_layered_forward.restype = ctypes.c_int
+    L.rw_layered_adjoint.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, u64, vp, vp, vp,
+                                     vp, vp, vp, P(RwBatchOptsC), vp]
+    L.rw_layered_adjoint.restype = ctypes.c_int
     L.rw_debug_trace_layered.argtypes = [vp, P(RwLayersC), P(RwGeometryC), vp, i64, i64, u64,
                                          ctypes.c_uint32, vp, vp, vp]
     L.rw_debug_trace_layered.restype = ctypes.c_int
@@ -469,6 +472,21 @@ def rw_layered_forward(ctx: Context, layers: Layers, geom: Geometry, paths_per_u
                                                  _ptr(paths_per_unit), int(paths_uniform),
                                                  int(seed), ctypes.byref(out._c),
                                                  ctypes.byref(o), _stream(stream)))
+
+
+def rw_layered_adjoint(ctx: Context, layers: Layers, geom: Geometry, paths_per_unit,
+                       paths_uniform: int, seed: int, cot_R, cot_bins, grad, grad_sumsq, vertices,
+                       flags, use_graph=True, autotune=False, unit_begin=0, unit_end=0,
+                       stream=None):
+    _adj_args(layers, geom, cot_R, cot_bins, grad, grad_sumsq, vertices, flags)
+    if paths_per_unit is not None:
+        _need(paths_per_unit, torch.int32, (layers.n_units,), "paths_per_unit")
+    g = geom.c()
+    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    ctx._check(load_library().rw_layered_adjoint(
+        ctx.h, ctypes.byref(layers._c), ctypes.byref(g), _ptr(paths_per_unit), int(paths_uniform),
+        int(seed), _ptr(cot_R), _ptr(cot_bins), _ptr(grad), _ptr(grad_sumsq), _ptr(vertices),
+        _ptr(flags), ctypes.byref(o), _stream(stream)))
 
 
 def rw_debug_trace_layered(ctx: Context, layers: Layers, geom: Geometry, words, n_paths: int,

@@ -151,6 +151,12 @@ def test_layered_invalid_inputs():
     assert flags & rw.RW_FLAG_BAD_PARAMS
     assert float(res.tally.R[1, 0]) == 0.0 and float(res.tally.R[2, 0]) == 0.0
     assert float(res.tally.R[0, 0]) > 0.0
+    # the adjoint flags the same units and leaves their gradients at zero
+    cR = torch.ones(3, dtype=torch.float32, device="cuda")
+    grad, _, _, fl = api.layered_adjoint(ctx(), L, geo, 256, 1, cot_R=cR)
+    assert rw.rw_check(ctx(), fl) & rw.RW_FLAG_BAD_PARAMS
+    G = np64(grad)
+    assert np.all(G[1:] == 0.0) and np.any(G[0] != 0.0)
     # the top layer must end above a slab's bottom
     geo_s, _ = _geoms(1.4, slab_mm=0.05)
     res, flags = _forward(_layers([[2.0], [1.0]], [[0.9], [0.9]], [[0.5], [0.5]], [0.1], 1.4),
@@ -162,3 +168,85 @@ def test_layered_invalid_inputs():
     L_bad = _layers([[2.0], [1.0]], [[0.9], [0.9]], [[0.5], [0.5]], [0.1], 0.0)
     with pytest.raises(rw.RwError, match="n_rel_bottom"):
         api.layered_forward(ctx(), L_bad, geo, 64, 0)
+
+
+def test_layered_adjoint_vs_oracle_same_streams():
+    """Two-layer adjoint (rw_layered_adjoint) against the oracle's FP64 gradient
+    on the same Philox streams: synthetic tones with an index step at the
+    interface, random bin cotangents; graph and eager launches agree."""
+    wl = workloads.layered_tones(n_tones=1, paths=1 << 14, seed=13, n_rel=1.45, n_rel_bottom=1.36)
+    sub = wl.subset(np.arange(0, 81, 8))
+    L = rw.Layers.from_numpy(sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm, sub.n_rel_bottom)
+    geo, ogeo = _geoms(sub.n_rel)
+    N = sub.paths_per_unit
+    rng = np.random.default_rng(14)
+    cR = rng.standard_normal(sub.n_units).astype(np.float32)
+    cB = rng.standard_normal((sub.n_units, geo.n_bins + 2)).astype(np.float32)
+    kw = dict(cot_R=torch.from_numpy(cR).cuda(), cot_bins=torch.from_numpy(cB).cuda())
+    grad, sq, vert, flags = api.layered_adjoint(ctx(), L, geo, N, 15, **kw)
+    assert rw.rw_check(ctx(), flags) == 0
+    g2, _, v2, _ = api.layered_adjoint(ctx(), L, geo, N, 15, use_graph=False, **kw)
+    G = np64(grad)
+    np.testing.assert_allclose(np64(g2), G, rtol=1e-9, atol=1e-9 * np.abs(G).max())
+    assert torch.equal(v2, vert)
+    assert np.all(G[:, 6:] == 0.0)
+    og, osq = O.layered_adjoint(ogeo, sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm,
+                                float(np.float32(sub.n_rel_bottom)), N, 15, cot_R=cR, cot_bins=cB)
+    mg, sg = mean_se(G[:, :6], np64(sq)[:, :6], N)
+    mo, so = mean_se(og[:, :6], osq[:, :6], N)
+    z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    # same random numbers: far inside the statistical error
+    assert np.median(np.abs(z)) <= 0.25, np.median(np.abs(z))
+    # the replay walks the forward's paths: vertex counts agree to the rare
+    # path whose float rounding diverges
+    fwd = api.layered_forward(ctx(), L, geo, N, 15)
+    fv, av = np64(fwd.vertices), np64(vert)
+    assert np.all(np.abs(fv - av) <= 1e-3 * fv)
+
+
+def test_layered_adjoint_closed_form_absorbing_top():
+    """Absorbing non-scattering top layer over an isotropic bottom, n = 1: the
+    device gradient against the derivatives of the closed form
+    (dR/dsigma_top = d dR/dtau, dR/dalpha_bottom, dR/dsigma_bottom = 0)."""
+    N = 1 << 20
+    geo, _ = _geoms(1.0)
+    taus, als, d = [0.3, 1.0], [0.95, 0.8], 0.25
+    L = _layers([[t / d for t in taus], [3.0, 3.0]], [[0.0, 0.0], als], [[0.0, 0.0], [0.0, 0.0]],
+                [d, d], 1.0)
+    cR = torch.ones(2, dtype=torch.float32, device="cuda")
+    grad, sq, _, flags = api.layered_adjoint(ctx(), L, geo, N, 16, cot_R=cR)
+    assert rw.rw_check(ctx(), flags) == 0
+    m, se = mean_se(np64(grad), np64(sq), N)
+    h = 1e-5
+    for u, (tau, al) in enumerate(zip(taus, als)):
+        dtau = (cf.R_absorbing_top(al, tau + h) - cf.R_absorbing_top(al, tau - h)) / (2 * h)
+        dal = (cf.R_absorbing_top(al + h, tau) - cf.R_absorbing_top(al - h, tau)) / (2 * h)
+        z = [(m[u, 0] - d * dtau) / se[u, 0], (m[u, 3] - dal) / se[u, 3], m[u, 1] / se[u, 1]]
+        assert np.all(np.abs(z) <= 3.5), (u, z)
+
+
+def test_layered_adjoint_many_units_per_wave():
+    """Many small two-layer units, so that paths end after their wave moved on
+    and tally into their own unit's slot from global memory: sampled units
+    match the oracle on the same streams."""
+    rng = np.random.default_rng(17)
+    n = 16384
+    s = np.stack([rng.uniform(3.0, 12.0, n), rng.uniform(0.5, 3.0, n)]).astype(np.float32)
+    a = np.stack([rng.uniform(0.6, 0.95, n), rng.uniform(0.8, 0.99, n)]).astype(np.float32)
+    g = np.stack([rng.uniform(0.5, 0.9, n), rng.uniform(0.3, 0.9, n)]).astype(np.float32)
+    d = rng.uniform(0.05, 0.35, n).astype(np.float32)
+    L = rw.Layers.from_numpy(s, a, g, d, 1.4)
+    geo, ogeo = _geoms(1.4)
+    N = 64
+    cR = torch.ones(n, dtype=torch.float32, device="cuda")
+    grad, sq, _, flags = api.layered_adjoint(ctx(), L, geo, N, 18, cot_R=cR)
+    assert rw.rw_check(ctx(), flags) == 0
+    G, S = np64(grad), np64(sq)
+    for u in (0, 1, 4321, n - 1):
+        og, osq = O.layered_adjoint(ogeo, s[:, u:u + 1], a[:, u:u + 1], g[:, u:u + 1], d[u:u + 1],
+                                    float(np.float32(1.4)), N, 18, cot_R=[1.0], unit_base=u)
+        mg, sg = mean_se(G[u, :6], S[u, :6], N)
+        mo, so = mean_se(og[0, :6], osq[0, :6], N)
+        z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+        assert np.all(np.abs(z) <= 3.5), (u, z)
