@@ -568,10 +568,10 @@ def lut_generation(rw, torch, args):
 
 
 def layered_tones(rw, torch, args):
-    """The two-layer tissue walk (Sec. 3 geometry, rw_layered_forward) over N
-    synthetic tones x 81 wavelengths at --layers-photons photons per
-    (tone, wavelength), n = 1.4 in both layers, timed with HIP events on the
-    launch stream (second of two calls).  The paper generates 30,000 tones x
+    """The two-layer tissue walk (Sec. 3 geometry, rw_layered_forward, then its
+    adjoint rw_layered_adjoint) over N synthetic tones x 81 wavelengths at
+    --layers-photons photons per (tone, wavelength), n = 1.4 in both layers,
+    each timed with HIP events on the launch stream (second of two calls).  The paper generates 30,000 tones x
     376 wavelengths at 10^6 photons; the time for that is projected linearly
     from the measured per-photon rate of these tones.  The FP64 oracle is
     timed on a bounded sample of the same units."""
@@ -618,6 +618,30 @@ def layered_tones(rw, torch, args):
                      "note": "slot model of the mixture forward vertex (the interface adds "
                              "work only at crossing vertices)"},
     }
+    # the adjoint replay of the same walk (rw_layered_adjoint), R and bin cotangents
+    n = wl.n_units
+    cot_R = torch.ones(n, dtype=torch.float32, device="cuda")
+    cot_bins = torch.randn((n, wl.n_bins + 2), generator=torch.Generator().manual_seed(1)).cuda()
+    grad = torch.empty((n, 8), dtype=torch.float64, device="cuda")
+    sumsq = torch.empty_like(grad)
+    avert = torch.empty(n, dtype=torch.int64, device="cuda")
+    aflags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for rep in range(2):
+        ev[0].record(s)
+        rw.rw_layered_adjoint(ctx, layers, geom, None, P, 100 + rep, cot_R, cot_bins, grad, sumsq,
+                              avert, aflags, stream=s)
+        ev[1].record(s)
+        torch.cuda.synchronize()
+    ams = ev[0].elapsed_time(ev[1])
+    av = int(avert.sum().item())
+    aslots = alg_slots_per_vertex(True)
+    a_ach = aslots * av / (ams * 1e-3) / 1e12
+    out["adjoint"] = {"ms": ams, "vertices_per_s": av / (ams * 1e-3), "vertices": av,
+                      "device_flags": rw.rw_check(ctx, aflags),
+                      "roofline": {"bound": "alu", "achieved": a_ach, "peak": peak,
+                                   "unit": "Tslot/s", "frac": a_ach / peak,
+                                   "kernel": "walk_kernel<2, adjoint, layered>",
+                                   "slots_per_vertex": aslots}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = layered_cpu_baseline(wl)
     print(json.dumps(out), flush=True)
