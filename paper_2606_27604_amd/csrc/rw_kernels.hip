@@ -419,8 +419,13 @@ __device__ __forceinline__ VertexDraw load_draw(const float* dr, uint32_t i) {
   return d;
 }
 
+// The two-layer adjoint carries both layers' scores and would take 81 VGPRs,
+// i.e. 5 waves per SIMD; asking for 6 fits it in 79 without spills (7 would
+// spill in the vertex loop).  The other instantiations are left to the
+// compiler (7 waves at 63-74 VGPRs).
 template <int K, bool ADJ, bool LAYERED>
-__global__ void __launch_bounds__(256) walk_kernel(const WalkArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ && LAYERED ? 6 : 1)))
+walk_kernel(const WalkArgs a) {
   extern __shared__ u64 lds[];
   const int lane = lane_id();
   // the wave index is uniform; say so, or every schedule value derived from it
