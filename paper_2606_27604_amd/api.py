@@ -158,3 +158,36 @@ class RWReflectance(torch.autograd.Function):
         K = geom.n_media
         gr = grad.t().reshape(4, K, -1).float()
         return gr[0], gr[1], gr[2], gr[3], None, None, None, None, None, None
+
+
+class RWLayeredReflectance(torch.autograd.Function):
+    """Differentiable two-layer reflectance (the Sec. 3 tissue geometry).
+
+    forward(sigma_t, albedo, g [2, n_units] float32 on the GPU (row 0 top
+    layer), thickness_mm [n_units]) -> (R [n_units], bins [n_units, n_bins + 2])
+    as per-path means (bins not per area).  backward replays the same random
+    numbers in the two-layer adjoint and returns d/d(sigma_t, albedo, g) of both
+    layers.  The thickness gets no gradient: moving the interface moves the
+    paths' support, which a score function does not capture."""
+
+    @staticmethod
+    def forward(fctx, sigma_t, albedo, g, thickness_mm, ctx, geom, paths, seed, n_rel_bottom):
+        layers = rw.Layers(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
+                           thickness_mm.contiguous(), n_rel_bottom)
+        tally = Tally(layers.n_units, geom.n_bins, device=sigma_t.device)
+        rw.rw_layered_forward(ctx, layers, geom, None, paths, seed, tally)
+        fctx.save_for_backward(sigma_t, albedo, g, thickness_mm)
+        fctx.meta = (ctx, geom, paths, seed, n_rel_bottom)
+        return tally.R[:, 0] / paths, tally.bins[:, :, 0] / paths
+
+    @staticmethod
+    def backward(fctx, gR, gB):
+        sigma_t, albedo, g, thickness_mm = fctx.saved_tensors
+        ctx, geom, paths, seed, n_rel_bottom = fctx.meta
+        layers = rw.Layers(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
+                           thickness_mm.contiguous(), n_rel_bottom)
+        cot_R = None if gR is None else (gR / paths).float().contiguous()
+        cot_B = None if gB is None else (gB / paths).float().contiguous()
+        grad, _, _, _ = layered_adjoint(ctx, layers, geom, paths, seed, cot_R, cot_B)
+        gr = grad[:, :6].t().reshape(3, 2, -1).float()
+        return gr[0], gr[1], gr[2], None, None, None, None, None, None

@@ -250,3 +250,80 @@ def test_layered_adjoint_many_units_per_wave():
         mo, so = mean_se(og[0, :6], osq[0, :6], N)
         z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
         assert np.all(np.abs(z) <= 3.5), (u, z)
+
+
+def test_layered_adjoint_uneven_paths_and_window():
+    """Per-unit path counts (0 included) and a resume window on the two-layer
+    adjoint: against the oracle with the same counts on the same streams; a
+    unit without paths has no gradient; a window [b, e) fills exactly its
+    units, equal to the full call up to FP64 summation order."""
+    wl = workloads.layered_tones(n_tones=1, paths=4096, seed=19, n_rel=1.45, n_rel_bottom=1.36)
+    sub = wl.subset(np.arange(0, 80, 10))
+    n = sub.n_units
+    L = rw.Layers.from_numpy(sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm, sub.n_rel_bottom)
+    geo, ogeo = _geoms(sub.n_rel)
+    counts = np.array([0, 1, 63, 64, 65, 4095, 4096, 777], np.int32)
+    assert counts.size == n
+    P = int(counts.max())
+    pc = torch.from_numpy(counts).cuda()
+    cR = torch.ones(n, dtype=torch.float32, device="cuda")
+    grad, sq, vert, fl = api.layered_adjoint(ctx(), L, geo, P, 20, cot_R=cR, paths_per_unit=pc)
+    assert rw.rw_check(ctx(), fl) == 0
+    G, S = np64(grad), np64(sq)
+    assert int(vert[0]) == 0 and np.all(G[0] == 0.0) and np.all(S[0] == 0.0)
+    og, osq = O.layered_adjoint(ogeo, sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm,
+                                float(np.float32(sub.n_rel_bottom)), counts, 20,
+                                cot_R=np.ones(n, np.float32))
+    assert np.all(og[0] == 0.0)
+    for u in range(2, n):  # enough paths for a standard error
+        N = int(counts[u])
+        mg, sg = mean_se(G[u, :6], S[u, :6], N)
+        mo, so = mean_se(og[u, :6], osq[u, :6], N)
+        z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+        assert np.all(np.abs(z) <= 3.5), (u, z)
+    # the one-path unit walks the oracle's path: the same gradient up to the FP32
+    # accumulation of its scores (n_coll / sigma_t - L cancels)
+    np.testing.assert_allclose(G[1], og[1], rtol=2e-3, atol=2e-3 * np.abs(og[1]).max())
+    # resume window [2, 5)
+    gw = torch.full((n, 8), -1.0, dtype=torch.float64, device="cuda")
+    sw = torch.full((n, 8), -1.0, dtype=torch.float64, device="cuda")
+    vw = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    fw = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rw.rw_layered_adjoint(ctx(), L, geo, pc, P, 20, cR, None, gw, sw, vw, fw, unit_begin=2,
+                          unit_end=5)
+    torch.cuda.synchronize()
+    W = np64(gw)
+    np.testing.assert_allclose(W[2:5], G[2:5], rtol=1e-9, atol=1e-12 * np.abs(G[2:5]).max())
+    assert torch.equal(vw[2:5], vert[2:5])
+    assert np.all(W[:2] == -1.0) and np.all(W[5:] == -1.0)
+    assert bool((vw[:2] == -1).all()) and bool((vw[5:] == -1).all())
+
+
+def test_layered_autograd_wrapper():
+    """api.RWLayeredReflectance: its outputs are the forward's per-path means and
+    its gradients the two-layer adjoint with the cotangents over the path count."""
+    wl = workloads.layered_tones(n_tones=1, paths=1 << 12, seed=21)
+    sub = wl.subset(np.arange(0, 81, 9))
+    n = sub.n_units
+    geo, _ = _geoms(sub.n_rel)
+    N = sub.paths_per_unit
+    dev = "cuda"
+    s = torch.tensor(sub.sigma_t, device=dev, requires_grad=True)
+    a = torch.tensor(sub.albedo, device=dev, requires_grad=True)
+    g = torch.tensor(sub.g, device=dev, requires_grad=True)
+    d = torch.tensor(sub.thickness_mm, device=dev, requires_grad=True)
+    R, B = api.RWLayeredReflectance.apply(s, a, g, d, ctx(), geo, N, 22, sub.n_rel_bottom)
+    L = rw.Layers.from_numpy(sub.sigma_t, sub.albedo, sub.g, sub.thickness_mm, sub.n_rel_bottom)
+    fwd = api.layered_forward(ctx(), L, geo, N, 22)
+    assert torch.equal(R, fwd.tally.R[:, 0] / N) and torch.equal(B, fwd.tally.bins[:, :, 0] / N)
+    rng = np.random.default_rng(23)
+    wR = torch.tensor(rng.standard_normal(n), device=dev)
+    wB = torch.tensor(rng.standard_normal((n, geo.n_bins + 2)), device=dev)
+    ((R * wR).sum() + (B * wB).sum()).backward()
+    grad, _, _, _ = api.layered_adjoint(ctx(), L, geo, N, 22, cot_R=(wR / N).float(),
+                                        cot_bins=(wB / N).float())
+    G = np64(grad)
+    for t, c in ((s, 0), (a, 2), (g, 4)):
+        ref = G[:, c:c + 2].T
+        np.testing.assert_allclose(np64(t.grad), ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+    assert d.grad is None or float(d.grad.abs().sum()) == 0.0
