@@ -288,6 +288,40 @@ def test_full_size_81_wavelengths_sampled_units_vs_oracle():
     assert np.all((np64(res.R) > 0) & (np64(res.R) < 1))
 
 
+def test_full_size_81_wavelengths_adjoint_sampled_units_vs_oracle():
+    """The benchmark's adjoint (81 wavelengths x 2^20 paths, persistent graph
+    launch, v_R = 1, v_bins ~ N(0, 1)) against the oracle's FP64 score gradient
+    on sampled units, which draw the same random numbers (unit_base)."""
+    wl = workloads.config2()
+    m = media(wl.sigma_t, wl.albedo, wl.g, wl.weight)
+    g, og = geoms(3, wl.n_rel, n_bins=wl.n_bins)
+    rng = np.random.default_rng(2024)
+    cR = np.ones(wl.n_units, np.float32)
+    cB = rng.standard_normal((wl.n_units, g.n_bins + 2)).astype(np.float32)
+    N = wl.paths_per_unit
+    grad, sq, vert, flags = api.adjoint(ctx(), m, g, N, 3, cot_R=torch.from_numpy(cR).cuda(),
+                                        cot_bins=torch.from_numpy(cB).cuda())
+    assert rw.rw_check(ctx(), flags) == 0
+    G, S = np64(grad), np64(sq)
+    sample = np.array([0, 33, 80])
+    sub = wl.subset(sample)
+    zs = []
+    for i, u in enumerate(sample):
+        og_, osq = O.adjoint(og, sub.sigma_t[:, i:i + 1], sub.albedo[:, i:i + 1], sub.g[:, i:i + 1],
+                             sub.weight[:, i:i + 1], N, 3, cot_R=cR[u:u + 1],
+                             cot_bins=cB[u:u + 1], unit_base=int(u))
+        mg, sg = mean_se(G[u], S[u], N)
+        mo, so = mean_se(og_[0], osq[0], N)
+        z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+        assert np.all(np.abs(z) <= 3.5), (u, z)
+        zs += list(np.abs(z))
+    # same random numbers: far inside the statistical error
+    assert np.median(zs) <= 0.05, np.median(zs)
+    # properties at any size: the logit gradients of every unit sum to zero
+    K = 3
+    assert np.allclose(G[:, 3 * K:].sum(1), 0.0, atol=1e-6 * np.abs(G).max())
+
+
 def test_adjoint_plain_batched_graph_agree_and_sigma_invariance():
     wl = workloads.config2(paths=1 << 14)
     sub = wl.subset(np.arange(9))
