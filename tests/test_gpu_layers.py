@@ -327,3 +327,41 @@ def test_layered_autograd_wrapper():
         ref = G[:, c:c + 2].T
         np.testing.assert_allclose(np64(t.grad), ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
     assert d.grad is None or float(d.grad.abs().sum()) == 0.0
+
+
+@pytest.mark.parametrize("trial", [0, 1, 2, 3])
+def test_layered_random_parameters_vs_oracle(trial):
+    """Two-layer forward and adjoint over random units spanning the parameter
+    space (sigma_t 0.5-40 /mm, albedo 0.5-0.999, g -0.5-0.95, d 0.02-1 mm, both
+    indices 1.0-1.6, normal and cosine incidence) against the oracle on the
+    same streams; the adjoint walks the forward's vertices."""
+    rng = np.random.default_rng(1000 + trial)
+    n = 24
+    s = np.stack([rng.uniform(0.5, 40, n), rng.uniform(0.5, 40, n)]).astype(np.float32)
+    a = np.stack([rng.uniform(0.5, 0.999, n), rng.uniform(0.5, 0.999, n)]).astype(np.float32)
+    g = np.stack([rng.uniform(-0.5, 0.95, n), rng.uniform(-0.5, 0.95, n)]).astype(np.float32)
+    d = rng.uniform(0.02, 1.0, n).astype(np.float32)
+    n_top, n_bot = float(rng.uniform(1.0, 1.6)), float(rng.uniform(1.0, 1.6))
+    geo, ogeo = _geoms(n_top, incidence=trial % 2)
+    L = rw.Layers.from_numpy(s, a, g, d, n_bot)
+    N = 1 << 13
+    cR = np.ones(n, np.float32)
+    cB = rng.standard_normal((n, geo.n_bins + 2)).astype(np.float32)
+    seed = 50 + trial
+    grad, sq, vert, fl = api.layered_adjoint(ctx(), L, geo, N, seed, cot_R=torch.from_numpy(cR).cuda(),
+                                             cot_bins=torch.from_numpy(cB).cuda())
+    assert rw.rw_check(ctx(), fl) == 0
+    og, osq = O.layered_adjoint(ogeo, s, a, g, d, float(np.float32(n_bot)), N, seed, cot_R=cR,
+                                cot_bins=cB)
+    mg, sg = mean_se(np64(grad)[:, :6], np64(sq)[:, :6], N)
+    mo, so = mean_se(og[:, :6], osq[:, :6], N)
+    z = np.abs(mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+    assert z.max() <= 3.5 and np.median(z) <= 0.05, (z.max(), np.median(z))
+    res, flags = _forward(L, geo, N, seed)
+    assert flags == 0
+    tal, _, _ = O.layered_forward(ogeo, s, a, g, d, float(np.float32(n_bot)), N, seed)
+    R, se = np64(res.R), np64(res.R_se)
+    oR, ose = mean_se(tal[:, 0], tal[:, 1], N)
+    assert np.all(np.abs(R - oR) <= 0.25 * np.hypot(se, ose) + 1e-12)
+    fv, av = np64(res.vertices), np64(vert)
+    assert np.all(np.abs(fv - av) <= 1e-3 * fv)
