@@ -534,3 +534,39 @@ def test_per_slot_jacobian_matches_oracle():
     cR = torch.ones(2, dtype=torch.float32, device="cuda")
     grad, _, _, _ = api.adjoint(ctx(), m, g, N, 17, cot_R=cR)
     np.testing.assert_allclose(J.sum(1), np64(grad), rtol=1e-9, atol=1e-9 * np.abs(J).max())
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_mixture_random_parameters_vs_oracle(K):
+    """Forward and adjoint over random mixtures spanning the parameter space
+    (sigma_t 0.5-40 /mm, albedo 0.5-0.999, g -0.5-0.95, Dirichlet weights,
+    n 1.0-1.6, normal and cosine incidence) against the oracle on the same
+    streams; the adjoint walks the forward's vertices."""
+    rng = np.random.default_rng(2000 + K)
+    n = 24
+    s = rng.uniform(0.5, 40, (K, n)).astype(np.float32)
+    a = rng.uniform(0.5, 0.999, (K, n)).astype(np.float32)
+    g = rng.uniform(-0.5, 0.95, (K, n)).astype(np.float32)
+    w = rng.dirichlet(np.ones(K), n).T.astype(np.float32)
+    m = media(s, a, g, w)
+    gg, og = geoms(K, float(rng.uniform(1.0, 1.6)), incidence=K % 2)
+    N = 1 << 13
+    seed = 70 + K
+    cR = np.ones(n, np.float32)
+    cB = rng.standard_normal((n, gg.n_bins + 2)).astype(np.float32)
+    grad, sq, vert, flags = api.adjoint(ctx(), m, gg, N, seed, cot_R=torch.from_numpy(cR).cuda(),
+                                        cot_bins=torch.from_numpy(cB).cuda())
+    assert rw.rw_check(ctx(), flags) == 0
+    ogr, osq = O.adjoint(og, s, a, g, w, N, seed, cot_R=cR, cot_bins=cB)
+    mg, sg = mean_se(np64(grad), np64(sq), N)
+    mo, so = mean_se(ogr, osq, N)
+    z = np.abs(mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
+    assert z.max() <= 3.5 and np.median(z) <= 0.05, (z.max(), np.median(z))
+    res, f2 = gpu_forward(m, gg, N, seed)
+    assert f2 == 0
+    tal, _, _ = O.forward(og, s, a, g, w, N, seed)
+    R, se = np64(res.R), np64(res.R_se)
+    oR, ose = mean_se(tal[:, 0], tal[:, 1], N)
+    assert np.all(np.abs(R - oR) <= 0.25 * np.hypot(se, ose) + 1e-12)
+    fv, av = np64(res.vertices), np64(vert)
+    assert np.all(np.abs(fv - av) <= 1e-3 * fv)
