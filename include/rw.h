@@ -248,8 +248,9 @@ rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_
                              const rw_batch_opts* opts, void* stream);
 
 /* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
- * path count N (DEVICE int32 paths_per_unit [n_units], or NULL and
- * paths_uniform):
+ * path count N the walk ran: with a DEVICE int32 paths_per_unit [n_units],
+ * N = min(max(paths_per_unit[u], 0), paths_uniform) (the clamp of
+ * rw_batch_forward; paths_uniform must then be > 0), else N = paths_uniform:
  *   R_mean = sum x / N,  R_se = sqrt((sum x^2 - (sum x)^2 / N) / (N (N - 1))),
  *   Rr[b]  = bins sum / (N * pi (r_{b+1}^2 - r_b^2))  [mm^-2], b = 0..n_bins-1,
  *   Rr_se  likewise from the per-slot sums of squares,

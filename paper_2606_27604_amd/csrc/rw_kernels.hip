@@ -948,7 +948,14 @@ __global__ void finalize_kernel(const WalkGeom geo, int64_t n_units, const int32
        t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t u = t / (nb + 1);
     const int j = int(t - u * (nb + 1));  // j == nb: the unit's totals, else bin j
-    const double N = double(paths ? paths[u] : paths_uniform);
+    // the path count the walk ran: a per-unit entry clamped to [0, paths_uniform]
+    // exactly as the walk's work map clamps it
+    int64_t n_run = paths_uniform;
+    if (paths) {
+      const int64_t q = paths[u];
+      n_run = q < 0 ? 0 : (q < paths_uniform ? q : paths_uniform);
+    }
+    const double N = double(n_run);
     const double sx = R[u * 4 + 0], sx2 = R[u * 4 + 1];
     const double mean = N > 0 ? sx / N : 0.0;
     if (j == nb) {

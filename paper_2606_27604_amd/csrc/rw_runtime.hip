@@ -984,8 +984,11 @@ rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
   if (n_units < 0) return fail(ctx, RW_E_INVALID, "n_units must be >= 0");
   if (!tally || !tally->R || !tally->bins)
     return fail(ctx, RW_E_INVALID, "tally R and bins must be non-NULL");
-  if (!paths_per_unit && paths_uniform < 0)
-    return fail(ctx, RW_E_INVALID, "paths_uniform must be >= 0");
+  if (paths_uniform < 0 || paths_uniform > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "paths_uniform must be in [0, 2^31]");
+  if (paths_per_unit && paths_uniform <= 0 && n_units > 0)
+    return fail(ctx, RW_E_INVALID,
+                "with a per-unit path array, paths_uniform must give the largest count (> 0)");
   st = need_device(ctx);
   if (st != RW_OK) return st;
   RW_HIP(ctx, launch_finalize(make_geom(geom), n_units, paths_per_unit, paths_uniform, tally->R,

@@ -115,6 +115,28 @@ def test_finalize_matches_definition():
     np.testing.assert_allclose(bins[:, :, 0].sum(1), Rs[:, 0], rtol=1e-12)
 
 
+def test_finalize_clamps_path_counts_like_the_walk():
+    """A per-unit count above paths_uniform runs paths_uniform paths (the walk's
+    clamp), and finalize divides by that same count: R, its SE and the profile
+    equal those of a uniform call at paths_uniform.  A negative count runs no
+    path and finalizes to zeros."""
+    wl = workloads.config2(paths=1 << 12)
+    sub = wl.subset(np.arange(4))
+    m = media(sub.sigma_t, sub.albedo, sub.g, sub.weight)
+    g, _ = geoms(3, sub.n_rel)
+    P = 2048
+    counts = torch.tensor([5000, P, 1 << 30, -3], dtype=torch.int32, device="cuda")
+    got = api.forward(ctx(), m, g, P, 9, paths_per_unit=counts)
+    ref = api.forward(ctx(), m, g, P, 9)
+    torch.cuda.synchronize()
+    for u in (0, 1, 2):
+        assert torch.equal(got.tally.R[u], ref.tally.R[u]), u
+        assert torch.equal(got.R[u], ref.R[u]) and torch.equal(got.R_se[u], ref.R_se[u]), u
+        assert torch.equal(got.Rr[u], ref.Rr[u]) and torch.equal(got.Pd[u], ref.Pd[u]), u
+    assert float(got.R[3]) == 0.0 and float(got.R_se[3]) == 0.0
+    assert float(got.Rr[3].abs().sum()) == 0.0 and int(got.vertices[3]) == 0
+
+
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_mixtures_of_other_sizes_vs_oracle(K):
     rng = np.random.default_rng(40 + K)
