@@ -145,6 +145,25 @@ typedef struct {
 rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                      int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
 
+/* Allocation-free variant of rw_forward, for callers that cannot allocate
+ * device memory during the call: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, launches and
+ * results as rw_forward (bit-identical tallies for the same seed), but it
+ * calls no hipMalloc, hipFree or other allocating routine, on the device or
+ * the host: the forward slot sums of a call whose units span several work
+ * items live in a fixed 64 MiB device array that the library holds on every
+ * device it runs on until the process ends (its address is looked up once
+ * per device by rw_create).  The plan is rw_forward's, except that work items
+ * grow (doubling from 2048 paths, at most 65 536) until n_items *
+ * ((n_bins + 2) * 16 + 40) bytes fit the array; a call that still does not
+ * fit returns RW_E_UNSUPPORTED before anything is enqueued (e.g. more than
+ * 1 023 work items of 65 536 paths at 4 096 bins).  Every call on a device
+ * shares that array, so calls that overlap on one device (two streams, two
+ * contexts, two threads) race; callers serialise them.  The array is cleared
+ * by each call, on its stream, with kernels (no memset nodes). */
+rw_status rw_forward_noalloc(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                             int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
+
 /* Batched persistent form of the forward walk: a persistent grid pulls
  * (unit, chunk) work items from a device queue, units with the longest
  * estimated paths first, and wavefronts move on to further items without

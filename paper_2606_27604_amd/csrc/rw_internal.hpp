@@ -115,6 +115,8 @@ constexpr int kColdConstWords = 4;  // 32 bytes after the media table
 // bound on the forward slot workspace of one call (bytes)
 constexpr int64_t kMaxSlotBytes = int64_t(1) << 30;
 inline int forward_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
+// int64 words of one forward slot in global memory: bins, (x, x^2, T, A), vertices
+inline int forward_slot_words(int n_bins) { return 2 * (n_bins + 2) + 5; }
 inline int adjoint_acc_words(int K) { return 8 * K + 2; }
 // media of the adjoint sums: K for the mixture, the two layers for the
 // two-layer walk

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,11 +43,30 @@ struct GraphEntry {
 
 }  // namespace
 
+// ---- scratch of the allocation-free forward (rw_forward_noalloc) ----------
+// The forward slot sums of a call whose units span several work items, in a
+// file-scope device array: every device the library runs on holds its own
+// copy until the process ends, and every rw_forward_noalloc call on a device
+// shares it (calls that overlap on one device race).  Host code never passes
+// the array's name to a kernel (on the host it only names the symbol): it
+// uses the device address that rw_create looks up once per device.
+constexpr int64_t kNoAllocScratchBytes = int64_t(64) << 20;
+// largest work item the allocation-free plan grows to before it gives up
+constexpr int kNoAllocMaxChunk = 1 << 16;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+}  // namespace
+
 struct rw_context {
   int device = -1;          // -1: validation-only context (no device)
+  void* scratch = nullptr;  // this device's copy of `scratch` (device address)
   int n_cu = 0;
   int max_lds = 0;          // bytes of LDS a workgroup may allocate
-  std::string last_error;
+  char last_error[512] = {0};  // a fixed buffer: reporting an error allocates nothing
   void* workspace = nullptr;      // adjoint sums (128-bit) and vertex counts
   size_t workspace_bytes = 0;
   uint32_t* queue = nullptr;
@@ -62,12 +82,10 @@ namespace {
 
 rw_status fail(rw_context* ctx, rw_status st, const char* fmt, ...) {
   if (ctx) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(ctx->last_error, sizeof(ctx->last_error), fmt, ap);
     va_end(ap);
-    ctx->last_error = buf;
   }
   return st;
 }
@@ -286,9 +304,13 @@ struct Plan {
 
 int round_up(int64_t v, int64_t m) { return int((v + m - 1) / m * m); }
 
+// Forward calls with several items per unit keep one slot of sums per item;
+// max_slot_bytes bounds that workspace, and items grow (doubling, up to
+// max_chunk paths) until it fits.
 rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_geometry* geom,
                      int64_t n_units, const int32_t* paths, int64_t paths_uniform, uint64_t seed,
-                     int64_t ub, int64_t ue, bool adjoint, const TuneCfg& cfg) {
+                     int64_t ub, int64_t ue, bool adjoint, const TuneCfg& cfg,
+                     int64_t max_slot_bytes = kMaxSlotBytes, int max_chunk = 1 << 30) {
   WalkArgs& a = P.a;
   a = WalkArgs{};
   a.sigma_t = media.sigma_t;
@@ -311,16 +333,17 @@ rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_
   P.n_window = ue - ub;
   // chunk: at most the configured size, and no larger than the (rounded) path
   // count.  Forward calls with several items per unit keep one slot of sums
-  // per item in the workspace; when that would exceed kMaxSlotBytes, items
-  // grow (up to one item per unit, which needs no workspace at all).
+  // per item in the workspace; when that would exceed max_slot_bytes, items
+  // grow (up to one item per unit, which needs no workspace at all, or to
+  // max_chunk paths).
   int chunk = cfg.chunk;
   if (paths_uniform > 0 && paths_uniform < chunk) chunk = std::max(64, round_up(paths_uniform, 64));
   if (!adjoint && paths_uniform > chunk) {
-    const double slot_bytes = double(2 * (geom->n_bins + 2) + 5) * 8.0;
+    const double slot_bytes = double(forward_slot_words(geom->n_bins)) * 8.0;
     while (paths_uniform > chunk &&
            double(ue - ub) * double((paths_uniform + chunk - 1) / chunk) * slot_bytes >
-               double(kMaxSlotBytes) &&
-           chunk < (1 << 30))
+               double(max_slot_bytes) &&
+           chunk < max_chunk)
       chunk *= 2;
     if (paths_uniform <= chunk) chunk = std::max(64, round_up(paths_uniform, 64));
   }
@@ -380,13 +403,28 @@ struct Region {
   uint64_t* p;
   int64_t n;
 };
+// the regions a launch sequence clears (at most three; no heap)
+struct Regions {
+  Region r[3];
+  int n = 0;
+  void add(uint64_t* p, int64_t count) { r[n++] = Region{p, count}; }
+};
 
-rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, std::vector<Region>& clear) {
+// Bytes of forward slot workspace a plan needs (0 when every unit is one item).
+int64_t forward_slot_bytes(const Plan& P) {
+  if (P.adjoint || P.a.map.chunks_per_unit <= 1) return 0;
+  return P.a.map.n_items * int64_t(forward_slot_words(P.a.geo.n_bins)) * int64_t(sizeof(int64_t));
+}
+
+// fixed_ws: when non-NULL, the forward slots go there (the caller checked its
+// size with forward_slot_bytes) instead of the context's workspace.
+rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, Regions& clear,
+                        void* fixed_ws = nullptr) {
   WalkArgs& a = P.a;
   const int64_t ub = a.map.unit_begin;
   const int64_t nb2 = 2 * (a.geo.n_bins + 2);
   const int64_t ni = a.map.n_items;
-  clear.clear();
+  clear.n = 0;
   if (!P.adjoint) {
     a.out_R = out->R;
     a.out_bins = out->bins;
@@ -396,16 +434,20 @@ rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, std::vector<Reg
       a.tb = reinterpret_cast<int64_t*>(out->bins);
       a.tc = reinterpret_cast<int64_t*>(out->R);
       a.tv = out->vertices;
-      clear.push_back({reinterpret_cast<uint64_t*>(a.tb + ub * nb2), P.n_window * nb2});
-      clear.push_back({reinterpret_cast<uint64_t*>(a.tc + ub * 4), P.n_window * 4});
-      clear.push_back({reinterpret_cast<uint64_t*>(a.tv + ub), P.n_window});
+      clear.add(reinterpret_cast<uint64_t*>(a.tb + ub * nb2), P.n_window * nb2);
+      clear.add(reinterpret_cast<uint64_t*>(a.tc + ub * 4), P.n_window * 4);
+      clear.add(reinterpret_cast<uint64_t*>(a.tv + ub), P.n_window);
     } else {
-      rw_status st = ensure_workspace(ctx, size_t(ni) * size_t(nb2 + 5) * sizeof(int64_t));
-      if (st != RW_OK) return st;
-      a.tb = reinterpret_cast<int64_t*>(ctx->workspace);
+      void* ws = fixed_ws;
+      if (!ws) {
+        rw_status st = ensure_workspace(ctx, size_t(forward_slot_bytes(P)));
+        if (st != RW_OK) return st;
+        ws = ctx->workspace;
+      }
+      a.tb = reinterpret_cast<int64_t*>(ws);
       a.tc = a.tb + ni * nb2;
       a.tv = a.tc + ni * 4;
-      clear.push_back({reinterpret_cast<uint64_t*>(a.tb), ni * (nb2 + 5)});
+      clear.add(reinterpret_cast<uint64_t*>(a.tb), ni * (nb2 + 5));
     }
   } else {
     const int km = adjoint_media(P.K);
@@ -413,7 +455,7 @@ rw_status setup_tallies(rw_context* ctx, Plan& P, rw_tally* out, std::vector<Reg
     if (st != RW_OK) return st;
     a.adj = reinterpret_cast<double*>(ctx->workspace);
     a.adj_vertices = reinterpret_cast<int64_t*>(a.adj + ni * (8 * km));
-    clear.push_back({reinterpret_cast<uint64_t*>(a.adj), ni * (8 * km + 1)});
+    clear.add(reinterpret_cast<uint64_t*>(a.adj), ni * (8 * km + 1));
   }
   return RW_OK;
 }
@@ -426,16 +468,17 @@ int64_t persistent_grid(rw_context* ctx, const Plan& P) {
 
 // Enqueue the launch sequence of a plan (no graph).
 rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, double* grad,
-                  double* grad_sumsq, int64_t* adj_vertices, int32_t* flags, hipStream_t s) {
+                  double* grad_sumsq, int64_t* adj_vertices, int32_t* flags, hipStream_t s,
+                  void* fixed_ws = nullptr) {
   WalkArgs& a = P.a;
   if (fault_injected("launch")) return fail(ctx, RW_E_HIP, "injected launch failure");
   RW_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(flags), 1, 0u, s));
   a.flags = flags;
   if (P.n_window <= 0) return RW_OK;
-  std::vector<Region> clear;
-  rw_status st0 = setup_tallies(ctx, P, out, clear);
+  Regions clear;
+  rw_status st0 = setup_tallies(ctx, P, out, clear, fixed_ws);
   if (st0 != RW_OK) return st0;
-  for (const Region& r : clear) RW_HIP(ctx, launch_fill_u64(r.p, r.n, s));
+  for (int i = 0; i < clear.n; ++i) RW_HIP(ctx, launch_fill_u64(clear.r[i].p, clear.r[i].n, s));
   if (a.map.n_items > 0) {
     const int wpw = P.cfg.waves_per_wg;
     int64_t grid;
@@ -639,7 +682,7 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
   a.flags = flags;
   if (P.n_window <= 0 || a.map.n_items == 0)
     return enqueue(ctx, P, true, out, grad, grad_sumsq, adj_vertices, flags, s);
-  std::vector<Region> clear;
+  Regions clear;
   rw_status st0 = setup_tallies(ctx, P, out, clear);
   if (st0 != RW_OK) return st0;
   const int wpw = P.cfg.waves_per_wg;
@@ -664,7 +707,7 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
   };
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(flags_u), arg_bytes(one), arg_bytes(zero)}});
-  for (const Region& r : clear) fill64(r.p, r.n);
+  for (int i = 0; i < clear.n; ++i) fill64(clear.r[i].p, clear.r[i].n);
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(ctx->queue), arg_bytes(one), arg_bytes(zero)}});
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
@@ -815,7 +858,7 @@ rw_status run_media(rw_context* ctx, const rw_media* media, const rw_geometry* g
                     int64_t* adj_vertices, int32_t* flags, const rw_batch_opts* opts, bool batched,
                     bool adjoint, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   int64_t n_units = 0;
@@ -883,6 +926,22 @@ rw_status rw_create(rw_context** out, int hip_device) {
     delete ctx;
     return RW_E_NOMEM;
   }
+  // the allocation-free forward's scratch: its device address on this device,
+  // looked up once per device with the device current
+  if (hip_device < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[hip_device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        hipFree(ctx->queue);
+        delete ctx;
+        return RW_E_HIP;
+      }
+      g_scratch_ptr[hip_device] = p;
+    }
+    ctx->scratch = g_scratch_ptr[hip_device];
+  }
   *out = ctx;
   return RW_OK;
 }
@@ -905,12 +964,47 @@ rw_status rw_destroy(rw_context* ctx) {
   return RW_OK;
 }
 
-const char* rw_last_error(const rw_context* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+const char* rw_last_error(const rw_context* ctx) { return ctx ? ctx->last_error : ""; }
 
 rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                      int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream) {
   return run_media(ctx, media, geom, nullptr, paths_per_unit, seed, out, nullptr, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, false, false, stream);
+}
+
+rw_status rw_forward_noalloc(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                             int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error[0] = 0;
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  int64_t n_units = 0;
+  st = check_media(ctx, media, &n_units);
+  if (st != RW_OK) return st;
+  if (paths_per_unit < 0 || paths_per_unit > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "path count must be in [0, 2^31] (got %lld)",
+                (long long)paths_per_unit);
+  if (!out || !out->R || !out->bins || !out->vertices || !out->flags)
+    return fail(ctx, RW_E_INVALID, "tally pointers must be non-NULL");
+  // the plan of rw_forward, with the slot workspace bounded by the scratch
+  Plan P;
+  st = build_plan(ctx, P, view_of(media, geom, n_units), geom, n_units, nullptr, paths_per_unit,
+                  seed, 0, n_units, false, TuneCfg{}, kNoAllocScratchBytes, kNoAllocMaxChunk);
+  if (st != RW_OK) return st;
+  const int64_t need = forward_slot_bytes(P);
+  if (need > kNoAllocScratchBytes)
+    return fail(ctx, RW_E_UNSUPPORTED,
+                "rw_forward_noalloc: %lld units x %lld paths at %d bins need %lld bytes of "
+                "scratch; the limit is %lld (at most %d paths per work item)",
+                (long long)n_units, (long long)paths_per_unit, geom->n_bins, (long long)need,
+                (long long)kNoAllocScratchBytes, kNoAllocMaxChunk);
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  if (!ctx->scratch)
+    return fail(ctx, RW_E_UNSUPPORTED, "no scratch on device %d (device index >= %d)", ctx->device,
+                kMaxDevices);
+  return enqueue(ctx, P, false, out, nullptr, nullptr, nullptr, out->flags,
+                 reinterpret_cast<hipStream_t>(stream), ctx->scratch);
 }
 
 rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
@@ -943,7 +1037,7 @@ rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_
                              const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
                              rw_tally* out, const rw_batch_opts* opts, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   MediaView v;
@@ -961,7 +1055,7 @@ rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_
                              double* grad_sumsq, int64_t* vertices, int32_t* flags,
                              const rw_batch_opts* opts, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   MediaView v;
@@ -978,7 +1072,7 @@ rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
                       double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,
                       void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   if (n_units < 0) return fail(ctx, RW_E_INVALID, "n_units must be >= 0");
@@ -1015,7 +1109,7 @@ rw_status rw_debug_trace(rw_context* ctx, const rw_media* media, const rw_geomet
                          uint32_t unit_index, float* events, float* path_out, float* path_adj,
                          void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   int64_t n_units = 0;
@@ -1050,7 +1144,7 @@ rw_status rw_debug_trace_layered(rw_context* ctx, const rw_layers* layers,
                                  int64_t n_blocks, uint64_t seed, uint32_t unit_index,
                                  float* events, float* path_out, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   rw_status st = check_geom(ctx, geom);
   if (st != RW_OK) return st;
   MediaView v;
@@ -1085,7 +1179,7 @@ rw_status rw_lut_loss_grad(rw_context* ctx, const rw_lut* lut, const rw_lut_targ
                            int64_t n_units, int32_t n_media, const float* params, float* grad,
                            float* loss, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   LutArgs a;
   rw_status st = lut_args(ctx, lut, targets, n_units, n_media, params, &a);
   if (st != RW_OK) return st;
@@ -1101,7 +1195,7 @@ rw_status rw_lut_fit_step(rw_context* ctx, const rw_lut* lut, const rw_lut_targe
                           int64_t n_units, int32_t n_media, float* params, float* adam_m,
                           float* adam_v, int32_t step, float lr, float* loss, void* stream) {
   if (!ctx) return RW_E_INVALID;
-  ctx->last_error.clear();
+  ctx->last_error[0] = 0;
   LutArgs a;
   rw_status st = lut_args(ctx, lut, targets, n_units, n_media, params, &a);
   if (st != RW_OK) return st;

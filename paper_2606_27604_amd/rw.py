@@ -125,6 +125,7 @@ EXPORTS = [
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
     "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
     "rw_layered_adjoint", "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
+    "rw_forward_noalloc",
 ]
 
 _lib = None
@@ -153,6 +154,8 @@ def load_library(path: str = LIB_PATH):
     L.rw_version.restype = ctypes.c_char_p
     L.rw_forward.argtypes = [vp, P(RwMediaC), P(RwGeometryC), i64, u64, P(RwTallyC), vp]
     L.rw_forward.restype = ctypes.c_int
+    L.rw_forward_noalloc.argtypes = [vp, P(RwMediaC), P(RwGeometryC), i64, u64, P(RwTallyC), vp]
+    L.rw_forward_noalloc.restype = ctypes.c_int
     L.rw_batch_forward.argtypes = [vp, P(RwMediaC), P(RwGeometryC), vp, i64, u64, P(RwTallyC),
                                    P(RwBatchOptsC), vp]
     L.rw_batch_forward.restype = ctypes.c_int
@@ -382,6 +385,14 @@ def rw_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit: int, 
     ctx._check(load_library().rw_forward(ctx.h, ctypes.byref(media._c), ctypes.byref(g),
                                          int(paths_per_unit), int(seed), ctypes.byref(out._c),
                                          _stream(stream)))
+
+
+def rw_forward_noalloc(ctx: Context, media: Media, geom: Geometry, paths_per_unit: int, seed: int,
+                       out: Tally, stream=None):
+    g = geom.c()
+    ctx._check(load_library().rw_forward_noalloc(ctx.h, ctypes.byref(media._c), ctypes.byref(g),
+                                                 int(paths_per_unit), int(seed),
+                                                 ctypes.byref(out._c), _stream(stream)))
 
 
 def rw_batch_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit, paths_uniform: int,

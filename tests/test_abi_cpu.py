@@ -147,3 +147,23 @@ def test_product_path_has_no_cpu_fallback(tmp_path):
     src = open(os.path.join(ROOT, "paper_2606_27604_amd", "rw.py")).read()
     src += open(os.path.join(ROOT, "paper_2606_27604_amd", "api.py")).read()
     assert "oracle" not in src
+
+
+def test_noalloc_forward_checks_its_scratch_bound_on_the_host(lib):
+    """rw_forward_noalloc rejects a call whose slot sums cannot fit its fixed
+    scratch array before anything reaches a device; a call that fits passes the
+    check and then reports the missing device."""
+    ctx = rw.Context(-1)
+    m = rw.RwMediaC(0x1000, 0x2000, 0x3000, 0x4000, 0, 2048, 1, None, 0)
+    t = rw.RwTallyC(0x5000, 0x6000, 0x7000, 0x8000)
+    g = rw.Geometry(n_media=1, n_bins=4096).c()
+    st = lib.rw_forward_noalloc(ctx.h, ctypes.byref(m), ctypes.byref(g), 1 << 17, 0,
+                                ctypes.byref(t), None)
+    assert st == rw.RW_E_UNSUPPORTED and "scratch" in ctx.last_error()
+    g256 = rw.Geometry(n_media=1).c()
+    st = lib.rw_forward_noalloc(ctx.h, ctypes.byref(m), ctypes.byref(g256), 1 << 17, 0,
+                                ctypes.byref(t), None)
+    assert st == rw.RW_E_UNSUPPORTED and "validation-only" in ctx.last_error()
+    bad_t = rw.RwTallyC(0x5000, 0, 0x7000, 0x8000)
+    assert lib.rw_forward_noalloc(ctx.h, ctypes.byref(m), ctypes.byref(g256), 16, 0,
+                                  ctypes.byref(bad_t), None) == rw.RW_E_INVALID
