@@ -49,7 +49,7 @@ def pieces(rr_exe):
 
 
 ORDER = ["energy", "special", "plane", "beer", "mixture", "single_scatter", "analog", "scale",
-         "brute", "adj_plane", "adj_mixture", "second_moment", "trace", "spherical",
+         "brute", "adj_plane", "adj_mixture", "jacobian", "second_moment", "trace", "spherical",
          "analog_cosine", "layers_trace", "layers_beer", "layers_plane", "layers_absorbing_top",
          "layers_adj_absorbing_top",
          "layers_stack", "layers_analog", "adding_doubling"]

@@ -364,6 +364,65 @@ def check_adjoint_vs_crn_fd(paths=1 << 15, reps=8, seed=13, k=3.5):
     return _r(np.all(np.abs(z) <= k), f"z={np.round(z, 2)}")
 
 
+def check_jacobian(paths=1 << 13, seed=14, rtol=1e-9):
+    """The Jacobian output of the oracle's adjoint (per unit, the score sums of
+    the total and of every radial slot), pinned without re-deriving it:
+    (i) contracted with any cotangents it gives the gradient the adjoint
+        returns for those cotangents (a vector-Jacobian product is the
+        Jacobian's transpose applied to the cotangent), for K = 1..4 on two
+        units, with a Fresnel boundary and g != 0;
+    (ii) its slots add up to its total row (every top exit lands in one slot);
+    (iii) on single-scattering paths (order filter 1, eq. sss with one
+        scattering vertex) the exit weight is linear in the albedo, so the
+        albedo column of every slot equals that slot's forward sum divided by
+        the albedo, and the logit columns of each slot sum to zero (the
+        softmax weights sum to one)."""
+    rng = np.random.default_rng(seed)
+    for K in (1, 2, 3, 4):
+        n_units = 2
+        geo = O.Geometry(n_media=K, n_rel=1.4, n_bins=12, r_min_mm=1e-2, r_max_mm=20.0)
+        sig = 10 ** rng.uniform(-0.5, 1.0, (K, n_units))
+        alb = rng.uniform(0.5, 0.97, (K, n_units))
+        gg = rng.uniform(-0.3, 0.9, (K, n_units))
+        w = rng.dirichlet(np.ones(K), n_units).T
+        cotR = rng.standard_normal(n_units)
+        cotB = rng.standard_normal((n_units, geo.n_bins + 2))
+        grad, _, jR, jB = O.adjoint(geo, sig, alb, gg, w, paths, seed + K, cot_R=cotR,
+                                    cot_bins=cotB, jacobian=True)
+        vjp = cotR[:, None] * jR + np.einsum("us,usj->uj", cotB, jB)
+        scale = np.abs(cotR)[:, None] * np.abs(jR) + np.einsum("us,usj->uj", np.abs(cotB),
+                                                               np.abs(jB)) + 1e-300
+        err = np.abs(vjp - grad) / scale
+        if not np.all(err <= rtol):
+            return _r(False, f"K={K}: contraction differs from the gradient, max rel {err.max():.2e}")
+        if not np.allclose(jB.sum(1), jR, rtol=1e-12, atol=1e-12 * np.abs(jR).max()):
+            return _r(False, f"K={K}: slots do not add up to the total row")
+        if not np.any(np.abs(jB) > 0):
+            return _r(False, f"K={K}: empty Jacobian")
+    # (iii) single scattering, K = 1 (albedo column) and K = 3 (logit columns)
+    for K in (1, 3):
+        geo = O.Geometry(n_media=K, n_rel=1.4, n_bins=12, r_min_mm=1e-2, r_max_mm=20.0,
+                         order_filter=1)
+        sig = np.array([2.0, 0.7, 5.0][:K])
+        alb = np.array([0.8, 0.6, 0.95][:K])
+        gg = np.array([0.5, 0.1, 0.8][:K])
+        w = np.array([0.5, 0.2, 0.3][:K]) if K == 3 else np.ones(1)
+        _, bins, _ = O.forward(geo, sig, alb, gg, w, paths * 4, seed + 10)
+        _, _, jR, jB = O.adjoint(geo, sig, alb, gg, w, paths * 4, seed + 10, cot_R=[1.0],
+                                 jacobian=True)
+        if K == 1:
+            want = bins[0, :, 0] / alb[0]
+            if not np.allclose(jB[0, :, 1], want, rtol=1e-12, atol=1e-15):
+                return _r(False, "single-scatter albedo column != slot sum / albedo")
+            if not np.any(want > 0):
+                return _r(False, "no single-scatter exits")
+        else:
+            lsum = jB[0, :, 9:12].sum(1)
+            if not np.all(np.abs(lsum) <= 1e-12 * (np.abs(jB[0, :, 9:12]).sum(1) + 1e-300)):
+                return _r(False, "logit columns of a slot do not sum to zero")
+    return _r(True, "")
+
+
 # ---- two-layer tissue ------------------------------------------------------
 def _layered(geo, top, bot, d, n_bottom, paths, seed, n=1):
     """top/bot = (sigma_t, albedo, g) of each layer, repeated over n units.
@@ -610,6 +669,7 @@ BATTERY_SMALL = [
     ("brute", lambda: check_brute_force_single_scatter(m=32)),
     ("adj_plane", lambda: check_adjoint_plane(paths=1 << 16, k=4.0)),
     ("adj_mixture", lambda: check_adjoint_mixture(paths=1 << 16, k=4.0)),
+    ("jacobian", lambda: check_jacobian(paths=1 << 11)),
     ("spherical", lambda: check_spherical_albedo(paths=1 << 16, k=4.0)),
     ("analog_cosine", lambda: check_analog_vs_weighted_cosine(paths=1 << 16, k=4.0)),
     ("layers_beer", lambda: check_two_layer_beer_lambert(paths=1 << 16, k=4.0)),

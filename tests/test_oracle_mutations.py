@@ -67,6 +67,10 @@ MUTATIONS = [
     ("refraction_tangent_unscaled", "        d[1] *= rel;\n", ""),
     ("interface_missed_upward", "if (d[2] < 0.0 && zn <= lp->d) { face = 2; zf = lp->d; }",
      "if (d[2] < 0.0 && zn <= 0.0) { face = 2; zf = lp->d; }"),
+    ("jacobian_slot_index_transposed", "jacB[(int64_t)r.slot * P + j] += r.x * score[j];",
+     "jacB[(int64_t)j * (nb + 2) + r.slot] += r.x * score[j];"),
+    ("jacobian_total_times_cotangent", "jacR[j] += r.x * score[j];",
+     "jacR[j] += r.x * cot * score[j];"),
 ]
 
 

@@ -104,6 +104,10 @@ def test_adjoint_against_crn_finite_differences():
     _assert(P.check_adjoint_vs_crn_fd())
 
 
+def test_adjoint_jacobian_output():
+    _assert(P.check_jacobian())
+
+
 def test_results_do_not_depend_on_thread_count():
     geo = O.Geometry(n_media=3, n_rel=1.4)
     args = ([[1.0], [5.0], [0.2]], [[0.9], [0.5], [0.99]], [[0.7], [0.1], [0.2]],
