@@ -307,13 +307,20 @@ typedef struct {
   float min_mass;        /* bins with mass < min_mass stay out of the shape term */
   float shape_floor;     /* relative floor f: the shape term compares
                             log(P + f P_t) with log(P_t + f P_t) */
+  int32_t shape_form;    /* RW_LUT_SHAPE_PAPER: P_hat = sum_k w_k P_k, as Sec. 4.2
+                            defines it after eq. refl_loss; RW_LUT_SHAPE_MIXTURE:
+                            the normalised profile of eq. mixture,
+                            P_hat = sum_k w_k R_k P_k / max(R_hat, 1e-12) */
 } rw_lut_targets;
+
+#define RW_LUT_SHAPE_PAPER 0
+#define RW_LUT_SHAPE_MIXTURE 1
 
 /* Loss and gradient of eq. joint_loss for K media per unit (K = 1..4):
  *   L = sqrt(mean over bins with mass >= min_mass of
  *            (log(P_hat + f P_t + 1e-12) - log(P_t + f P_t + 1e-12))^2 + 1e-30)
  *       + lambda_R (R_hat - R_t)^2,
- * R_hat = sum_k w_k R(alpha_k, g_k), P_hat = sum_k w_k R_k P_k / max(R_hat, 1e-12).
+ * R_hat = sum_k w_k R(alpha_k, g_k), P_hat as targets->shape_form selects.
  * params: DEVICE float [4K - 1][n_units] raw parameters (row-major by
  * parameter): log sigma_t (K rows), logit alpha (K), logit(g / 0.99) (K) and
  * the first K - 1 softmax logits of the weights (the last logit is 0).

@@ -138,6 +138,7 @@ struct LutArgs {
   const float* r_mm;           // [n_r]
   int32_t n_r;
   float lambda_R, min_mass, shape_floor;
+  int32_t shape_form;          // RW_LUT_SHAPE_PAPER or RW_LUT_SHAPE_MIXTURE
   int64_t n_units;
   const float* params;         // read
   float* params_out;           // Adam writes here (the same array: in place)

@@ -1,7 +1,9 @@
 // Lookup-table fit (Sec. 4.2): the K-media profile of eq. mixture from the
 // scale-independent tables R(alpha, g) and P_d(r | alpha, g) at sigma_t = 1,
 // the per-unit loss of eq. joint_loss, its analytic gradient and an Adam step,
-// fused in one kernel.
+// fused in one kernel.  The shape term compares P_hat = sum_k w_k P_k, as
+// defined after eq. refl_loss, or (shape_form = mixture) the normalised
+// profile of eq. mixture, sum_k w_k R_k P_k / R_hat.
 //
 // One wavefront per unit; lanes stride over the evaluation radii.  Every
 // per-radius term of the gradient is linear in the shape term's per-unit
@@ -98,6 +100,12 @@ __global__ void __launch_bounds__(256) lut_fit_kernel(const LutArgs a) {
   }
   const float Rc = fmaxf(R_hat, 1e-12f);
   const float inv_Rc = 1.0f / Rc;
+  // profile weights of the media: w_k (paper form) or w_k R_k / R_hat (mixture)
+  const bool mix = a.shape_form == RW_LUT_SHAPE_MIXTURE;
+  const float pnorm = mix ? inv_Rc : 1.0f;
+  float cw[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) cw[k] = mix ? w[k] * Rk[k] : w[k];
 
   // one pass over the radii: loss sums and unscaled gradient sums
   float sum_d2 = 0.0f, cnt = 0.0f, s_rd = 0.0f;
@@ -135,9 +143,9 @@ __global__ void __launch_bounds__(256) lut_fit_kernel(const LutArgs a) {
       dPa[k] = s2 * (2.0f * val + dfb * cb.dt * a.inv_step);
       dPb[k] = s2 * dfa * ca[k].dt;   // per unit of alpha
       dPc[k] = s2 * dfg * cg[k].dt;   // per unit of g
-      Rd += w[k] * Rk[k] * Pk[k];
+      Rd += cw[k] * Pk[k];
     }
-    const float Pd = Rd * inv_Rc;
+    const float Pd = Rd * pnorm;
     const int64_t tj = u * a.n_r + j;
     float q = 0.0f;
     if (a.t_mass[tj] >= a.min_mass) {
@@ -149,8 +157,8 @@ __global__ void __launch_bounds__(256) lut_fit_kernel(const LutArgs a) {
       cnt += 1.0f;
       q = d / den;
     }
-    const float uq = q * inv_Rc;
-    s_rd += q * Rd;
+    const float uq = q * pnorm;
+    s_rd += q * Rd;  // the mixture form's dependence on R_hat
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       A[k] += uq * Pk[k];
@@ -174,17 +182,20 @@ __global__ void __launch_bounds__(256) lut_fit_kernel(const LutArgs a) {
   const float scale = 1.0f / (ncnt * shape);
   const float dR = R_hat - a.t_R[u];
   const float loss = shape + a.lambda_R * dR * dR;
-  // d L / d R_hat: the reflectance term and the normalisation of P_hat
-  const float gRh = 2.0f * a.lambda_R * dR - (R_hat > 1e-12f ? scale * s_rd * inv_Rc * inv_Rc : 0.0f);
+  // d L / d R_hat: the reflectance term, and in the mixture form the
+  // normalisation of P_hat
+  const float gRh =
+      2.0f * a.lambda_R * dR - (mix && R_hat > 1e-12f ? scale * s_rd * inv_Rc * inv_Rc : 0.0f);
 
   float gr[P];
   float gw[K], wgw = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float sA = scale * A[k];
-    gw[k] = Rk[k] * sA + gRh * Rk[k];
-    const float gRk = w[k] * sA + gRh * w[k];
-    const float wr = w[k] * Rk[k] * scale;
+    // d L / d w_k and d L / d R_k; wr: d L / d P_k per unit of the radial sums
+    gw[k] = (mix ? Rk[k] * sA : sA) + gRh * Rk[k];
+    const float gRk = (mix ? w[k] * sA : 0.0f) + gRh * w[k];
+    const float wr = cw[k] * scale;
     gr[k] = wr * Ba[k];                                                   // log sigma_t
     gr[K + k] = (wr * Bb[k] + gRk * dRa[k]) * alb[k] * (1.0f - alb[k]);   // logit alpha
     gr[2 * K + k] = (wr * Bc[k] + gRk * dRg[k]) * 0.99f * sg[k] * (1.0f - sg[k]);  // logit(g/0.99)

@@ -846,6 +846,9 @@ rw_status lut_args(rw_context* ctx, const rw_lut* lut, const rw_lut_targets* t, 
   a->lambda_R = t->lambda_R;
   a->min_mass = t->min_mass;
   a->shape_floor = t->shape_floor;
+  if (t->shape_form != RW_LUT_SHAPE_PAPER && t->shape_form != RW_LUT_SHAPE_MIXTURE)
+    return fail(ctx, RW_E_INVALID, "shape_form must be RW_LUT_SHAPE_PAPER or RW_LUT_SHAPE_MIXTURE");
+  a->shape_form = t->shape_form;
   a->n_units = n_units;
   a->params = params;
   return RW_OK;

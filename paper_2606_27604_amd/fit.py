@@ -226,7 +226,7 @@ def run_fit(n_targets: int = 4096, iters: int = 200, paths: int = 4096, target_p
 def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_paths: int = 1 << 14,
                 target_paths: int = 1 << 18, lr: float = 1e-2, noise: float = 0.01, seed: int = 5,
                 device: str = "cuda", schedule: str = "constant", init_k1_iters: int = 0,
-                progress: bool = False) -> dict:
+                progress: bool = False, shape_form: str = "paper") -> dict:
     """The paper's own fitting route on the same targets as run_fit: tables
     R(alpha, g), P_d(r | alpha, g) from the walk at sigma_t = 1 (lut_n x lut_n
     cells at lut_paths photons), then Adam on eq. joint_loss with the LUT
@@ -255,7 +255,7 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
     t1 = time.perf_counter()
     (s, a, g, w), hist = L.fit(table, tg["R_noisy"], tg["Pd_noisy"], tg["mass"], start, r,
                                 iters=iters, lr=lr, schedule=schedule, init_k1_iters=init_k1_iters,
-                                ctx=ctx)
+                                ctx=ctx, shape_form=shape_form)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t1
     with torch.no_grad():
@@ -266,7 +266,7 @@ def run_lut_fit(n_targets: int = 256, iters: int = 200, lut_n: int = 128, lut_pa
     return {"workload": f"LUT refit: {n_targets} targets x {n_wl} wavelengths, LUT {lut_n}x{lut_n} "
                         f"at {lut_paths} photons, {iters} Adam steps ({schedule} schedule"
                         + (f", K = 1 profile start of {init_k1_iters} steps" if init_k1_iters else "")
-                        + ")",
+                        + f", P_hat of the {shape_form} form)",
             "lut_seconds": t_lut, "fit_seconds": t_fit, "loss_history": hist,
             "spectral_rmse": rmse, "recovery_median_abs_error": recovery((s, a, g, w), true)}
 
@@ -284,13 +284,17 @@ def main():
     ap.add_argument("--schedule", choices=("constant", "cosine"), default="constant")
     ap.add_argument("--lut-init-k1", type=int, default=0,
                     help="steps of the K = 1 profile-only fit that starts the LUT fit")
+    ap.add_argument("--lut-shape-form", choices=("paper", "mixture"), default="paper",
+                    help="P_hat of the LUT fit's shape term: sum_k w_k P_k (paper) or the "
+                         "normalised profile of eq. mixture")
     args = ap.parse_args()
     res = run_fit(args.targets, args.iters, args.paths, args.target_paths, log_every=args.log_every,
                   schedule=args.schedule, progress=True)
     if args.lut:
         res["lut_fit"] = run_lut_fit(args.targets, args.iters, args.lut, args.lut_paths,
                                      args.target_paths, schedule=args.schedule,
-                                     init_k1_iters=args.lut_init_k1, progress=True)
+                                     init_k1_iters=args.lut_init_k1, progress=True,
+                                     shape_form=args.lut_shape_form)
     print(json.dumps(res), flush=True)
 
 

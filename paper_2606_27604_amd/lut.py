@@ -16,9 +16,10 @@ with R bilinear in (alpha, g) and P trilinear in (alpha, g, log r), the radial
 coordinate scaled by sigma_t as above.  The loss is eq. joint_loss (lambda_R =
 5) and the optimiser Adam.  Each optimisation step is one fused HIP kernel
 (rw_lut_fit_step: the lookups, the loss, its analytic gradient and the Adam
-update, one wavefront per unit); the tables come from the walk kernel.
-lookup_R, lookup_P and mixture_profile evaluate the same model with torch
-tensor operations (for inspection and plots).
+update, one wavefront per unit); the tables come from the walk kernel.  The
+shape term compares P_hat = sum_k w_k P_k, the definition after eq.
+refl_loss (shape_form "paper", the default), or the normalised profile of
+eq. mixture, sum_k w_k R_k P_k / R_hat (shape_form "mixture").
 
 Readings: the grid is uniform in alpha over [0, alpha_max] and in g over
 [0, g_max] (the paper gives the size, not the spacing); radial interpolation is
@@ -92,77 +93,6 @@ def generate(ctx: rw.Context, n_alpha: int, n_g: int, paths: int, n_rel: float =
                r_min, r_max, n_rel, paths)
 
 
-def _cell(t: torch.Tensor, n: int):
-    """Cell index i in [0, n - 2] and weight t - i of a continuous grid coordinate
-    t (clamped to [0, n - 1]); the index is clamped as an integer, so i + 1 is
-    always a valid grid index (a float bound such as n - 1 - eps rounds to
-    n - 1 in FP32 for large n)."""
-    t = t.clamp(0.0, float(n - 1))
-    i = t.floor().long().clamp(0, max(n - 2, 0))
-    return i, t - i.to(t.dtype)
-
-
-def _grid_coord(x: torch.Tensor, grid: torch.Tensor):
-    """Index and weight of x on a uniform grid (clamped to its range)."""
-    n = grid.numel()
-    lo, hi = float(grid[0]), float(grid[-1])
-    return _cell((x - lo) / (hi - lo) * (n - 1), n)
-
-
-def lookup_R(lut: LUT, alpha: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
-    """Bilinear R(alpha, g)."""
-    ia, wa = _grid_coord(alpha, lut.alpha)
-    ig, wg = _grid_coord(g, lut.g)
-    T = lut.R
-    r00, r01 = T[ia, ig], T[ia, ig + 1]
-    r10, r11 = T[ia + 1, ig], T[ia + 1, ig + 1]
-    return ((1 - wa) * ((1 - wg) * r00 + wg * r01) + wa * ((1 - wg) * r10 + wg * r11))
-
-
-def lookup_P(lut: LUT, alpha: torch.Tensor, g: torch.Tensor, sigma_t: torch.Tensor,
-             r: torch.Tensor) -> torch.Tensor:
-    """Trilinear P(r | alpha, g, sigma_t) = sigma_t^2 P_d(sigma_t r | alpha, g, 1)
-    (eq. separability); alpha, g, sigma_t: [...]; r: [n_r] radii in mm.
-    Returns [..., n_r]."""
-    ia, wa = _grid_coord(alpha, lut.alpha)
-    ig, wg = _grid_coord(g, lut.g)
-    nb = lut.n_bins
-    # bin centres of the table, log-spaced
-    lr_min, lr_max = math.log(lut.r_min), math.log(lut.r_max)
-    step = (lr_max - lr_min) / nb
-    x = torch.log(sigma_t[..., None] * r) - (lr_min + 0.5 * step)   # [..., n_r]
-    tb = x / step
-    # the table covers [r_min, r_max): half a bin beyond the outer centres (with
-    # a rounding margin), held constant there
-    inside = (tb >= -0.5 - 1e-3) & (tb <= nb - 0.5 + 1e-3)
-    ib, wb = _cell(tb, nb)
-    flat = lut.Pd.reshape(-1)
-    ng = lut.g.numel()
-
-    def corner(da, dg):
-        # flat index of (alpha cell, g cell, radial cell): only the needed
-        # entries are gathered, never a whole [..., nb] plane per unit
-        base = (((ia + da) * ng + (ig + dg)) * nb)[..., None]
-        lo = flat[base + ib]
-        hi = flat[base + ib + 1]
-        return (1 - wb) * lo + wb * hi
-
-    wa_, wg_ = wa[..., None], wg[..., None]
-    val = ((1 - wa_) * ((1 - wg_) * corner(0, 0) + wg_ * corner(0, 1)) +
-           wa_ * ((1 - wg_) * corner(1, 0) + wg_ * corner(1, 1)))
-    return torch.where(inside, val, torch.zeros_like(val)) * (sigma_t[..., None] ** 2)
-
-
-def mixture_profile(lut: LUT, sigma_t, albedo, g, w, r):
-    """eq. mixture: R_hat = sum_k w_k R_k and R_d(r) = sum_k w_k R_k P_k(r);
-    parameters [K, n_units].  Returns (R_hat [n], R_d [n, n_r])."""
-    Rk = lookup_R(lut, albedo, g)                          # [K, n]
-    Pk = lookup_P(lut, albedo, g, sigma_t, r)              # [K, n, n_r]
-    R_hat = (w * Rk).sum(0)
-    Rd = ((w * Rk)[..., None] * Pk).sum(0)
-    return R_hat, Rd
-
-
 # Components of the K = 1 initialisation: extinction factors around the K = 1 fit
 K1_SPREAD = (0.5, 1.0, 2.0, 4.0)
 
@@ -177,7 +107,11 @@ def _native_tables(lut: LUT):
     return c, (R, Pd)
 
 
-def _native_targets(R_t, Pd_t, mass_t, r, lambda_R: float):
+SHAPE_FORMS = {"paper": rw.RW_LUT_SHAPE_PAPER, "mixture": rw.RW_LUT_SHAPE_MIXTURE}
+
+
+def _native_targets(R_t, Pd_t, mass_t, r, lambda_R: float, shape_form: str = "paper",
+                    min_mass: float | None = None, shape_floor: float | None = None):
     from .fit import MIN_BIN_MASS, SHAPE_FLOOR
 
     R = R_t.float().contiguous()
@@ -185,7 +119,9 @@ def _native_targets(R_t, Pd_t, mass_t, r, lambda_R: float):
     mass = mass_t.float().contiguous()
     rr = r.float().contiguous()
     c = rw.RwLutTargetsC(R.data_ptr(), Pd.data_ptr(), mass.data_ptr(), rr.data_ptr(), rr.numel(),
-                         float(lambda_R), MIN_BIN_MASS, SHAPE_FLOOR)
+                         float(lambda_R), MIN_BIN_MASS if min_mass is None else float(min_mass),
+                         SHAPE_FLOOR if shape_floor is None else float(shape_floor),
+                         SHAPE_FORMS[shape_form])
     return c, (R, Pd, mass, rr)
 
 
@@ -223,7 +159,7 @@ def _adam_native(ctx, tabs, tg, params, K, iters, lr, schedule, hist, tag):
 
 def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
         start, r: torch.Tensor, iters: int = 200, lr: float = 1e-2, schedule: str = "constant",
-        init_k1_iters: int = 0, ctx: rw.Context | None = None):
+        init_k1_iters: int = 0, ctx: rw.Context | None = None, shape_form: str = "paper"):
     """Adam over (log sigma_t, logit alpha, logit g / 0.99, K - 1 free logits)
     per unit on eq. joint_loss with the LUT model (Sec. 4.2, "Optimization"),
     one fused HIP kernel launch per step (rw_lut_fit_step: lookups, loss,
@@ -236,6 +172,8 @@ def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
     the paper initialises its fit; the K components then start at that medium
     with sigma_t scaled by 0.5, 1, 2 (, 4) and equal weights, since identical
     components would stay identical under a symmetric loss.
+    shape_form selects P_hat of the shape term ("paper" or "mixture", see the
+    module docstring).
     Returns the fitted physical parameters and the loss history
     [(stage, iteration, mean loss before the step)]."""
     from .fit import LAMBDA_R
@@ -249,13 +187,13 @@ def fit(lut: LUT, R_t: torch.Tensor, Pd_t: torch.Tensor, mass_t: torch.Tensor,
     if init_k1_iters > 0:
         one = torch.ones((1, n), dtype=torch.float64, device=dev)
         p1 = raw_from_physical(one, 0.9 * one, 0.5 * one, one)
-        tg1 = _native_targets(R_t, Pd_t, mass_t, r, 0.0)
+        tg1 = _native_targets(R_t, Pd_t, mass_t, r, 0.0, shape_form)
         _adam_native(ctx, tabs, tg1, p1, 1, init_k1_iters, lr, schedule, hist, "k1")
         s1, a1, g1, _ = physical_from_raw(p1, 1)
         f = torch.tensor(K1_SPREAD[:K], dtype=torch.float64, device=dev)[:, None]
         start = (s1 * f, a1.expand(K, n), g1.expand(K, n),
                  torch.full((K, n), 1.0 / K, dtype=torch.float64, device=dev))
     params = raw_from_physical(*start)
-    tg = _native_targets(R_t, Pd_t, mass_t, r, LAMBDA_R)
+    tg = _native_targets(R_t, Pd_t, mass_t, r, LAMBDA_R, shape_form)
     _adam_native(ctx, tabs, tg, params, K, iters, lr, schedule, hist, "mix")
     return physical_from_raw(params, K), hist

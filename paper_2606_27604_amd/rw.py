@@ -99,6 +99,7 @@ class RwLutTargetsC(ctypes.Structure):
         ("lambda_R", ctypes.c_float),
         ("min_mass", ctypes.c_float),
         ("shape_floor", ctypes.c_float),
+        ("shape_form", ctypes.c_int32),
     ]
 
 
@@ -119,6 +120,8 @@ class RwBatchOptsC(ctypes.Structure):
         ("unit_end", ctypes.c_int64),
     ]
 
+
+RW_LUT_SHAPE_PAPER, RW_LUT_SHAPE_MIXTURE = 0, 1
 
 EXPORTS = [
     "rw_create", "rw_destroy", "rw_last_error", "rw_status_string", "rw_forward",

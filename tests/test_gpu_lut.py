@@ -1,26 +1,51 @@
-"""GPU: lookup tables from the batched walk (Sec. 4.2) and the LUT-based fit.
+"""GPU: lookup tables from the batched walk (Sec. 4.2) and the fused LUT-fit
+kernel, checked against the FP64 LUT oracle (oracle/lut_oracle.py).
 
-Pins: with n = 1 and g = 0 the table's R(alpha) is the plane albedo
+Tables: with n = 1 and g = 0 the table's R(alpha) is the plane albedo
 1 - H(1) sqrt(1 - alpha) (closed form); eq. separability (a sigma_t = 2 walk
-against the table's sigma_t^2 P_d(sigma_t r) prediction); eq. mixture with a
-one-hot weight reproduces the single-medium table row; the LUT fit lowers
-eq. joint_loss on targets drawn from the table model itself."""
+against the oracle's sigma_t^2 P_d(sigma_t r) prediction from the table).
+Kernel: loss and gradient of eq. joint_loss (both definitions of P_hat, with
+and without the mass threshold and floor), three Adam steps, and a whole fit
+with the paper's schedule, each against the oracle on the same FP32 inputs;
+the fit lowers the loss on a table made by the walk."""
 import math
 
 import numpy as np
 import pytest
 
 from oracle import closed_forms as cf
+from oracle import lut_oracle as LO
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 from paper_2606_27604_amd import rw  # noqa: E402
+from tests import lut_tables as T  # noqa: E402
 from tests.gpu_common import ctx, np64  # noqa: E402
+
+FORMS = {"paper": LO.SHAPE_PAPER, "mixture": LO.SHAPE_MIXTURE}
+
+
+def _oracle_table(t):
+    """The oracle's view of a product table (the same FP32 values, in FP64)."""
+    return LO.Table(np64(t.R), np64(t.Pd), float(t.alpha[-1]), float(t.g[-1]), t.r_min, t.r_max)
+
+
+def _product_table(tab):
+    from paper_2606_27604_amd import lut as L
+    f32 = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")  # noqa: E731
+    return L.LUT(f32(np.linspace(0.0, tab.alpha_max, tab.n_alpha)),
+                 f32(np.linspace(0.0, tab.g_max, tab.n_g)), f32(tab.R), f32(tab.Pd), tab.r_min,
+                 tab.r_max, 1.4, 1)
+
+
+def _r_centres(n_bins, r_min, r_max):
+    step = (math.log(r_max) - math.log(r_min)) / n_bins
+    return np.exp(math.log(r_min) + (np.arange(n_bins) + 0.5) * step)
 
 
 def test_table_R_matches_plane_albedo_and_separability():
-    from paper_2606_27604_amd import api, lut, rw
+    from paper_2606_27604_amd import api, lut
     N = 1 << 20
     t = lut.generate(ctx(), 9, 2, N, n_rel=1.0, alpha_max=0.99, g_max=0.5)
     al = np64(t.alpha)
@@ -36,15 +61,13 @@ def test_table_R_matches_plane_albedo_and_separability():
     res = api.forward(ctx(), m, geom, 1 << 20, 3)
     # the walk's own bins (256 over [1e-3, 50] mm), predicted from the wider table
     nb = geom.n_bins
-    step = (math.log(geom.r_max_mm) - math.log(geom.r_min_mm)) / nb
-    r = torch.exp(math.log(geom.r_min_mm) +
-                  (torch.arange(nb, device="cuda", dtype=torch.float32) + 0.5) * step)
-    pred = lut.lookup_P(t, t.alpha[6:7], t.g[1:2], torch.full((1,), 2.0, device="cuda"), r)[0]
+    r = _r_centres(nb, geom.r_min_mm, geom.r_max_mm)
+    pr = LO.lookup_P(_oracle_table(t), np.array([a]), np.array([g]), np.array([2.0]), r)[0][0]
     got = np64(res.Pd[0])
-    pr = np64(pred)
     # compare where both sides expect >= 400 exits in the bin (relative noise
     # <= 5 %): mass per bin = P x annulus area (the sigma_t^2 of the rescaling
     # cancels against the area of the scaled annulus)
+    step = (math.log(geom.r_max_mm) - math.log(geom.r_min_mm)) / nb
     edges = geom.r_min_mm * np.exp(np.arange(nb + 1) * step)
     area = np.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
     Rw, Rt = float(res.R[0]), float(t.R[6, 1])
@@ -53,137 +76,135 @@ def test_table_R_matches_plane_albedo_and_separability():
     assert ok.sum() > 40 and np.median(rel) < 0.05, (ok.sum(), np.median(rel))
 
 
-def test_mixture_one_hot_and_lut_fit_lowers_loss():
-    from paper_2606_27604_amd import fit, lut
-    t = lut.generate(ctx(), 33, 33, 1 << 12)
-    nb = t.n_bins
-    step = (math.log(t.r_max) - math.log(t.r_min)) / nb
-    r = torch.exp(math.log(t.r_min) + (torch.arange(nb, device="cuda", dtype=torch.float32) + 0.5) * step)
-    # one-hot weights reproduce the table at a grid point (sigma_t = 1)
-    K, n = 3, 1
-    s = torch.ones((K, n), device="cuda")
-    al = torch.stack([t.alpha[20], t.alpha[5], t.alpha[7]])[:, None]
-    gg = torch.stack([t.g[10], t.g[3], t.g[4]])[:, None]
-    w = torch.tensor([[1.0], [0.0], [0.0]], device="cuda")
-    R_hat, Rd = lut.mixture_profile(t, s, al, gg, w, r)
-    assert abs(float(R_hat[0]) - float(t.R[20, 10])) < 1e-6
-    # the FP32 grid coordinate of a grid point is within ~1e-5 of an integer, so
-    # that share of a neighbouring cell of the (noisy) table can leak in
-    nbr = float(t.Pd[19:22, 9:12].max())
-    np.testing.assert_allclose(np64(Rd[0]) / float(t.R[20, 10]), np64(t.Pd[20, 10]), rtol=1e-4,
-                               atol=1e-4 * nbr)
-    # targets from the table model, fit from another start: the loss drops
-    gen = np.random.default_rng(3)
-    n = 64
-    tr = [torch.tensor(x, device="cuda") for x in (
-        (10 ** gen.uniform(-0.5, 1, (K, n))).astype(np.float32),
-        gen.uniform(0.5, 0.98, (K, n)).astype(np.float32),
-        gen.uniform(0.0, 0.9, (K, n)).astype(np.float32),
-        gen.dirichlet(np.ones(K), n).T.astype(np.float32).copy())]
-    R_t, Rd_t = lut.mixture_profile(t, *tr, r)
-    Pd_t = (Rd_t / R_t[:, None]).double()
-    area = fit.bin_areas(type("G", (), {"n_bins": nb, "r_min_mm": t.r_min, "r_max_mm": t.r_max})(),
-                         "cuda")
-    mass = Pd_t * area
-    start = [torch.tensor(x, device="cuda") for x in (
-        (10 ** gen.uniform(-0.5, 1, (K, n))).astype(np.float32),
-        gen.uniform(0.5, 0.98, (K, n)).astype(np.float32),
-        gen.uniform(0.0, 0.9, (K, n)).astype(np.float32),
-        gen.dirichlet(np.ones(K), n).T.astype(np.float32).copy())]
-    _, hist = lut.fit(t, R_t.double(), Pd_t, mass, start, r, iters=150, lr=2e-2)
-    assert hist[-1][2] < 0.5 * hist[0][2], hist
-    # the paper's schedule: K = 1 profile-only start, cosine-annealed Adam
-    _, hist = lut.fit(t, R_t.double(), Pd_t, mass, start, r, iters=150, lr=2e-2,
-                      schedule="cosine", init_k1_iters=60)
-    k1 = [h for h in hist if h[0] == "k1"]
-    mix = [h for h in hist if h[0] == "mix"]
-    assert k1[-1][2] < k1[0][2] and mix[-1][2] < mix[0][2], hist
+def _problem(K, n, seed, form):
+    """The smooth synthetic table, targets from the oracle's model at random
+    parameters, a random start; FP32 copies for the kernel and the same values
+    in FP64 for the oracle."""
+    tab, r = T.smooth_table()
+    # the kernel reads the grid bounds in FP32
+    tab.alpha_max, tab.g_max = float(np.float32(tab.alpha_max)), float(np.float32(tab.g_max))
+    r = np.asarray(r, np.float32).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    s, a, g, w = T.random_params(rng, K, n)
+    Rk = np.stack([LO.lookup_R(tab, a[k], g[k])[0] for k in range(K)])
+    Pk = np.stack([LO.lookup_P(tab, a[k], g[k], s[k], r)[0] for k in range(K)])
+    R_t = (w * Rk).sum(0)
+    if form == LO.SHAPE_PAPER:
+        P_t = (w[..., None] * Pk).sum(0)
+    else:
+        P_t = ((w * Rk)[..., None] * Pk).sum(0) / R_t[:, None]
+    mass = T.annulus_mass(P_t, r)
+    f32 = lambda x: np.asarray(x, np.float32).astype(np.float64)  # noqa: E731
+    R_t, P_t, mass = f32(R_t), f32(P_t), f32(mass)
+    start = LO.raw_from_physical(*T.random_params(rng, K, n)).astype(np.float32)
+    return tab, r, R_t, P_t, mass, start
 
 
-def _smooth_problem(K=3, n=64, seed=4):
-    """A smooth synthetic table on the GPU, targets from its own model at
-    random parameters, and a random raw start (tests.test_lut_cpu's table)."""
+def _native(tab, r, R_t, P_t, mass, lambda_R, form, min_mass, floor):
     from paper_2606_27604_amd import lut as L
-    from tests.test_lut_cpu import _smooth_table
-    t, r = _smooth_table()
-    t = L.LUT(t.alpha.cuda(), t.g.cuda(), t.R.cuda(), t.Pd.cuda(), t.r_min, t.r_max, t.n_rel,
-              t.paths)
-    r = r.cuda()
-    gen = torch.Generator(device="cuda").manual_seed(seed)
-    truth = (10 ** (torch.rand((K, n), generator=gen, device="cuda") - 0.5),
-             0.5 + 0.45 * torch.rand((K, n), generator=gen, device="cuda"),
-             0.8 * torch.rand((K, n), generator=gen, device="cuda"),
-             torch.softmax(torch.randn((K, n), generator=gen, device="cuda"), 0))
-    R_t, Rd_t = L.mixture_profile(t, *truth, r)
-    Pd_t = (Rd_t / R_t[:, None]).double()
-    lr_ = torch.log(r.double())
-    h = float(lr_[1] - lr_[0])
-    edges = torch.exp(torch.cat([lr_ - 0.5 * h, lr_[-1:] + 0.5 * h]))
-    mass = Pd_t * math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
-    start = (10 ** (torch.rand((K, n), generator=gen, device="cuda") - 0.5),
-             0.5 + 0.45 * torch.rand((K, n), generator=gen, device="cuda"),
-             0.8 * torch.rand((K, n), generator=gen, device="cuda"),
-             torch.softmax(torch.randn((K, n), generator=gen, device="cuda"), 0))
-    return t, r, R_t.double(), Pd_t, mass, start
+    cuda = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")  # noqa: E731
+    pt = _product_table(tab)
+    tabs = L._native_tables(pt)
+    tg = L._native_targets(cuda(R_t), cuda(P_t), cuda(mass), cuda(r), lambda_R, form, min_mass,
+                           floor)
+    return pt, tabs, tg
 
 
-@pytest.mark.parametrize("K", [1, 3])
-def test_lut_kernel_loss_and_gradient_match_autograd(K):
-    from paper_2606_27604_amd import lut as L
-    from tests.lut_reference import loss_reference
-    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=K)
-    n = R_t.numel()
-    params = L.raw_from_physical(*start)
-    tabs = L._native_tables(t)
-    tg = L._native_targets(R_t, Pd_t, mass, r, 5.0)
+@pytest.mark.parametrize("form", ["paper", "mixture"])
+@pytest.mark.parametrize("K,min_mass,floor", [(1, 0.0, 0.0), (3, 0.0, 0.0), (3, 1e-3, 1e-2),
+                                              (4, 1e-3, 1e-2)])
+def test_lut_kernel_loss_and_gradient_match_oracle(form, K, min_mass, floor):
+    tab, r, R_t, P_t, mass, start = _problem(K, 64, 10 + K, FORMS[form])
+    n = R_t.size
+    _, tabs, tg = _native(tab, r, R_t, P_t, mass, 5.0, form, min_mass, floor)
+    params = torch.tensor(start, device="cuda")
     grad = torch.zeros_like(params)
     loss = torch.zeros(n, dtype=torch.float32, device="cuda")
     rw.rw_lut_loss_grad(ctx(), tabs[0], tg[0], n, K, params, grad, loss)
     torch.cuda.synchronize()
-    p64 = params.double().clone().requires_grad_(True)
-    ref = loss_reference(t, p64, K, R_t, Pd_t, mass, r)
-    ref.sum().backward()
-    np.testing.assert_allclose(np64(loss), np64(ref.detach()), rtol=2e-4, atol=1e-6)
-    G, Gr = np64(grad), np64(p64.grad)
-    scale = np.abs(Gr).max(axis=0, keepdims=True)
-    np.testing.assert_allclose(G, Gr, rtol=3e-3, atol=1e-3 * float(scale.max()))
+    mm = float(np.float32(min_mass))
+    ref_loss, ref_grad = LO.loss_and_grad(tab, start.astype(np.float64), K, R_t, P_t, mass, r,
+                                          5.0, mm, float(np.float32(floor)), FORMS[form])
+    np.testing.assert_allclose(np64(loss), ref_loss, rtol=2e-4, atol=1e-6)
+    G = np64(grad)
+    scale = np.abs(ref_grad).max()
+    np.testing.assert_allclose(G, ref_grad, rtol=3e-3, atol=1e-3 * scale)
 
 
-def test_lut_kernel_adam_steps_match_torch_adam():
-    from paper_2606_27604_amd import lut as L
-    from tests.lut_reference import loss_reference
+@pytest.mark.parametrize("form", ["paper", "mixture"])
+def test_lut_kernel_adam_steps_match_oracle(form):
     K = 3
-    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=K, n=32, seed=5)
-    n = R_t.numel()
-    params = L.raw_from_physical(*start)
-    ref = params.double().clone().requires_grad_(True)
-    opt = torch.optim.Adam([ref], lr=1e-2)
+    tab, r, R_t, P_t, mass, start = _problem(K, 32, 5, FORMS[form])
+    n = R_t.size
+    _, tabs, tg = _native(tab, r, R_t, P_t, mass, 5.0, form, 0.0, 0.0)
+    params = torch.tensor(start, device="cuda")
     m, v = torch.zeros_like(params), torch.zeros_like(params)
-    tabs = L._native_tables(t)
-    tg = L._native_targets(R_t, Pd_t, mass, r, 5.0)
+    p = start.astype(np.float64)
+    pm, pv = np.zeros_like(p), np.zeros_like(p)
     for step in (1, 2, 3):
         rw.rw_lut_fit_step(ctx(), tabs[0], tg[0], n, K, params, m, v, step, 1e-2)
-        opt.zero_grad()
-        loss_reference(t, ref, K, R_t, Pd_t, mass, r).sum().backward()
-        opt.step()
+        _, gr = LO.loss_and_grad(tab, p, K, R_t, P_t, mass, r, 5.0, 0.0, 0.0, FORMS[form])
+        p, pm, pv = LO.adam_step(p, gr, pm, pv, step, 1e-2)
         torch.cuda.synchronize()
         # each Adam step moves a parameter by at most ~lr; the two agree to a
         # small fraction of that (tiny gradients, whose step is eps-limited,
         # may differ)
-        d = np.abs(np64(params) - np64(ref.detach()))
+        d = np.abs(np64(params) - p)
         assert np.quantile(d, 0.98) <= 1e-3 * step, np.quantile(d, 0.98)
 
 
-def test_native_fit_follows_the_reference_fit():
+def test_native_fit_follows_the_oracle_fit():
+    """lut.fit (one fused kernel per Adam step) against the oracle's fit with the
+    paper's schedule: the K = 1 profile-only start, then all components, cosine
+    learning rate."""
     from paper_2606_27604_amd import lut as L
-    from tests.lut_reference import fit_reference
-    t, r, R_t, Pd_t, mass, start = _smooth_problem(K=3, n=48, seed=6)
-    (s1, a1, g1, w1), h1 = L.fit(t, R_t, Pd_t, mass, start, r, iters=60, lr=2e-2,
-                                 schedule="cosine", init_k1_iters=30, ctx=ctx())
-    (s2, a2, g2, w2), h2 = fit_reference(t, R_t, Pd_t, mass, start, r, iters=60, lr=2e-2,
-                                         schedule="cosine", init_k1_iters=30)
+    K, n = 3, 48
+    tab, r, R_t, P_t, mass, start = _problem(K, n, 6, LO.SHAPE_PAPER)
+    cuda = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")  # noqa: E731
+    pt = _product_table(tab)
+    st = tuple(torch.tensor(x, device="cuda") for x in LO.physical(start.astype(np.float64), K)[:4])
+    from paper_2606_27604_amd.fit import MIN_BIN_MASS, SHAPE_FLOOR
+    _, h1 = L.fit(pt, cuda(R_t), cuda(P_t), cuda(mass), st, cuda(r), iters=60, lr=2e-2,
+                  schedule="cosine", init_k1_iters=30, ctx=ctx())
+    _, h2 = LO.fit(tab, R_t, P_t, mass, start, K, r, iters=60, lr=2e-2, schedule="cosine",
+                   init_k1_iters=30, min_mass=float(np.float32(MIN_BIN_MASS)),
+                   shape_floor=float(np.float32(SHAPE_FLOOR)))
+    assert [h[:2] for h in h1] == [h[:2] for h in h2]
     l1 = np.array([h[2] for h in h1])
     l2 = np.array([h[2] for h in h2])
-    assert [h[:2] for h in h1] == [h[:2] for h in h2]
     np.testing.assert_allclose(l1, l2, rtol=5e-2)
     assert l1[-1] < l1[[i for i, h in enumerate(h1) if h[0] == "mix"][0]]
+
+
+@pytest.mark.parametrize("form", ["paper", "mixture"])
+def test_lut_fit_lowers_the_loss_on_a_walk_table(form):
+    """A 33 x 33 table from the batched walk; targets from the oracle's model on
+    that table; the native fit from another start lowers the loss."""
+    from paper_2606_27604_amd import lut as L
+    t = L.generate(ctx(), 33, 33, 1 << 12)
+    tab = _oracle_table(t)
+    r = _r_centres(256, 1e-3, 50.0).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(3)
+    K, n = 3, 64
+    s, a, g, w = (10 ** rng.uniform(-0.5, 1, (K, n)), rng.uniform(0.5, 0.98, (K, n)),
+                  rng.uniform(0.0, 0.9, (K, n)), rng.dirichlet(np.ones(K), n).T.copy())
+    Rk = np.stack([LO.lookup_R(tab, a[k], g[k])[0] for k in range(K)])
+    Pk = np.stack([LO.lookup_P(tab, a[k], g[k], s[k], r)[0] for k in range(K)])
+    R_t = (w * Rk).sum(0)
+    P_t = ((w[..., None] if form == "paper" else (w * Rk)[..., None]) * Pk).sum(0)
+    if form == "mixture":
+        P_t = P_t / R_t[:, None]
+    step = (math.log(50.0) - math.log(1e-3)) / 256
+    edges = 1e-3 * np.exp(np.arange(257) * step)
+    mass = P_t * np.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    cuda = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")  # noqa: E731
+    st = tuple(cuda(x) for x in (10 ** rng.uniform(-0.5, 1, (K, n)), rng.uniform(0.5, 0.98, (K, n)),
+                                 rng.uniform(0.0, 0.9, (K, n)), rng.dirichlet(np.ones(K), n).T.copy()))
+    _, hist = L.fit(t, cuda(R_t), cuda(P_t), cuda(mass), st, cuda(r), iters=150, lr=2e-2,
+                    shape_form=form, ctx=ctx())
+    assert hist[-1][2] < 0.5 * hist[0][2], hist
+    _, hist = L.fit(t, cuda(R_t), cuda(P_t), cuda(mass), st, cuda(r), iters=150, lr=2e-2,
+                    schedule="cosine", init_k1_iters=60, shape_form=form, ctx=ctx())
+    k1 = [h for h in hist if h[0] == "k1"]
+    mix = [h for h in hist if h[0] == "mix"]
+    assert k1[-1][2] < k1[0][2] and mix[-1][2] < mix[0][2], hist
