@@ -4,11 +4,20 @@ Scalars: |a - b| <= k * sqrt(se_a^2 + se_b^2) (k = 3 unless stated).
 Histograms: z-scores over slots that hold enough mass on both sides; accept when
 the chi-square of the z-scores is below its 0.999 quantile and the largest
 |z| is at most 5.  Fixed seeds make every outcome deterministic.
+
+Same random numbers: where both sides replay the same Philox streams, their
+difference comes only from paths whose FP32 and FP64 replays part at a
+threshold (a Fresnel or roulette draw, a boundary test, a bin edge within
+about 1e-6 of it), so the estimates agree to a small fraction of their
+standard error: |z| <= SAME_STREAM_Z.
 """
+
 from __future__ import annotations
 
 import numpy as np
 from scipy import stats
+
+SAME_STREAM_Z = 0.5
 
 
 def mean_se(sum_x, sum_x2, n):

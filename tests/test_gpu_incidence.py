@@ -11,7 +11,7 @@ import pytest
 from oracle import closed_forms as cf
 from oracle import oracle as O
 from paper_2606_27604_amd import api, rw, workloads
-from tests._stats import mean_se
+from tests._stats import SAME_STREAM_Z, mean_se
 
 pytestmark = pytest.mark.gpu
 
@@ -98,7 +98,7 @@ def test_cosine_mixture_forward_and_adjoint_vs_oracle():
     mg, sg = mean_se(np64(grad), np64(sq), N)
     mo, so = mean_se(og_, osq, N)
     z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
     # same random numbers: the two gradients are far closer than their SE
     close = np.abs(mg - mo) <= 0.25 * sg + 1e-9 * np.abs(mo).max()
     assert close.mean() >= 0.99, close.mean()

@@ -14,7 +14,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2606_27604_amd import api, rw, workloads
-from tests._stats import mean_se
+from tests._stats import SAME_STREAM_Z, mean_se
 
 pytestmark = pytest.mark.gpu
 
@@ -283,6 +283,62 @@ def test_autograd_function_matches_adjoint_and_finite_differences():
         assert np.all(np.abs(est - fd) <= 4 * sd + 1e-3 * np.abs(fd)), (k, est, fd, sd)
 
 
+def test_adjoint_against_crn_central_differences_every_parameter():
+    """The adjoint's vector-Jacobian product (v_R = 1, random bin cotangents)
+    against common-random-number central differences of the same
+    cotangent-weighted forward sums on the device, for every column: sigma_t
+    (h = 1e-3 sigma_t), albedo (h = 1e-3 alpha), g (h = 1e-3) and the softmax
+    logits (h = 1e-2: a logit step moves the medium-choice thresholds, so a
+    smaller one would rest on a handful of paths).  Units are independent, so
+    one pair of forward launches perturbs a medium of every unit at once.
+    Replica means over 8 seeds give the standard errors."""
+    K, n = 3, 4
+    rng = np.random.default_rng(12)
+    s = (10 ** rng.uniform(-0.5, 1, (K, n))).astype(np.float32)
+    a = rng.uniform(0.5, 0.95, (K, n)).astype(np.float32)
+    gg = rng.uniform(0.0, 0.8, (K, n)).astype(np.float32)
+    lg = rng.normal(0, 0.5, (K, n)).astype(np.float32)
+    g, _ = geoms(K, 1.4, n_bins=32, r_min=1e-2, r_max=20.0)
+    N = 1 << 15
+    cotB = rng.standard_normal((n, g.n_bins + 2)).astype(np.float32)
+    cR = torch.ones(n, dtype=torch.float32, device="cuda")
+    cB = torch.from_numpy(cotB).cuda()
+
+    def J(p4, seed):
+        res, flags = gpu_forward(media(*p4, logits=True), g, N, seed)
+        assert flags == 0
+        return (np64(res.tally.R)[:, 0] + (np64(res.tally.bins)[:, :, 0] * cotB).sum(1)) / N
+
+    reps, P = 8, 4 * K
+    adj = np.zeros((reps, n, P))
+    fd = np.zeros((reps, n, P))
+    for r in range(reps):
+        seed = 900 + r
+        grad, _, _, flags = api.adjoint(ctx(), media(s, a, gg, lg, logits=True), g, N, seed,
+                                        cot_R=cR, cot_bins=cB)
+        assert rw.rw_check(ctx(), flags) == 0
+        adj[r] = np64(grad) / N
+        for j in range(P):
+            grp, i = divmod(j, K)
+            base = [s, a, gg, lg]
+            x = base[grp]
+            h = (1e-3 * x[i], 1e-3 * x[i], np.full(n, 1e-3, np.float32),
+                 np.full(n, 1e-2, np.float32))[grp]
+            xp, xm = x.copy(), x.copy()
+            xp[i] = x[i] + h
+            xm[i] = x[i] - h
+            step = xp[i].astype(np.float64) - xm[i].astype(np.float64)  # the FP32 step taken
+            Jp = J([xp if q == grp else base[q] for q in range(4)], seed)
+            Jm = J([xm if q == grp else base[q] for q in range(4)], seed)
+            fd[r, :, j] = (Jp - Jm) / step
+    ma, sa = adj.mean(0), adj.std(0, ddof=1) / np.sqrt(reps)
+    mf, sf = fd.mean(0), fd.std(0, ddof=1) / np.sqrt(reps)
+    z = (ma - mf) / np.sqrt(sa ** 2 + sf ** 2 + 1e-30)
+    assert np.all(np.abs(z) <= 3.5), np.round(z, 2)
+    # most columns are resolved by the differences: the check is not vacuous
+    assert np.mean(np.abs(mf) > 2 * sf) > 0.5, np.round(mf / sf, 1)
+
+
 def test_full_size_81_wavelengths_sampled_units_vs_oracle():
     """The benchmark's workload and launch form (81 wavelengths x 2^20 paths,
     persistent graph launch) against the oracle on sampled units."""
@@ -335,7 +391,7 @@ def test_full_size_81_wavelengths_adjoint_sampled_units_vs_oracle():
         mg, sg = mean_se(G[u], S[u], N)
         mo, so = mean_se(og_[0], osq[0], N)
         z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-        assert np.all(np.abs(z) <= 3.5), (u, z)
+        assert np.all(np.abs(z) <= SAME_STREAM_Z), (u, z)
         zs += list(np.abs(z))
     # same random numbers: far inside the statistical error
     assert np.median(zs) <= 0.05, np.median(zs)
@@ -446,7 +502,7 @@ def test_adjoint_paths_outliving_their_wave_visit():
         mg, sg = mean_se(np64(ref[0])[u], np64(ref[1])[u], N)
         mo, so = mean_se(og_[0], osq[0], N)
         z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-        assert np.all(np.abs(z) <= 3.5), (u, z)
+        assert np.all(np.abs(z) <= SAME_STREAM_Z), (u, z)
 
 
 def test_adjoint_workload_subset_vs_oracle_gradient():
@@ -466,7 +522,7 @@ def test_adjoint_workload_subset_vs_oracle_gradient():
     mg, sg = mean_se(np64(grad), np64(sq), N)
     mo, so = mean_se(og_, osq, N)
     z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
     # same random numbers: far inside the statistical error
     assert np.median(np.abs(z)) <= 0.05, np.median(np.abs(z))
 
@@ -525,7 +581,7 @@ def test_full_size_adjoint_sweep_sampled_units_vs_oracle():
         mo, so = mean_se(og_, osq, N)
         zs.append(((mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)).ravel())
     z = np.concatenate(zs)
-    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
     # same random numbers: far inside the statistical error (a path whose FP32
     # and FP64 replays part at a threshold moves one unit's gradient by a
     # fraction of its SE, hence a median over the 144 sampled values)
@@ -583,7 +639,7 @@ def test_mixture_random_parameters_vs_oracle(K):
     mg, sg = mean_se(np64(grad), np64(sq), N)
     mo, so = mean_se(ogr, osq, N)
     z = np.abs(mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-    assert z.max() <= 3.5 and np.median(z) <= 0.05, (z.max(), np.median(z))
+    assert z.max() <= SAME_STREAM_Z and np.median(z) <= 0.05, (z.max(), np.median(z))
     res, f2 = gpu_forward(m, gg, N, seed)
     assert f2 == 0
     tal, _, _ = O.forward(og, s, a, g, w, N, seed)

@@ -14,7 +14,7 @@ import pytest
 from oracle import closed_forms as cf
 from oracle import oracle as O
 from paper_2606_27604_amd import rw, workloads
-from tests._stats import accept_histogram, histogram_z, mean_se
+from tests._stats import SAME_STREAM_Z, accept_histogram, histogram_z, mean_se
 
 pytestmark = pytest.mark.gpu
 
@@ -161,6 +161,7 @@ def test_forward_mixture_81_wavelengths_vs_oracle():
     assert np.all(np.abs(R - oR)[res_ok] <= 0.005 * oR[res_ok])
     # radial histograms, slot by slot
     gb = np64(res.tally.bins)
+    worst = worst_big = 0.0
     for u in range(wl.n_units):
         mg, sg = mean_se(gb[u, :, 0], gb[u, :, 1], N)
         mo, so = mean_se(bins[u, :, 0], bins[u, :, 1], N)
@@ -169,6 +170,16 @@ def test_forward_mixture_81_wavelengths_vs_oracle():
         zb = histogram_z(mg, sg, mo, so, mask=hits >= 30)
         ok, chi2, lim = accept_histogram(zb)
         assert ok, f"unit {u}: chi2 {chi2:.1f} > {lim:.1f} or max|z| {np.max(np.abs(zb)):.2f}"
+        # same random numbers: a slot differs only by the paths whose FP32 and
+        # FP64 replays part at a threshold, each moving it by about
+        # 1/sqrt(hits) of its SE; slots with >= 100 hits agree to a quarter of
+        # their SE, slots with 30-100 hits to half of it
+        zall = np.abs(histogram_z(mg, sg, mo, so, mask=hits >= 30))
+        zbig = np.abs(histogram_z(mg, sg, mo, so, mask=hits >= 100))
+        worst = max(worst, float(np.max(zall, initial=0.0)))
+        worst_big = max(worst_big, float(np.max(zbig, initial=0.0)))
+    assert worst_big <= 0.25, f"largest per-slot |difference| {worst_big:.3f} SE (>= 100 hits)"
+    assert worst <= 0.5, f"largest per-slot |difference| {worst:.3f} SE (>= 30 hits)"
     assert np.all(np.abs(np64(res.vertices) - vert) <= 2e-3 * vert)
 
 
@@ -231,6 +242,6 @@ def test_adjoint_vs_oracle_and_closed_forms():
     mg, sg = mean_se(np64(grad), np64(sq), Np)
     mo, so = mean_se(og_, osq, Np)
     z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2 + 1e-300)
-    assert np.all(np.abs(z) <= 3.5), np.abs(z).max()
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
     # logit gradients sum to zero (softmax), on both sides
     assert np.allclose(np64(grad)[:, 9:12].sum(1), 0.0, atol=1e-6 * np.abs(np64(grad)).max())
