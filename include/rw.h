@@ -34,7 +34,12 @@
  *
  * All entry points are asynchronous on the given HIP stream (passed as
  * void*, i.e. a hipStream_t; NULL is the null stream) and return once the
- * work is enqueued.  Host-side argument checks return RW_E_INVALID before
+ * work is enqueued; back-to-back batched calls with the same launch shape
+ * replay a ring of graph instantiations and do not wait for each other.  The
+ * exceptions: rw_check synchronises by definition; the first batched call
+ * with autotune = 1 on a new shape times candidate launches; a call that
+ * needs more workspace than the context holds waits for the device before it
+ * frees the smaller buffer.  Host-side argument checks return RW_E_INVALID before
  * anything is enqueued.  Per-unit parameter checks run on the device and set
  * bits in flags[0] (RW_FLAG_*); rw_check() synchronises and reports them.
  * Device pointers are caller-owned; the library never allocates caller-visible
@@ -134,7 +139,9 @@ typedef struct {
   int32_t* flags;     /* [1]: RW_FLAG_* bits (cleared by each call) */
 } rw_tally;
 
-/* Forward walk, plain form: one launch over a static grid of
+/* Forward walk (the mixture walk of Sec. 4.1: medium chosen once by its
+ * weight, eq. sss sampled per medium; tallies of eq. radsss), plain form:
+ * one launch over a static grid of
  * (unit, chunk of paths) work items, one item per wavefront; every unit runs
  * `paths_per_unit` paths (0..2^31).  Sums are exact (per path, 32-bit fixed
  * point; per unit, 64-bit integer sums, converted to FP64 at the end), so
@@ -164,7 +171,9 @@ rw_status rw_forward(rw_context* ctx, const rw_media* media, const rw_geometry* 
 rw_status rw_forward_noalloc(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                              int64_t paths_per_unit, uint64_t seed, rw_tally* out, void* stream);
 
-/* Batched persistent form of the forward walk: a persistent grid pulls
+/* Batched persistent form of the forward walk (not in the paper, which
+ * batches wavelengths in its simulator, Sec. 3; here a launch form for many
+ * parameter sets x wavelengths with uneven work): a persistent grid pulls
  * (unit, chunk) work items from a device queue, units with the longest
  * estimated paths first, and wavefronts move on to further items without
  * waiting for an item's slowest path.  `paths_per_unit` is a DEVICE int32

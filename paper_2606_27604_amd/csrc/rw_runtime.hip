@@ -32,13 +32,24 @@ struct TuneCfg {
   int wgs_per_cu = 0;      // persistent grid: workgroups per CU (0: occupancy limit)
 };
 
-struct GraphEntry {
-  hipGraph_t graph = nullptr;
+// One instantiation of a captured launch sequence and the event recorded after
+// its last replay.
+struct GraphExec {
   hipGraphExec_t exec = nullptr;
-  std::vector<hipGraphNode_t> nodes;
-  std::vector<const void*> funcs;
   hipEvent_t done = nullptr;
   bool launched = false;
+};
+
+// A launch sequence as a graph, with a small ring of instantiations: a call
+// updates the kernel arguments of one whose last replay has finished, so
+// back-to-back calls queue without the host waiting for the GPU.
+constexpr size_t kMaxGraphExecs = 4;
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  std::vector<hipGraphNode_t> nodes;
+  std::vector<const void*> funcs;
+  std::vector<GraphExec> execs;
+  size_t oldest = 0;  // the instantiation replayed longest ago
 };
 
 }  // namespace
@@ -627,6 +638,17 @@ std::vector<char> arg_bytes(const T& v) {
   return b;
 }
 
+hipKernelNodeParams node_params(const NodeSpec& spec, std::vector<void*>& ptrs) {
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(spec.func);
+  kp.gridDim = spec.grid;
+  kp.blockDim = spec.block;
+  kp.sharedMemBytes = spec.lds;
+  kp.kernelParams = ptrs.data();
+  kp.extra = nullptr;
+  return kp;
+}
+
 rw_status graph_launch(rw_context* ctx, const std::string& key, std::vector<NodeSpec>& specs,
                        hipStream_t s) {
   auto it = ctx->graphs.find(key);
@@ -638,41 +660,50 @@ rw_status graph_launch(rw_context* ctx, const std::string& key, std::vector<Node
     RW_HIP(ctx, hipGraphCreate(&ge.graph, 0));
     hipGraphNode_t prev = nullptr;
     for (size_t i = 0; i < specs.size(); ++i) {
-      hipKernelNodeParams kp{};
-      kp.func = const_cast<void*>(specs[i].func);
-      kp.gridDim = specs[i].grid;
-      kp.blockDim = specs[i].block;
-      kp.sharedMemBytes = specs[i].lds;
-      kp.kernelParams = ptrs[i].data();
-      kp.extra = nullptr;
+      const hipKernelNodeParams kp = node_params(specs[i], ptrs[i]);
       hipGraphNode_t node;
       RW_HIP(ctx, hipGraphAddKernelNode(&node, ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
       ge.nodes.push_back(node);
       ge.funcs.push_back(specs[i].func);
       prev = node;
     }
-    RW_HIP(ctx, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
-    RW_HIP(ctx, hipEventCreateWithFlags(&ge.done, hipEventDisableTiming));
     it = ctx->graphs.emplace(key, ge).first;
-  } else {
-    GraphEntry& ge = it->second;
-    // arguments of an instantiated graph may still be read by a queued launch
-    if (ge.launched) RW_HIP(ctx, hipEventSynchronize(ge.done));
-    for (size_t i = 0; i < specs.size(); ++i) {
-      hipKernelNodeParams kp{};
-      kp.func = const_cast<void*>(specs[i].func);
-      kp.gridDim = specs[i].grid;
-      kp.blockDim = specs[i].block;
-      kp.sharedMemBytes = specs[i].lds;
-      kp.kernelParams = ptrs[i].data();
-      kp.extra = nullptr;
-      RW_HIP(ctx, hipGraphExecKernelNodeSetParams(ge.exec, ge.nodes[i], &kp));
-    }
   }
   GraphEntry& ge = it->second;
-  RW_HIP(ctx, hipGraphLaunch(ge.exec, s));
-  RW_HIP(ctx, hipEventRecord(ge.done, s));
-  ge.launched = true;
+  // an instantiation whose last replay has finished (its arguments are no
+  // longer read), else a new one while the ring has room, else the oldest,
+  // after its replay
+  size_t pick = ge.execs.size();
+  for (size_t j = 0; j < ge.execs.size(); ++j) {
+    const size_t c = (ge.oldest + j) % ge.execs.size();
+    if (!ge.execs[c].launched) { pick = c; break; }
+    const hipError_t q = hipEventQuery(ge.execs[c].done);
+    if (q == hipSuccess) { pick = c; break; }
+    if (q != hipErrorNotReady) return fail(ctx, RW_E_HIP, "hipEventQuery failed: %s",
+                                           hipGetErrorString(q));
+  }
+  if (pick == ge.execs.size()) {
+    if (ge.execs.size() < kMaxGraphExecs) {
+      GraphExec gx;
+      RW_HIP(ctx, hipGraphInstantiate(&gx.exec, ge.graph, nullptr, nullptr, 0));
+      RW_HIP(ctx, hipEventCreateWithFlags(&gx.done, hipEventDisableTiming));
+      ge.execs.push_back(gx);
+    } else {
+      pick = ge.oldest;
+      RW_HIP(ctx, hipEventSynchronize(ge.execs[pick].done));
+    }
+  }
+  GraphExec& gx = ge.execs[pick];
+  // this call's arguments (an instantiation holds those of its last replay,
+  // or of the call that built the graph)
+  for (size_t i = 0; i < specs.size(); ++i) {
+    const hipKernelNodeParams kp = node_params(specs[i], ptrs[i]);
+    RW_HIP(ctx, hipGraphExecKernelNodeSetParams(gx.exec, ge.nodes[i], &kp));
+  }
+  RW_HIP(ctx, hipGraphLaunch(gx.exec, s));
+  RW_HIP(ctx, hipEventRecord(gx.done, s));
+  gx.launched = true;
+  ge.oldest = (pick + 1) % ge.execs.size();
   return RW_OK;
 }
 
@@ -955,9 +986,11 @@ rw_status rw_destroy(rw_context* ctx) {
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     for (auto& kv : ctx->graphs) {
-      if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+      for (GraphExec& gx : kv.second.execs) {
+        if (gx.exec) hipGraphExecDestroy(gx.exec);
+        if (gx.done) hipEventDestroy(gx.done);
+      }
       if (kv.second.graph) hipGraphDestroy(kv.second.graph);
-      if (kv.second.done) hipEventDestroy(kv.second.done);
     }
     if (ctx->workspace) hipFree(ctx->workspace);
     if (ctx->sched) hipFree(ctx->sched);

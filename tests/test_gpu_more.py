@@ -50,6 +50,27 @@ def test_graph_replays_match_eager():
         assert _same_tally(ref, got), f"graph replay with seed {seed} differs"
 
 
+def test_back_to_back_graph_replays_do_not_wait():
+    """Three batched calls of one launch shape (one graph key) with different
+    seeds, enqueued with no synchronisation in between: the host returns from
+    the last while the GPU is still busy with them (no wait between replays),
+    and each tally equals the eager launch of its seed."""
+    wl = workloads.config2()
+    m = media(wl.sigma_t, wl.albedo, wl.g, wl.weight)
+    g, _ = geoms(3, wl.n_rel)
+    P = wl.paths_per_unit
+    _run(m, g, P, 1)  # builds the graph
+    outs = [rw.Tally(m.n_units, g.n_bins) for _ in range(3)]
+    torch.cuda.synchronize()
+    for seed, t in zip((2, 3, 4), outs):
+        rw.rw_batch_forward(ctx(), m, g, None, P, seed, t)
+    pending = not torch.cuda.current_stream().query()
+    torch.cuda.synchronize()
+    assert pending, "the third call returned only after the GPU had finished"
+    for seed, t in zip((2, 3, 4), outs):
+        assert _same_tally(t, _run(m, g, P, seed, use_graph=False)), seed
+
+
 def test_uneven_path_counts_and_zero_units():
     """Per-unit path counts (zero included) give, unit by unit, the tallies of a
     uniform call with that unit's count."""
