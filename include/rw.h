@@ -186,6 +186,16 @@ typedef struct {
   int32_t autotune;             /* time candidate launch shapes on first use, cache them */
   int64_t unit_begin, unit_end; /* resume window [begin, end) of units; end <= 0: all.
                                    Units outside the window are left untouched. */
+  uint32_t* path_mask;          /* DEVICE [n_units][ceil(paths_uniform / 32)] words, or NULL.
+                                   A forward call clears the window's words and sets bit
+                                   (p mod 32) of word [u][p / 32] for every path p of unit u
+                                   that leaves the top surface (the only paths a gradient
+                                   sum can see: a path ended by roulette, the vertex cap or
+                                   a slab bottom adds nothing).  An adjoint call given the
+                                   mask of the forward with the same seed, path counts and
+                                   units replays only those paths, and its vertex counts are
+                                   the vertices it replayed.  A mask of another forward gives
+                                   a wrong gradient; the library cannot tell. */
 } rw_batch_opts;
 
 rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,

@@ -52,28 +52,33 @@ def finalize(ctx: Context, geom: Geometry, tally: Tally, n_units: int, paths_uni
 
 def forward(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, batched: bool = True,
             paths_per_unit=None, use_graph: bool = True, autotune: bool = False,
-            stream=None) -> ForwardResult:
-    """Forward walk + finalize.  batched=False uses the plain static launch."""
+            stream=None, path_mask=None) -> ForwardResult:
+    """Forward walk + finalize.  batched=False uses the plain static launch.
+    path_mask (batched only, rw.new_path_mask) receives the live-path mask
+    that lets the adjoint of the same seed skip paths that add nothing."""
     tally = Tally(media.n_units, geom.n_bins, device=media.sigma_t.device)
     if batched:
         rw.rw_batch_forward(ctx, media, geom, paths_per_unit, paths, seed, tally,
-                            use_graph=use_graph, autotune=autotune, stream=stream)
+                            use_graph=use_graph, autotune=autotune, stream=stream,
+                            path_mask=path_mask)
     else:
         rw.rw_forward(ctx, media, geom, paths, seed, tally, stream=stream)
     return finalize(ctx, geom, tally, media.n_units, paths, paths_per_unit, stream=stream)
 
 
 def layered_forward(ctx: Context, layers, geom: Geometry, paths: int, seed: int,
-                    paths_per_unit=None, use_graph: bool = True, stream=None) -> ForwardResult:
+                    paths_per_unit=None, use_graph: bool = True, stream=None,
+                    path_mask=None) -> ForwardResult:
     """Two-layer forward walk (rw_layered_forward) + finalize."""
     tally = Tally(layers.n_units, geom.n_bins, device=layers.sigma_t.device)
     rw.rw_layered_forward(ctx, layers, geom, paths_per_unit, paths, seed, tally,
-                          use_graph=use_graph, stream=stream)
+                          use_graph=use_graph, stream=stream, path_mask=path_mask)
     return finalize(ctx, geom, tally, layers.n_units, paths, paths_per_unit, stream=stream)
 
 
 def layered_adjoint(ctx: Context, layers, geom: Geometry, paths: int, seed: int, cot_R=None,
-                    cot_bins=None, paths_per_unit=None, use_graph: bool = True, stream=None):
+                    cot_bins=None, paths_per_unit=None, use_graph: bool = True, stream=None,
+                    path_mask=None):
     """Gradient sums of the two-layer walk (raw, see rw_layered_adjoint): columns
     (sigma_t top, bottom, albedo top, bottom, g top, bottom, 0, 0).  Returns
     (grad, grad_sumsq, vertices, flags)."""
@@ -84,14 +89,17 @@ def layered_adjoint(ctx: Context, layers, geom: Geometry, paths: int, seed: int,
     vert = torch.empty(n, dtype=torch.int64, device=dev)
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     rw.rw_layered_adjoint(ctx, layers, geom, paths_per_unit, paths, seed, cot_R, cot_bins, grad,
-                          sumsq, vert, flags, use_graph=use_graph, stream=stream)
+                          sumsq, vert, flags, use_graph=use_graph, stream=stream,
+                          path_mask=path_mask)
     return grad, sumsq, vert, flags
 
 
 def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, cot_R=None,
             cot_bins=None, batched: bool = True, paths_per_unit=None, use_graph: bool = True,
-            stream=None):
-    """Gradient sums (raw, see rw_adjoint).  Returns (grad, grad_sumsq, vertices, flags)."""
+            stream=None, path_mask=None):
+    """Gradient sums (raw, see rw_adjoint).  Returns (grad, grad_sumsq, vertices, flags).
+    path_mask (batched only): the live-path mask of the forward with the same
+    seed; the replay then skips the paths that add nothing."""
     dev = media.sigma_t.device
     n, P = media.n_units, 4 * geom.n_media
     grad = torch.empty((n, P), dtype=torch.float64, device=dev)
@@ -100,7 +108,8 @@ def adjoint(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int, c
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     if batched:
         rw.rw_batch_adjoint(ctx, media, geom, paths_per_unit, paths, seed, cot_R, cot_bins, grad,
-                            sumsq, vert, flags, use_graph=use_graph, stream=stream)
+                            sumsq, vert, flags, use_graph=use_graph, stream=stream,
+                            path_mask=path_mask)
     else:
         rw.rw_adjoint(ctx, media, geom, paths, seed, cot_R, cot_bins, grad, sumsq, vert, flags,
                       stream=stream)
@@ -112,16 +121,21 @@ def jacobian(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int,
     """Per-slot Jacobian of the forward sums: J[u][s][j] = d(sum of x over the
     paths of unit u that exit in slot s)/d theta_j (raw sums, layout of
     rw_adjoint's gradient), one path replay per slot with a one-hot bin
-    cotangent.  The total-R row is J.sum(1)."""
+    cotangent (batched: only the paths that leave the top, from one forward's
+    live-path mask).  The total-R row is J.sum(1)."""
     n, nb2, P = media.n_units, geom.n_bins + 2, 4 * geom.n_media
     dev = media.sigma_t.device
     J = torch.empty((n, nb2, P), dtype=torch.float64, device=dev)
     cot = torch.zeros((n, nb2), dtype=torch.float32, device=dev)
+    mask = None
+    if batched:
+        mask = rw.new_path_mask(n, paths, dev)
+        forward(ctx, media, geom, paths, seed, stream=stream, path_mask=mask)
     for s in range(nb2):
         cot.zero_()
         cot[:, s] = 1.0
         grad, _, _, flags = adjoint(ctx, media, geom, paths, seed, cot_bins=cot, batched=batched,
-                                    stream=stream)
+                                    stream=stream, path_mask=mask)
         J[:, s, :] = grad
     return J
 
@@ -133,7 +147,9 @@ class RWReflectance(torch.autograd.Function):
     (R [n_units], bins [n_units, n_bins + 2]) as per-path means (bins not per
     area).  backward replays the same random numbers (same seed) in the
     adjoint kernel and returns d/d(sigma_t, albedo, g, logits); the weights are
-    w = softmax(logits) over the K media.
+    w = softmax(logits) over the K media.  The forward keeps its live-path
+    mask, so the replay walks only the paths that left the top surface (the
+    others add nothing to any gradient).
     """
 
     @staticmethod
@@ -141,9 +157,11 @@ class RWReflectance(torch.autograd.Function):
         media = Media(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
                       logits.contiguous(), n_sets, n_wl, weights_are_logits=True)
         tally = Tally(media.n_units, geom.n_bins, device=sigma_t.device)
-        rw.rw_batch_forward(ctx, media, geom, None, paths, seed, tally)
+        mask = rw.new_path_mask(media.n_units, paths, sigma_t.device)
+        rw.rw_batch_forward(ctx, media, geom, None, paths, seed, tally, path_mask=mask)
         fctx.save_for_backward(sigma_t, albedo, g, logits)
         fctx.meta = (ctx, geom, paths, seed, n_sets, n_wl)
+        fctx.mask = mask
         return tally.R[:, 0] / paths, tally.bins[:, :, 0] / paths
 
     @staticmethod
@@ -154,7 +172,7 @@ class RWReflectance(torch.autograd.Function):
                       logits.contiguous(), n_sets, n_wl, weights_are_logits=True)
         cot_R = None if gR is None else (gR / paths).float().contiguous()
         cot_B = None if gB is None else (gB / paths).float().contiguous()
-        grad, _, _, _ = adjoint(ctx, media, geom, paths, seed, cot_R, cot_B)
+        grad, _, _, _ = adjoint(ctx, media, geom, paths, seed, cot_R, cot_B, path_mask=fctx.mask)
         K = geom.n_media
         gr = grad.t().reshape(4, K, -1).float()
         return gr[0], gr[1], gr[2], gr[3], None, None, None, None, None, None
@@ -175,9 +193,11 @@ class RWLayeredReflectance(torch.autograd.Function):
         layers = rw.Layers(sigma_t.contiguous(), albedo.contiguous(), g.contiguous(),
                            thickness_mm.contiguous(), n_rel_bottom)
         tally = Tally(layers.n_units, geom.n_bins, device=sigma_t.device)
-        rw.rw_layered_forward(ctx, layers, geom, None, paths, seed, tally)
+        mask = rw.new_path_mask(layers.n_units, paths, sigma_t.device)
+        rw.rw_layered_forward(ctx, layers, geom, None, paths, seed, tally, path_mask=mask)
         fctx.save_for_backward(sigma_t, albedo, g, thickness_mm)
         fctx.meta = (ctx, geom, paths, seed, n_rel_bottom)
+        fctx.mask = mask
         return tally.R[:, 0] / paths, tally.bins[:, :, 0] / paths
 
     @staticmethod
@@ -188,6 +208,7 @@ class RWLayeredReflectance(torch.autograd.Function):
                            thickness_mm.contiguous(), n_rel_bottom)
         cot_R = None if gR is None else (gR / paths).float().contiguous()
         cot_B = None if gB is None else (gB / paths).float().contiguous()
-        grad, _, _, _ = layered_adjoint(ctx, layers, geom, paths, seed, cot_R, cot_B)
+        grad, _, _, _ = layered_adjoint(ctx, layers, geom, paths, seed, cot_R, cot_B,
+                                        path_mask=fctx.mask)
         gr = grad[:, :6].t().reshape(3, 2, -1).float()
         return gr[0], gr[1], gr[2], None, None, None, None, None, None

@@ -92,6 +92,11 @@ struct WalkArgs {
   int64_t* adj_vertices;
   const float* cot_R;          // [n_units_total] or nullptr
   const float* cot_bins;       // [n_units_total][n_bins+2] or nullptr
+  // live-path mask [n_units_total][mask_words], bit p of unit u = path p left
+  // the top surface: the forward sets it, the adjoint replays only those
+  // paths (the others add nothing to any gradient sum); nullptr: not used
+  uint32_t* live_mask;
+  int64_t mask_words;          // words per unit: ceil(paths_uniform / 32)
   // per-wave LDS accumulators (8-byte words)
   int32_t acc_words;
   int32_t lds_words_per_wave;

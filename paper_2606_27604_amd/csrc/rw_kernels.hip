@@ -48,6 +48,29 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
 }
 
+// Position of the r-th set bit (r counted from 0) of b, for r < popcount(b):
+// the largest p with popcount(b & (2^p - 1)) <= r, by binary search.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
+  uint32_t p = 0;
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+    const uint64_t below = b & ((uint64_t(1) << (p + step)) - 1);
+    if (uint32_t(__popcll(below)) <= r) p += step;
+  }
+  return p;
+}
+
+// Forward: a path of unit u that left the top surface sets its bit of the
+// live mask.  The words of a work item belong to that item alone (items span
+// whole words: their first path is a multiple of the chunk, itself a
+// multiple of 64, and every unit starts on a word), and one wave runs all of
+// an item's paths, so the OR needs no ordering beyond the workgroup; it
+// stays in the L2 of the wave's XCD and is visible to later launches.
+__device__ __forceinline__ void mark_live(const WalkArgs& a, uint32_t u, uint32_t path) {
+  __hip_atomic_fetch_or(a.live_mask + int64_t(u) * a.mask_words + (path >> 5), 1u << (path & 31u),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // item -> (local unit, first path, end path); pb >= pe for an empty item
 __device__ __forceinline__ void map_item(const WorkMap& m, int64_t item, int64_t& u, int64_t& pb,
                                          int64_t& pe) {
@@ -537,6 +560,7 @@ walk_kernel(const WalkArgs a) {
         if (ev >= EV_EXIT_TOP) {
           sel = false;
           alive = false;
+          if (!ADJ && ev == EV_EXIT_TOP && a.live_mask) mark_live(a, lunit, path);
           if constexpr (ADJ && LAYERED) {
             exit_adjoint_layered(a, L, lslot == uint32_t(cur_slot), lslot, lunit, ev, p, v);
           } else if (lslot == uint32_t(cur_slot)) {
@@ -591,19 +615,45 @@ walk_kernel(const WalkArgs a) {
         cursor = __builtin_amdgcn_readfirstlane(cursor);
         pend = __builtin_amdgcn_readfirstlane(pend);
       }
-      if (!alive) {
-        const uint32_t cand = cursor + lane_rank(idle);
-        if (cand < pend) {
-          path = cand;
-          v = 0;
-          alive = true;
-          lunit = uint32_t(u_cur);
-          lslot = uint32_t(cur_slot);
-          lctr = a.unit_base + lunit;
+      if (ADJ && a.live_mask) {
+        // replay only the paths the forward saw leave the top: of the next 64
+        // path indices, the r-th idle lane takes the r-th live one, and the
+        // cursor moves past the last one taken (or past all 64)
+        const uint32_t c = cursor + uint32_t(lane);
+        bool live = false;
+        if (c < pend)
+          live = (a.live_mask[u_cur * a.mask_words + (c >> 5)] >> (c & 31u)) & 1u;
+        const uint64_t lb = __ballot(live);
+        const uint32_t n_live = uint32_t(__popcll(lb));
+        const uint32_t n_idle = uint32_t(__popcll(idle));
+        if (!alive) {
+          const uint32_t r = lane_rank(idle);
+          if (r < n_live) {
+            path = cursor + nth_set_bit(lb, r);
+            v = 0;
+            alive = true;
+            lunit = uint32_t(u_cur);
+            lslot = uint32_t(cur_slot);
+            lctr = a.unit_base + lunit;
+          }
         }
+        const uint32_t next = n_live > n_idle ? cursor + nth_set_bit(lb, n_idle) : cursor + 64u;
+        cursor = next < pend ? next : pend;
+      } else {
+        if (!alive) {
+          const uint32_t cand = cursor + lane_rank(idle);
+          if (cand < pend) {
+            path = cand;
+            v = 0;
+            alive = true;
+            lunit = uint32_t(u_cur);
+            lslot = uint32_t(cur_slot);
+            lctr = a.unit_base + lunit;
+          }
+        }
+        const uint32_t next = cursor + uint32_t(__popcll(idle));
+        cursor = next < pend ? next : pend;
       }
-      const uint32_t next = cursor + uint32_t(__popcll(idle));
-      cursor = next < pend ? next : pend;
     }
     // no lane alive: the last item has been handed out and every path ended
     const uint64_t busy = __ballot(alive);
@@ -659,6 +709,7 @@ walk_kernel(const WalkArgs a) {
         head += n;
       }
       if (ending) {
+        if (!ADJ && ev == EV_EXIT_TOP && a.live_mask) mark_live(a, lunit, path);
         if (local) {
           const uint32_t i = (tail + lane_rank(lm)) & (kExitRing - 1);
           if (!ADJ) {

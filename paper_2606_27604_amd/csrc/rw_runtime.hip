@@ -490,6 +490,9 @@ rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, doub
   rw_status st0 = setup_tallies(ctx, P, out, clear, fixed_ws);
   if (st0 != RW_OK) return st0;
   for (int i = 0; i < clear.n; ++i) RW_HIP(ctx, launch_fill_u64(clear.r[i].p, clear.r[i].n, s));
+  if (!P.adjoint && a.live_mask)
+    RW_HIP(ctx, launch_fill_u32(a.live_mask + a.map.unit_begin * a.mask_words,
+                                P.n_window * a.mask_words, 0u, s));
   if (a.map.n_items > 0) {
     const int wpw = P.cfg.waves_per_wg;
     int64_t grid;
@@ -739,6 +742,13 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(flags_u), arg_bytes(one), arg_bytes(zero)}});
   for (int i = 0; i < clear.n; ++i) fill64(clear.r[i].p, clear.r[i].n);
+  if (!P.adjoint && a.live_mask) {
+    uint32_t* m0 = a.live_mask + a.map.unit_begin * a.mask_words;
+    const int64_t nw = P.n_window * a.mask_words;
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((nw + 255) / 256, 65536));
+    specs.push_back({fill_u32_kernel_ptr(), dim3(unsigned(g)), dim3(256), 0,
+                     {arg_bytes(m0), arg_bytes(nw), arg_bytes(zero)}});
+  }
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
                    {arg_bytes(ctx->queue), arg_bytes(one), arg_bytes(zero)}});
   specs.push_back({fill_u32_kernel_ptr(), dim3(1), dim3(256), 0,
@@ -790,9 +800,11 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
   }
   int64_t ub = 0, ue = n_units;
   bool use_graph = false, tune = false;
+  uint32_t* mask = nullptr;
   if (opts) {
     use_graph = opts->use_graph != 0;
     tune = opts->autotune != 0;
+    mask = opts->path_mask;
     if (opts->unit_end > 0 || opts->unit_begin != 0) {
       ub = opts->unit_begin;
       ue = opts->unit_end > 0 ? opts->unit_end : n_units;
@@ -823,6 +835,8 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
     P.a.cot_R = cot_R;
     P.a.cot_bins = cot_bins;
   }
+  P.a.live_mask = mask;
+  P.a.mask_words = (paths_uniform + 31) / 32;
   if (batched && tune && ctx->tune.find(key) == ctx->tune.end() && P.a.map.n_items > 0 &&
       P.n_window > 0) {
     TuneCfg best;
@@ -836,6 +850,8 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
       P.a.cot_R = cot_R;
       P.a.cot_bins = cot_bins;
     }
+    P.a.live_mask = mask;
+    P.a.mask_words = (paths_uniform + 31) / 32;
   }
   if (batched && use_graph)
     return enqueue_graph(ctx, P, out, grad, grad_sumsq, adj_vertices, flags, s);
@@ -1046,7 +1062,7 @@ rw_status rw_forward_noalloc(rw_context* ctx, const rw_media* media, const rw_ge
 rw_status rw_batch_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                            const int32_t* paths_per_unit, int64_t paths_uniform, uint64_t seed,
                            rw_tally* out, const rw_batch_opts* opts, void* stream) {
-  rw_batch_opts def{1, 0, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0, nullptr};
   return run_media(ctx, media, geom, paths_per_unit, paths_uniform, seed, out, nullptr, nullptr,
                   nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false, stream);
 }
@@ -1064,7 +1080,7 @@ rw_status rw_batch_adjoint(rw_context* ctx, const rw_media* media, const rw_geom
                            const float* cot_R, const float* cot_bins, double* grad,
                            double* grad_sumsq, int64_t* vertices, int32_t* flags,
                            const rw_batch_opts* opts, void* stream) {
-  rw_batch_opts def{1, 0, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0, nullptr};
   return run_media(ctx, media, geom, paths_per_unit, paths_uniform, seed, nullptr, cot_R, cot_bins,
                   grad, grad_sumsq, vertices, flags, opts ? opts : &def, true, true, stream);
 }
@@ -1079,7 +1095,7 @@ rw_status rw_layered_forward(rw_context* ctx, const rw_layers* layers, const rw_
   MediaView v;
   st = check_layers(ctx, layers, geom, &v);
   if (st != RW_OK) return st;
-  rw_batch_opts def{1, 0, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0, nullptr};
   return run_walk(ctx, v, layers->n_units, geom, paths_per_unit, paths_uniform, seed, out, nullptr,
                   nullptr, nullptr, nullptr, nullptr, nullptr, opts ? opts : &def, true, false,
                   stream);
@@ -1097,7 +1113,7 @@ rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_
   MediaView v;
   st = check_layers(ctx, layers, geom, &v);
   if (st != RW_OK) return st;
-  rw_batch_opts def{1, 0, 0, 0};
+  rw_batch_opts def{1, 0, 0, 0, nullptr};
   return run_walk(ctx, v, layers->n_units, geom, paths_per_unit, paths_uniform, seed, nullptr,
                   cot_R, cot_bins, grad, grad_sumsq, vertices, flags, opts ? opts : &def, true,
                   true, stream);

@@ -118,6 +118,7 @@ class RwBatchOptsC(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("unit_begin", ctypes.c_int64),
         ("unit_end", ctypes.c_int64),
+        ("path_mask", ctypes.c_void_p),
     ]
 
 
@@ -375,8 +376,23 @@ class Context:
             raise RwError(st, self.last_error())
 
 
-def _opts(use_graph=True, autotune=False, unit_begin=0, unit_end=0):
-    return RwBatchOptsC(int(use_graph), int(autotune), unit_begin, unit_end)
+def _opts(use_graph=True, autotune=False, unit_begin=0, unit_end=0, path_mask=None):
+    return RwBatchOptsC(int(use_graph), int(autotune), unit_begin, unit_end, _ptr(path_mask))
+
+
+def mask_words(paths_uniform: int) -> int:
+    """Words per unit of a live-path mask (rw_batch_opts.path_mask)."""
+    return (int(paths_uniform) + 31) // 32
+
+
+def new_path_mask(n_units: int, paths_uniform: int, device="cuda") -> torch.Tensor:
+    """An int32 tensor [n_units, ceil(paths / 32)] to hold a live-path mask."""
+    return torch.empty((n_units, mask_words(paths_uniform)), dtype=torch.int32, device=device)
+
+
+def _check_mask(mask, n_units, paths_uniform):
+    if mask is not None:
+        _need(mask, torch.int32, (n_units, mask_words(paths_uniform)), "path_mask")
 
 
 # ---------------------------------------------------------------------------
@@ -400,11 +416,12 @@ def rw_forward_noalloc(ctx: Context, media: Media, geom: Geometry, paths_per_uni
 
 def rw_batch_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit, paths_uniform: int,
                      seed: int, out: Tally, use_graph=True, autotune=False, unit_begin=0,
-                     unit_end=0, stream=None):
+                     unit_end=0, stream=None, path_mask=None):
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (media.n_units,), "paths_per_unit")
+    _check_mask(path_mask, media.n_units, paths_uniform)
     g = geom.c()
-    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end, path_mask)
     ctx._check(load_library().rw_batch_forward(ctx.h, ctypes.byref(media._c), ctypes.byref(g),
                                                _ptr(paths_per_unit), int(paths_uniform), int(seed),
                                                ctypes.byref(out._c), ctypes.byref(o),
@@ -437,12 +454,13 @@ def rw_adjoint(ctx: Context, media: Media, geom: Geometry, paths_per_unit: int, 
 
 def rw_batch_adjoint(ctx: Context, media: Media, geom: Geometry, paths_per_unit, paths_uniform: int,
                      seed: int, cot_R, cot_bins, grad, grad_sumsq, vertices, flags, use_graph=True,
-                     autotune=False, unit_begin=0, unit_end=0, stream=None):
+                     autotune=False, unit_begin=0, unit_end=0, stream=None, path_mask=None):
     _adj_args(media, geom, cot_R, cot_bins, grad, grad_sumsq, vertices, flags)
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (media.n_units,), "paths_per_unit")
+    _check_mask(path_mask, media.n_units, paths_uniform)
     g = geom.c()
-    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end, path_mask)
     ctx._check(load_library().rw_batch_adjoint(
         ctx.h, ctypes.byref(media._c), ctypes.byref(g), _ptr(paths_per_unit), int(paths_uniform),
         int(seed), _ptr(cot_R), _ptr(cot_bins), _ptr(grad), _ptr(grad_sumsq), _ptr(vertices),
@@ -477,11 +495,12 @@ def rw_debug_trace(ctx: Context, media: Media, geom: Geometry, words, n_paths: i
 
 def rw_layered_forward(ctx: Context, layers: Layers, geom: Geometry, paths_per_unit,
                        paths_uniform: int, seed: int, out: Tally, use_graph=True, autotune=False,
-                       unit_begin=0, unit_end=0, stream=None):
+                       unit_begin=0, unit_end=0, stream=None, path_mask=None):
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (layers.n_units,), "paths_per_unit")
+    _check_mask(path_mask, layers.n_units, paths_uniform)
     g = geom.c()
-    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end, path_mask)
     ctx._check(load_library().rw_layered_forward(ctx.h, ctypes.byref(layers._c), ctypes.byref(g),
                                                  _ptr(paths_per_unit), int(paths_uniform),
                                                  int(seed), ctypes.byref(out._c),
@@ -491,12 +510,13 @@ def rw_layered_forward(ctx: Context, layers: Layers, geom: Geometry, paths_per_u
 def rw_layered_adjoint(ctx: Context, layers: Layers, geom: Geometry, paths_per_unit,
                        paths_uniform: int, seed: int, cot_R, cot_bins, grad, grad_sumsq, vertices,
                        flags, use_graph=True, autotune=False, unit_begin=0, unit_end=0,
-                       stream=None):
+                       stream=None, path_mask=None):
     _adj_args(layers, geom, cot_R, cot_bins, grad, grad_sumsq, vertices, flags)
     if paths_per_unit is not None:
         _need(paths_per_unit, torch.int32, (layers.n_units,), "paths_per_unit")
+    _check_mask(path_mask, layers.n_units, paths_uniform)
     g = geom.c()
-    o = _opts(use_graph, autotune, unit_begin, unit_end)
+    o = _opts(use_graph, autotune, unit_begin, unit_end, path_mask)
     ctx._check(load_library().rw_layered_adjoint(
         ctx.h, ctypes.byref(layers._c), ctypes.byref(g), _ptr(paths_per_unit), int(paths_uniform),
         int(seed), _ptr(cot_R), _ptr(cot_bins), _ptr(grad), _ptr(grad_sumsq), _ptr(vertices),
