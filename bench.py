@@ -23,9 +23,11 @@ gradients equal to FP64 rounding) for the batched/plain ratio at matched
 statistical error.
 
 Extra fields: the batched sweep of 65,536 three-medium sets x 16 wavelengths
-at 4,096 paths (one persistent launch) and its per-set plain launches timed on
-a subset of sets; the adjoint sweep (1,024 sets x 81 wavelengths x 2^14
-paths, random bin cotangents); the roofline of the dominant kernel (ALU-bound: VALU issue
+at 4,096 paths (one persistent launch) against one plain static launch over
+the same units, and its per-set plain launches timed on a subset of sets; the
+adjoint sweep (1,024 sets x 81 wavelengths x 2^14 paths, random bin
+cotangents); the inverse fit (4,096 targets x 81 wavelengths, 200 Adam steps
+at 2^12 paths, by the adjoint and by the LUT route); the autotuned step; the roofline of the dominant kernel (ALU-bound: VALU issue
 slots per vertex x vertices / measured kernel time, against the issue peak of
 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
@@ -223,12 +225,20 @@ def main():
     ap.add_argument("--c3-sets", type=int, default=65536)
     ap.add_argument("--c3-plain-sets", type=int, default=512)
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--c5-targets", type=int, default=4096)
+    ap.add_argument("--c5-iters", type=int, default=200)
+    ap.add_argument("--c5-lut", type=int, default=800)
+    ap.add_argument("--c5-lut-photons", type=int, default=1 << 16)
     ap.add_argument("--c4-sets", type=int, default=1024)
     ap.add_argument("--micro", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run an elementwise copy of 256 MiB in / 256 MiB out (reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the headline legs themselves (the default run adds a separate "
+                         "autotuned leg)")
+    ap.add_argument("--no-autotune-leg", action="store_true")
     ap.add_argument("--lut", type=int, default=0,
                     help="instead of the step benchmark, time the generation of an N x N "
                          "(alpha, g) lookup table (Sec. 4.2) and print its own JSON line")
@@ -287,25 +297,28 @@ def main():
     aflags = torch.zeros(1, dtype=torch.int32, device="cuda")
     mask = rw.new_path_mask(n, P)
 
+    cur = {"ctx": ctx, "tune": args.autotune}
+
     def step(seed, batched, ev=None, skip=True):
         pm = mask if (batched and skip) else None
+        c = cur["ctx"]
         if ev:
             ev[0].record(stream)
         if batched:
-            rw.rw_batch_forward(ctx, media, geom, None, P, seed, tally, autotune=args.autotune,
+            rw.rw_batch_forward(c, media, geom, None, P, seed, tally, autotune=cur["tune"],
                                 stream=stream, path_mask=pm)
         else:
-            rw.rw_forward(ctx, media, geom, P, seed, tally, stream=stream)
+            rw.rw_forward(c, media, geom, P, seed, tally, stream=stream)
         if ev:
             ev[1].record(stream)
-        rw.rw_finalize(ctx, geom, n, None, P, tally, R_mean, R_se, Rr, Rr_se, Pd, stream=stream)
+        rw.rw_finalize(c, geom, n, None, P, tally, R_mean, R_se, Rr, Rr_se, Pd, stream=stream)
         if ev:
             ev[2].record(stream)
         if batched:
-            rw.rw_batch_adjoint(ctx, media, geom, None, P, seed, cot_R, cot_B, grad, sumsq, avert,
-                                aflags, autotune=args.autotune, stream=stream, path_mask=pm)
+            rw.rw_batch_adjoint(c, media, geom, None, P, seed, cot_R, cot_B, grad, sumsq, avert,
+                                aflags, autotune=cur["tune"], stream=stream, path_mask=pm)
         else:
-            rw.rw_adjoint(ctx, media, geom, P, seed, cot_R, cot_B, grad, sumsq, avert, aflags,
+            rw.rw_adjoint(c, media, geom, P, seed, cot_R, cot_B, grad, sumsq, avert, aflags,
                           stream=stream)
         if ev:
             ev[3].record(stream)
@@ -432,6 +445,8 @@ def main():
                                                v["gradient_max_rel_diff"] < 1e-9
                                                for v in m.values())
         out["matched_statistical_error_check"] = m
+    if not args.no_autotune_leg:
+        out["autotuned"] = autotuned_leg(rw, torch, cur, run, bat, args)
     del tally, grad, sumsq
     torch.cuda.empty_cache()
 
@@ -439,9 +454,81 @@ def main():
         out["batched_sweep"] = c3(ctx, rw, api, workloads, torch, args)
     if not args.no_c4:
         out["adjoint_sweep"] = c4(ctx, rw, workloads, torch, args)
+    if not args.no_c5:
+        out["inverse_fit"] = c5(torch, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, seed=5)
     print(json.dumps(out), flush=True)
+
+
+def autotuned_leg(rw, torch, cur, run, bat, args):
+    """The headline step with autotune = 1 on a fresh context: its first
+    forward and adjoint calls time the candidate shapes (paths per work item,
+    waves per workgroup, wave occupancy) and cache the fastest; the timed steps
+    then run with them.  Reports the shapes chosen, read back from the cache
+    file, next to the untuned step."""
+    import tempfile
+
+    path = os.path.join(tempfile.mkdtemp(prefix="rw_tune_"), "cache.txt")
+    old = os.environ.get("RW_AUTOTUNE_CACHE")
+    os.environ["RW_AUTOTUNE_CACHE"] = path
+    try:
+        saved = dict(cur)
+        cur["ctx"], cur["tune"] = rw.Context(0), True
+        t0 = time.perf_counter()
+        r = run(True, 1)  # the warm-up steps include the tuning
+        tuned_wall = time.perf_counter() - t0
+        cur.update(saved)
+    finally:
+        if old is None:
+            os.environ.pop("RW_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["RW_AUTOTUNE_CACHE"] = old
+    chosen = {}
+    with open(path) as f:
+        for line in f:
+            key, _, val = line.strip().partition("|")
+            c, w, o = (int(x) for x in val.split())
+            chosen[key] = {"chunk": c, "paths_per_lane_per_item": c // 64, "waves_per_wg": w,
+                           "wgs_per_cu": o if o > 0 else "occupancy limit"}
+    return {"ms_per_step": 1e3 * r["wall"] / args.steps,
+            "forward_ms": float(np.mean(r["fwd_ms"])), "adjoint_ms": float(np.mean(r["adj_ms"])),
+            "untuned_ms_per_step": 1e3 * bat["wall"] / args.steps,
+            "tuning_and_warmup_s": tuned_wall - r["wall"],
+            "same_vertices_as_untuned": r["vf"] == bat["vf"],
+            "chosen": chosen,
+            "default": {"chunk": 2048, "waves_per_wg": 4, "wgs_per_cu": "occupancy limit"}}
+
+
+def c5(torch, args):
+    """The inverse fit: 4,096 target spectra (81 wavelengths, the forward
+    walk's R(lambda) and R(r, lambda) at random three-medium parameters, 2^18
+    paths, 1 % noise), each refit from a random start by Adam over the 11
+    parameters per wavelength for 200 steps, through the batched forward and
+    the path-replay adjoint at 2^12 paths per evaluation; then the paper's LUT
+    route (an 800 x 800 table from the walk, the fused LUT-fit kernel) on the
+    same targets.  Both are scored by the walk at 2^18 paths: spectral RMSE
+    against the noise-free targets and parameter recovery up to component
+    permutation (median absolute errors)."""
+    from paper_2606_27604_amd import fit, lut
+
+    print(f"c5: targets for {args.c5_targets} spectra", file=sys.stderr, flush=True)
+    prob = fit.make_problem(args.c5_targets, 1 << 18)
+    print(f"c5: targets ready ({prob.target_seconds:.1f} s); mc fit", file=sys.stderr, flush=True)
+    mc = fit.run_fit(iters=args.c5_iters, paths=1 << 12, problem=prob, log_every=20, progress=True)
+    print(f"c5: mc fit {mc['fit_seconds']:.1f} s; lut table", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    table = lut.generate(prob.ctx, args.c5_lut, args.c5_lut, args.c5_lut_photons)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    print(f"c5: table {t_table:.1f} s; lut fit", file=sys.stderr, flush=True)
+    lf = fit.run_lut_fit(iters=args.c5_iters, problem=prob, table=table)
+    lf["lut_seconds"] = t_table
+    return {"workload": f"inverse fit: {args.c5_targets} targets x 81 wavelengths (K=3, n=1.4), "
+                        f"{args.c5_iters} Adam steps; targets from the walk at 2^18 paths + 1 % "
+                        f"noise; scored by the walk at 2^18 paths",
+            "mc_adjoint_route": mc, "lut_route": lf}
 
 
 def c3(ctx, rw, api, workloads, torch, args):
@@ -465,7 +552,25 @@ def c3(ctx, rw, api, workloads, torch, args):
     res = {"workload": f"batched-{wl.n_sets}x16: K=3, n=1.4, 4096 paths per unit",
            "units": n, "batched_ms": full_ms, "batched_vertices_per_s": full_v / (full_ms * 1e-3),
            "spectra_per_s": wl.n_sets / (full_ms * 1e-3)}
-    # like for like on a subset: per-set plain launches vs one batched launch
+    # matched shape: one plain static launch (rw_forward) over all the units,
+    # same seed, same estimates
+    stat = rw.Tally(n, wl.n_bins)
+    rw.rw_forward(ctx, media, geom, P, 7, stat, stream=s)
+    torch.cuda.synchronize()
+    e0.record(s)
+    rw.rw_forward(ctx, media, geom, P, 7, stat, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    st_ms = e0.elapsed_time(e1)
+    res.update({"plain_static_ms": st_ms,
+                "plain_static_vertices_per_s": full_v / (st_ms * 1e-3),
+                "plain_static_over_batched_time": st_ms / full_ms,
+                "plain_static_tallies_bit_identical": bool(
+                    torch.equal(stat.R, tally.R) and torch.equal(stat.bins, tally.bins) and
+                    torch.equal(stat.vertices, tally.vertices))})
+    del stat
+    # secondary: per-set plain launches (16 units each) vs one batched launch,
+    # on a subset of sets
     S = min(args.c3_plain_sets, wl.n_sets)
     U = S * wl.n_wl
     sub_media = media.unit_range(0, U)

@@ -26,6 +26,10 @@ using namespace rw;
 
 namespace {
 
+// Launch shape of a walk.  chunk / 64 is the number of paths each lane of a
+// wave walks from one work item (lanes regenerate: a lane takes the item's
+// next path as soon as its path ends, so the paths per thread follow from the
+// chunk); wgs_per_cu sets the wave occupancy of the persistent grid.
 struct TuneCfg {
   int chunk = 2048;        // paths per work item (multiple of 64)
   int waves_per_wg = 4;    // workgroup = waves_per_wg wavefronts
@@ -522,11 +526,11 @@ rw_status enqueue(rw_context* ctx, Plan& P, bool persistent, rw_tally* out, doub
 }
 
 // ---- autotuner ------------------------------------------------------------
-std::string tune_key(const Plan& P, bool persistent, int64_t paths_uniform) {
+std::string tune_key(const Plan& P, bool persistent, int64_t paths_uniform, bool masked) {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "gfx950 K%d %s %s nb%d p%lld", P.K, P.adjoint ? "adj" : "fwd",
-                persistent ? "persistent" : "static", P.a.geo.n_bins,
-                (long long)std::min<int64_t>(paths_uniform, 1 << 16));
+  std::snprintf(buf, sizeof(buf), "gfx950 K%d %s %s nb%d p%lld m%d", P.K,
+                P.adjoint ? "adj" : "fwd", persistent ? "persistent" : "static", P.a.geo.n_bins,
+                (long long)std::min<int64_t>(paths_uniform, 1 << 16), masked ? 1 : 0);
   return buf;
 }
 
@@ -544,8 +548,9 @@ void load_tune_cache(rw_context* ctx) {
     *bar = 0;
     TuneCfg c;
     if (std::sscanf(bar + 1, "%d %d %d", &c.chunk, &c.waves_per_wg, &c.wgs_per_cu) == 3 &&
-        c.chunk >= 64 && c.chunk % 64 == 0 && (c.waves_per_wg == 1 || c.waves_per_wg == 2 ||
-                                               c.waves_per_wg == 4))
+        c.chunk >= 64 && c.chunk % 64 == 0 && c.chunk <= (1 << 20) &&
+        (c.waves_per_wg == 1 || c.waves_per_wg == 2 || c.waves_per_wg == 4) &&
+        c.wgs_per_cu >= 0 && c.wgs_per_cu <= 64)
       ctx->tune[line] = c;
   }
   std::fclose(f);
@@ -572,8 +577,12 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
   int64_t n_sample = std::max<int64_t>(1, (int64_t(1) << 22) / std::max<int64_t>(paths, 1));
   n_sample = std::max<int64_t>(n_sample, 2 * ctx->n_cu);
   n_sample = std::min<int64_t>(n_sample, base.n_window);
+  // paths per item (each lane walks chunk / 64 of them), waves per workgroup,
+  // and the wave occupancy of the persistent grid as quarters of the kernel's
+  // occupancy limit
   const int chunks[] = {1024, 2048, 4096, 8192};
   const int wpws[] = {1, 2, 4};
+  const int occ_quarters[] = {4, 3, 2};
   hipEvent_t e0, e1;
   RW_HIP(ctx, hipEventCreate(&e0));
   RW_HIP(ctx, hipEventCreate(&e1));
@@ -581,11 +590,12 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
   *best = base.cfg;
   for (int chunk : chunks) {
     for (int wpw : wpws) {
+     for (int oq : occ_quarters) {
       Plan P = base;
       if (walk_lds_bytes(P.a, wpw) > ctx->max_lds) continue;
       P.cfg.chunk = chunk;
       P.cfg.waves_per_wg = wpw;
-      P.cfg.wgs_per_cu = 0;
+      P.cfg.wgs_per_cu = oq == 4 ? 0 : std::max(1, occupancy_wgs(P, wpw) * oq / 4);
       P.n_window = n_sample;
       WorkMap& m = P.a.map;
       m.n_units = n_sample;
@@ -614,6 +624,7 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
         best_ms = ms_sum;
         *best = P.cfg;
       }
+     }
     }
   }
   hipEventDestroy(e0);
@@ -825,7 +836,7 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
     // a tune-key probe plan (shape only)
     st = build_plan(ctx, P, media, geom, n_units, paths, paths_uniform, seed, ub, ue, adjoint, cfg);
     if (st != RW_OK) return st;
-    key = tune_key(P, true, paths_uniform);
+    key = tune_key(P, true, paths_uniform, mask != nullptr);
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) cfg = it->second;
   }
