@@ -151,6 +151,10 @@ def _bind(L):
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_int, dp, dp, i64p]
     L.orc_layered_forward.restype = ctypes.c_int
+    L.orc_layered_hero_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
+                                           ctypes.c_int, i64p, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.c_uint32, ctypes.c_int, dp, dp, i64p]
+    L.orc_layered_hero_forward.restype = ctypes.c_int
     L.orc_layered_adjoint.argtypes = [gp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64, i64p,
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_int, dp, dp, dp, dp]
@@ -312,6 +316,32 @@ def layered_forward(geo: Geometry, sigma_t, albedo, g, thickness, n_bottom: floa
                                    _i64ptr(vert))
     if rc != 0:
         raise ValueError(f"orc_layered_forward failed with code {rc}")
+    return tally, bins, vert
+
+
+def layered_hero_forward(geo: Geometry, sigma_t, albedo, g, thickness, n_bottom: float,
+                         n_hero: int, paths, seed: int, tag: int = 0,
+                         n_threads: int | None = None, unit_base: int = 0):
+    """Hero-wavelength two-layer walk (orc_layered_hero_forward): units in
+    groups of n_hero consecutive units sharing one walk, `paths` per group
+    (scalar or [n_groups], multiples of n_hero).  Returns (tally, bins,
+    vertices) per unit as layered_forward (absorbed weight 0; vertices of the
+    paths each unit was hero of)."""
+    sigma_t = np.asarray(sigma_t)
+    n_units = sigma_t.size // 2
+    s, a, gg = (_soa(v, 2, n_units) for v in (sigma_t, albedo, g))
+    d = np.ascontiguousarray(np.asarray(thickness, np.float64).reshape(n_units))
+    p = _paths(paths, n_units // n_hero)
+    tally = np.zeros((n_units, 8))
+    bins = np.zeros((n_units, geo.n_bins + 2, 2))
+    vert = np.zeros(n_units, dtype=np.int64)
+    cg = geo.c()
+    rc = lib().orc_layered_hero_forward(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(d),
+                                        float(n_bottom), n_units, int(n_hero), _i64ptr(p), seed,
+                                        tag, unit_base, n_threads or default_threads(),
+                                        _dptr(tally), _dptr(bins), _i64ptr(vert))
+    if rc != 0:
+        raise ValueError(f"orc_layered_hero_forward failed with code {rc}")
     return tally, bins, vert
 
 

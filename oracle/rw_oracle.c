@@ -446,6 +446,80 @@ typedef struct {
   double n[2];                        /* indices relative to the outside */
 } layer_params;
 
+/* ------------------------------------------------------------------------- */
+/* Hero wavelengths: one path serves a group of C wavelengths of one tissue     */
+/* ------------------------------------------------------------------------- */
+#define ORC_MAX_HERO 16
+
+/* log of the Henyey-Greenstein density of mu = cos(theta) */
+static double hg_log_pdf(double g, double mu) {
+  return log(0.5 * (1.0 - g * g)) - 1.5 * log(1.0 + g * g - 2.0 * g * mu);
+}
+
+/* Hero-wavelength spectral sampling (Wilkie et al. 2014, the "hero
+ * wavelength" tracking named in Sec. 2; Sec. 3's simulator propagates all its
+ * wavelengths together) in the two-layer walk.  Group member `hero` samples
+ * the path with its own optics: free flights from its sigma_t, scattering from
+ * its Henyey-Greenstein g (the Fresnel and interface decisions depend on the
+ * indices alone, which the group shares).  Every member i carries its own
+ * weight x_i, multiplied by its albedo at each collision; Russian roulette
+ * decides on the largest weight (a decision that does not depend on i, so it
+ * leaves every weight unbiased) and boosts all of them.  The path density
+ * under member i's optics is
+ *   p_i = prod over layers of sigma_i^n_coll exp(-sigma_i L)
+ *         x prod over scatterings of p_HG(mu; g_i)
+ * times factors shared by all members, and with the hero chosen uniformly
+ * (path index mod C) the one-sample balance-heuristic estimator of member i's
+ * tally is F_i = C x_i p_i / sum_j p_j.  walk_layers runs this when given a
+ * hero_walk; with C = 1 it is the plain walk. */
+typedef struct {
+  const layer_params* lps; /* the C members */
+  int C, hero;
+  double x[ORC_MAX_HERO];  /* weights */
+  double hg[ORC_MAX_HERO]; /* sums of ln p_HG(mu; g_i) over the scatterings */
+  double F[ORC_MAX_HERO];  /* contributions of a path that leaves (else 0) */
+} hero_walk;
+
+/* A collision in `layer` of a hero path: every member's weight times its
+ * albedo, roulette on the largest weight, the hero's Henyey-Greenstein
+ * scattering and every member's log phase density of it. */
+static int collide_hero(const orc_geometry* geo, hero_walk* hw, int layer, const double u[4],
+                        double d[3], path_result* res) {
+  res->n_coll += 1;
+  double xmax = 0.0;
+  for (int i = 0; i < hw->C; ++i) {
+    hw->x[i] *= hw->lps[i].albedo[layer];
+    if (hw->x[i] > xmax) xmax = hw->x[i];
+  }
+  if (geo->rr_weight > 0.0 && xmax < geo->rr_weight) {
+    if (u[3] < geo->rr_survive) {
+      for (int i = 0; i < hw->C; ++i) hw->x[i] /= geo->rr_survive;
+    } else {
+      return END_RR_KILLED;
+    }
+  }
+  const double mu = hg_cos(hw->lps[hw->hero].g[layer], u[1]);
+  for (int i = 0; i < hw->C; ++i) hw->hg[i] += hg_log_pdf(hw->lps[i].g[layer], mu);
+  const double phi = 2.0 * M_PI * u[2];
+  scatter_dir(d, mu, phi);
+  return END_NONE;
+}
+
+/* A hero path leaves: the balance-heuristic contributions of all members. */
+static void exit_hero(hero_walk* hw, const path_result* res) {
+  double lp[ORC_MAX_HERO], m = -INFINITY;
+  for (int i = 0; i < hw->C; ++i) {
+    lp[i] = hw->hg[i];
+    for (int l = 0; l < 2; ++l)
+      lp[i] += (double)res->n_coll_l[l] * log(hw->lps[i].sigma_t[l]) -
+               hw->lps[i].sigma_t[l] * res->L_l[l];
+    if (lp[i] > m) m = lp[i];
+  }
+  double S = 0.0;
+  for (int i = 0; i < hw->C; ++i) S += exp(lp[i] - m);
+  for (int i = 0; i < hw->C; ++i) hw->F[i] = (double)hw->C * hw->x[i] * exp(lp[i] - m) / S;
+}
+
 /* The same estimator as walk(), in layers.  Readings (identical on the GPU
  * side): the path enters the top layer through the surface of index n[0]; a
  * flight that reaches the interface z = d stops there (a vertex); the
@@ -455,10 +529,12 @@ typedef struct {
  * distribution is memoryless, so stopping at the interface does not change
  * the path density).  The bottom layer's lower face (slab tests) has index
  * n[1] over the outside.  For the adjoint the flight lengths, collisions and
- * g-score terms are also kept per layer (n_coll_l, L_l, Sg_l). */
+ * g-score terms are also kept per layer (n_coll_l, L_l, Sg_l).  Given a
+ * hero_walk (hw non-NULL), lp is its hero member and the collisions and the
+ * exit follow the hero-wavelength estimator (collide_hero, exit_hero). */
 static void walk_layers(const layer_params* lp, const orc_geometry* geo,
                         const block_source* src, path_result* res,
-                        double* events, int64_t max_events) {
+                        double* events, int64_t max_events, hero_walk* hw) {
   const int slab = geo->slab_mm > 0.0;
   double u[4];
   memset(res, 0, sizeof(*res));
@@ -473,6 +549,13 @@ static void walk_layers(const layer_params* lp, const orc_geometry* geo,
     res->end = END_SPECULAR;
     put_event(events, max_events, 0, EV_START, p, d, 0.0);
     return;
+  }
+  if (hw) {
+    for (int i = 0; i < hw->C; ++i) {
+      hw->x[i] = W;
+      hw->hg[i] = 0.0;
+      hw->F[i] = 0.0;
+    }
   }
   put_event(events, max_events, 0, EV_START, p, d, W);
 
@@ -530,6 +613,10 @@ static void walk_layers(const layer_params* lp, const orc_geometry* geo,
         put_event(events, max_events, v, EV_REFLECT, p, d, W);
         continue;
       }
+      if (hw) {
+        exit_hero(hw, res);
+        W = hw->F[hw->hero];
+      }
       res->x = W;
       if (face == 1) {
         res->end = END_EXIT_TOP;
@@ -547,7 +634,13 @@ static void walk_layers(const layer_params* lp, const orc_geometry* geo,
     res->L_l[layer] += flight;
     const int64_t nc0 = res->n_coll;
     const double sg0 = res->Sg;
-    const int end = collide(geo, lp->albedo[layer], lp->g[layer], u, d, &W, res);
+    int end;
+    if (hw) {
+      end = collide_hero(geo, hw, layer, u, d, res);
+      W = end == END_NONE ? hw->x[hw->hero] : 0.0;
+    } else {
+      end = collide(geo, lp->albedo[layer], lp->g[layer], u, d, &W, res);
+    }
     res->n_coll_l[layer] += res->n_coll - nc0;
     res->Sg_l[layer] += res->Sg - sg0;
     if (end != END_NONE) {
@@ -577,6 +670,9 @@ typedef struct {
   int layered;
   const double* thickness;
   double n_bottom;
+  /* hero-wavelength walk: groups of `hero` consecutive units (0: off); the
+   * task table then runs over groups */
+  int hero;
   /* adjoint inputs (NULL for the forward) */
   int adjoint;
   const double* cot_R;
@@ -636,7 +732,13 @@ static int load_layers(const job_t* job, int64_t u, layer_params* lp) {
 /* partial layout per task:
  *   forward: [T_NSLOTS] + bins[(nb+2)*2] + vertices(1)
  *   adjoint: grad[4K] + sumsq[4K] + (jac: jacR[4K] + jacB[(nb+2)*4K])      */
+static void run_hero_task(job_t* job, int64_t t);
+
 static void run_task(job_t* job, int64_t t) {
+  if (job->hero > 0) {
+    run_hero_task(job, t);
+    return;
+  }
   const orc_geometry* geo = job->geo;
   const int nb = geo->n_bins;
   const int K = job->K;
@@ -662,7 +764,7 @@ static void run_task(job_t* job, int64_t t) {
   for (int64_t pth = job->task_begin[t]; pth < job->task_end[t]; ++pth) {
     path_result r;
     src.path = (uint32_t)pth;
-    if (job->layered) walk_layers(&lp, geo, &src, &r, NULL, 0);
+    if (job->layered) walk_layers(&lp, geo, &src, &r, NULL, 0, NULL);
     else walk(&up, geo, &src, &r, NULL, 0);
     int tallied_top = (r.end == END_EXIT_TOP) &&
                       (geo->order_filter <= 0 || r.n_coll == geo->order_filter);
@@ -722,6 +824,62 @@ static void run_task(job_t* job, int64_t t) {
   }
 }
 
+/* partial layout of a hero task (group q): per member i,
+ *   [T_NSLOTS] + bins[(nb+2)*2] + vertices(1)
+ * with the vertices of the paths whose hero member i was */
+static void run_hero_task(job_t* job, int64_t t) {
+  const orc_geometry* geo = job->geo;
+  const int nb = geo->n_bins;
+  const int C = job->hero;
+  const int64_t q = job->task_unit[t];
+  const int64_t stride = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
+  double* part = job->part + t * job->part_len;
+  layer_params lps[ORC_MAX_HERO];
+  for (int i = 0; i < C; ++i) {
+    if (load_layers(job, q * C + i, &lps[i]) != 0 || lps[i].d != lps[0].d) {
+      pthread_mutex_lock(&job->lock);
+      job->status |= 1;
+      pthread_mutex_unlock(&job->lock);
+      return;
+    }
+  }
+  block_source src;
+  memset(&src, 0, sizeof(src));
+  src.key[0] = (uint32_t)job->seed;
+  src.key[1] = (uint32_t)(job->seed >> 32);
+  src.unit = (uint32_t)((uint64_t)job->unit_base + (uint64_t)q);
+  src.tag = job->tag;
+  src.n_blocks = INT64_MAX;
+  hero_walk hw;
+  hw.lps = lps;
+  hw.C = C;
+  const double* F = hw.F;
+  for (int64_t pth = job->task_begin[t]; pth < job->task_end[t]; ++pth) {
+    path_result r;
+    src.path = (uint32_t)pth;
+    const int hero = (int)(pth % C);
+    hw.hero = hero;
+    walk_layers(&lps[hero], geo, &src, &r, NULL, 0, &hw);
+    for (int i = 0; i < C; ++i) {
+      double* tal = part + i * stride;
+      double* bins = tal + T_NSLOTS;
+      if (r.end == END_EXIT_TOP) {
+        tal[T_SUMX] += F[i];
+        tal[T_SUMX2] += F[i] * F[i];
+        tal[T_NEXIT] += 1.0;
+        bins[r.slot * 2 + 0] += F[i];
+        bins[r.slot * 2 + 1] += F[i] * F[i];
+      } else if (r.end == END_EXIT_BOTTOM) {
+        tal[T_SUMT] += F[i];
+      }
+    }
+    double* th = part + hero * stride;
+    if (r.end == END_CAPPED) th[T_CAPPED] += 1.0;
+    if (r.end == END_RR_KILLED) th[T_KILLED] += 1.0;
+    th[T_NSLOTS + (nb + 2) * 2] += (double)r.n_vert;
+  }
+}
+
 static void* worker(void* arg) {
   job_t* job = (job_t*)arg;
   for (;;) {
@@ -734,9 +892,11 @@ static void* worker(void* arg) {
   return NULL;
 }
 
-static int run_job(job_t* job, int n_threads) {
+/* Split the paths of n_owners owners (units, or groups of a hero walk) into
+ * tasks of at most ORC_RANGE paths and run them on n_threads threads. */
+static int run_job_groups(job_t* job, int64_t n_owners, int n_threads) {
   int64_t n_tasks = 0;
-  for (int64_t u = 0; u < job->n_units; ++u) {
+  for (int64_t u = 0; u < n_owners; ++u) {
     if (job->paths[u] < 0) return -1;
     n_tasks += (job->paths[u] + ORC_RANGE - 1) / ORC_RANGE;
   }
@@ -750,7 +910,7 @@ static int run_job(job_t* job, int n_threads) {
     return -2;
   }
   int64_t t = 0;
-  for (int64_t u = 0; u < job->n_units; ++u) {
+  for (int64_t u = 0; u < n_owners; ++u) {
     for (int64_t b = 0; b < job->paths[u]; b += ORC_RANGE) {
       job->task_unit[t] = u;
       job->task_begin[t] = b;
@@ -774,6 +934,8 @@ static int run_job(job_t* job, int n_threads) {
   pthread_mutex_destroy(&job->lock);
   return job->status ? -3 : 0;
 }
+
+static int run_job(job_t* job, int n_threads) { return run_job_groups(job, job->n_units, n_threads); }
 
 static void free_job(job_t* job) {
   free(job->task_unit); free(job->task_begin); free(job->task_end); free(job->part);
@@ -966,6 +1128,60 @@ int orc_layered_forward(const orc_geometry* geo, const double* sigma_t, const do
   return rc;
 }
 
+/* Hero-wavelength two-layer walk: units in groups of C consecutive units
+ * (u = q C + i; the members of a group share the top-layer thickness, and the
+ * indices are the call's), paths[q] paths per group (a multiple of C), path p
+ * of group q drawing from Philox counter (v, p, tag, unit_base + q) with hero
+ * member p mod C.  Outputs per unit as orc_layered_forward (tally[T_SUMA] is
+ * 0; vertices[u] counts the paths whose hero u was).  Returns -1 for bad
+ * arguments (C outside 1..16, a path count not a multiple of C, analog mode),
+ * -3 when a group's layers are invalid or their thicknesses differ. */
+int orc_layered_hero_forward(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                             const double* g, const double* thickness, double n_bottom,
+                             int64_t n_units, int C, const int64_t* paths, uint64_t seed,
+                             uint32_t tag, uint32_t unit_base, int n_threads, double* tally,
+                             double* bins, int64_t* vertices) {
+  if (check_geometry(geo) || geo->n_media != 2 || geo->analog || !(n_bottom > 0.0) || !sigma_t ||
+      !albedo || !g || !thickness || !paths || n_units < 0 || !tally || !bins || !vertices ||
+      C < 1 || C > ORC_MAX_HERO || n_units % C != 0)
+    return -1;
+  const int64_t n_groups = n_units / C;
+  for (int64_t q = 0; q < n_groups; ++q)
+    if (paths[q] % C != 0) return -1;
+  const int nb = geo->n_bins;
+  const int64_t stride = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = 2;
+  job.layered = 1; job.thickness = thickness; job.n_bottom = n_bottom;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g;
+  /* the task table runs over groups; load_layers reads unit q C + i of the
+   * full arrays, so the SoA stride is the unit count */
+  job.n_units = n_units;
+  job.hero = C;
+  job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
+  job.part_len = (int64_t)C * stride;
+  int rc = run_job_groups(&job, n_groups, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(tally, 0, sizeof(double) * (size_t)n_units * T_NSLOTS);
+  memset(bins, 0, sizeof(double) * (size_t)n_units * (size_t)(nb + 2) * 2);
+  for (int64_t u = 0; u < n_units; ++u) vertices[u] = 0;
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    const int64_t q = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int i = 0; i < C; ++i) {
+      const int64_t u = q * C + i;
+      const double* pi = part + i * stride;
+      for (int k = 0; k < T_NSLOTS; ++k) tally[u * T_NSLOTS + k] += pi[k];
+      for (int k = 0; k < (nb + 2) * 2; ++k) bins[u * (nb + 2) * 2 + k] += pi[T_NSLOTS + k];
+      vertices[u] += (int64_t)pi[T_NSLOTS + (nb + 2) * 2];
+    }
+  }
+  free_job(&job);
+  return rc;
+}
+
 /* Score-function gradient of the two-layer walk, the layered counterpart of
  * orc_adjoint: grad[n_units][8] = (sigma_t top, bottom, albedo top, bottom,
  * g top, bottom, 0, 0), raw sums over the paths leaving the top of
@@ -1033,7 +1249,7 @@ int orc_layered_trace(const orc_geometry* geo, const double* sigma_t, const doub
     src.n_blocks = n_blocks;
     if (words) src.words = words + p * n_blocks * 4;
     path_result r;
-    walk_layers(&lp, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks);
+    walk_layers(&lp, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks, NULL);
     double* o = path_out + p * 8;
     o[0] = r.end; o[1] = r.k; o[2] = r.slot; o[3] = r.x; o[4] = r.r;
     o[5] = (double)r.n_vert; o[6] = (double)r.n_coll; o[7] = r.absorbed;

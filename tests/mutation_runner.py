@@ -52,7 +52,8 @@ ORDER = ["energy", "special", "plane", "beer", "mixture", "single_scatter", "ana
          "brute", "adj_plane", "adj_mixture", "jacobian", "second_moment", "trace", "spherical",
          "analog_cosine", "layers_trace", "layers_beer", "layers_plane", "layers_absorbing_top",
          "layers_adj_absorbing_top",
-         "layers_stack", "layers_analog", "adding_doubling"]
+         "layers_stack", "layers_analog", "hero_reductions", "hero_closed_forms",
+         "adding_doubling"]
 
 
 def main():

@@ -626,6 +626,84 @@ def check_layer_trace_invariants(n_paths=3000, seed=24):
 
 
 # ---- multiple scattering with g != 0 and Fresnel: adding-doubling ------------
+def _hero(geo, members, d, n_bottom, C, paths, seed):
+    """members: list over units of ((sigma_t, albedo, g) top, (...) bottom)."""
+    s = np.array([[m[0][0] for m in members], [m[1][0] for m in members]], np.float64)
+    a = np.array([[m[0][1] for m in members], [m[1][1] for m in members]], np.float64)
+    g = np.array([[m[0][2] for m in members], [m[1][2] for m in members]], np.float64)
+    geo = O.Geometry(**{**geo.__dict__, "max_vertices": min(geo.max_vertices, 1 << 16)})
+    return O.layered_hero_forward(geo, s, a, g, np.full(len(members), d), n_bottom, C, paths,
+                                  seed)
+
+
+def check_hero_reduces_to_the_plain_walk(paths=1 << 13, seed=40):
+    """Hero-wavelength groups in the two-layer walk, two exact reductions:
+    (i) a group of one (C = 1) is the plain walk itself, bit for bit (same
+        streams, same weights and roulette), with an index step at the
+        interface and both incidence modes;
+    (ii) a group of C identical members gives every member the plain walk of
+        that group's stream (the balance weights are 1/C each), to rounding."""
+    rng = np.random.default_rng(seed)
+    n = 6
+    for inc, n0, n1 in ((0, 1.4, 1.4), (1, 1.4, 1.33)):
+        geo = O.Geometry(n_media=2, n_rel=n0, incidence=inc, n_bins=24, r_min_mm=1e-2,
+                         r_max_mm=20.0)
+        s = np.stack([rng.uniform(5, 40, n), rng.uniform(0.5, 5, n)])
+        a = np.stack([rng.uniform(0.3, 0.9, n), rng.uniform(0.8, 0.995, n)])
+        g = np.stack([rng.uniform(0.0, 0.9, n), rng.uniform(0.0, 0.9, n)])
+        d = rng.uniform(0.05, 0.3, n)
+        t1, b1, v1 = O.layered_hero_forward(geo, s, a, g, d, n1, 1, paths, seed)
+        t0, b0, v0 = O.layered_forward(geo, s, a, g, d, n1, paths, seed)
+        if not (np.array_equal(t1[:, :3], t0[:, :3]) and np.array_equal(b1, b0) and
+                np.array_equal(v1, v0)):
+            return _r(False, f"C = 1 differs from the plain walk (incidence {inc})")
+        # (ii) three copies of unit 2 as one group (group 0 draws unit 0's stream)
+        C = 3
+        N = paths - paths % C  # a multiple of C: every member is hero equally often
+        rep = lambda x: np.repeat(x[:, 2:3], C, axis=1)  # noqa: E731
+        th, bh, _ = O.layered_hero_forward(geo, rep(s), rep(a), rep(g), np.full(C, d[2]), n1, C,
+                                           N, seed)
+        tp, bp, _ = O.layered_forward(geo, s[:, 2:3], a[:, 2:3], g[:, 2:3], d[2:3], n1, N,
+                                      seed)
+        for i in range(C):
+            if not (np.allclose(th[i, :3], tp[0, :3], rtol=1e-12, atol=0) and
+                    np.allclose(bh[i], bp[0], rtol=1e-12, atol=0)):
+                return _r(False, f"identical members differ from the plain walk (member {i})")
+    return _r(True, "")
+
+
+def check_hero_against_closed_forms(paths=1 << 17, seed=41, k=3.5):
+    """Members that differ from the hero are reweighted by their path-density
+    ratios; their estimates must match closed forms of their own optics:
+    (i) an absorbing non-scattering top layer over an isotropic bottom (n = 1)
+        with members differing in the top layer's sigma_t (optical thickness
+        0.2, 0.5, 0.9) and the bottom's albedo, against
+        e^-tau int dR/dmu e^(-tau/mu) dmu;
+    (ii) two scattering layers with a Fresnel surface whose members differ in
+        g, sigma_t and albedo of both layers, against adding-doubling."""
+    from oracle import adding_doubling as AD
+
+    zs = []
+    paths -= paths % 3  # a multiple of the group size
+    geo = O.Geometry(n_media=2, n_rel=1.0)
+    d = 0.25
+    taus, als = (0.2, 0.5, 0.9), (0.95, 0.9, 0.8)
+    mem = [((t / d, 0.0, 0.0), (3.0, al, 0.0)) for t, al in zip(taus, als)]
+    tal, _, _ = _hero(geo, mem, d, 1.0, 3, paths, seed)
+    for i, (t, al) in enumerate(zip(taus, als)):
+        m, se = mean_se(tal[i, 0], tal[i, 1], paths)
+        zs.append((m - cf.R_absorbing_top(al, t)) / se)
+    geo = O.Geometry(n_media=2, n_rel=1.4)
+    d = 0.1
+    tops = ((8.0, 0.7, 0.8), (7.0, 0.75, 0.7), (9.0, 0.65, 0.85))
+    bots = ((2.0, 0.97, 0.6), (1.8, 0.95, 0.7), (2.3, 0.98, 0.5))
+    tal, _, _ = _hero(geo, list(zip(tops, bots)), d, 1.4, 3, paths, seed + 1)
+    for i, (tp, bt) in enumerate(zip(tops, bots)):
+        m, se = mean_se(tal[i, 0], tal[i, 1], paths)
+        zs.append((m - AD.two_layer_R((tp[1], tp[2], tp[0] * d), (bt[1], bt[2]), 1.4)) / se)
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
 def check_adding_doubling(paths=1 << 18, seed=30, k=3.0):
     """Totals of multiply-scattering media with anisotropic scattering and a
     Fresnel boundary against the deterministic adding-doubling solution
@@ -681,4 +759,6 @@ BATTERY_SMALL = [
     ("layers_analog", lambda: check_layers_analog_vs_weighted(paths=1 << 16, k=4.0)),
     ("layers_trace", lambda: check_layer_trace_invariants(n_paths=1500)),
     ("adding_doubling", lambda: check_adding_doubling(paths=1 << 16, k=4.0)),
+    ("hero_reductions", lambda: check_hero_reduces_to_the_plain_walk(paths=1 << 11)),
+    ("hero_closed_forms", lambda: check_hero_against_closed_forms(paths=1 << 16, k=4.0)),
 ]

@@ -71,6 +71,17 @@ MUTATIONS = [
      "jacB[(int64_t)j * (nb + 2) + r.slot] += r.x * score[j];"),
     ("jacobian_total_times_cotangent", "jacR[j] += r.x * score[j];",
      "jacR[j] += r.x * cot * score[j];"),
+    ("hero_no_group_factor", "hw->F[i] = (double)hw->C * hw->x[i] * exp(lp[i] - m) / S;",
+     "hw->F[i] = hw->x[i] * exp(lp[i] - m) / S;"),
+    ("hero_density_with_hero_sigma", "(double)res->n_coll_l[l] * log(hw->lps[i].sigma_t[l]) -",
+     "(double)res->n_coll_l[l] * log(hw->lps[hw->hero].sigma_t[l]) -"),
+    ("hero_density_length_sign", "-\n               hw->lps[i].sigma_t[l] * res->L_l[l];",
+     "+\n               hw->lps[i].sigma_t[l] * res->L_l[l];"),
+    ("hero_phase_density_of_hero_g", "hw->hg[i] += hg_log_pdf(hw->lps[i].g[layer], mu);",
+     "hw->hg[i] += hg_log_pdf(hw->lps[hw->hero].g[layer], mu);"),
+    ("hero_weight_with_hero_albedo", "hw->x[i] *= hw->lps[i].albedo[layer];",
+     "hw->x[i] *= hw->lps[hw->hero].albedo[layer];"),
+    ("hero_never_rotates", "const int hero = (int)(pth % C);", "const int hero = 0;"),
 ]
 
 
@@ -90,6 +101,10 @@ def _run(lib, rr, threads=None):
     env = dict(os.environ)
     if threads:
         env["ORC_THREADS"] = str(threads)
+        # the battery's small dense solves (adding-doubling) run one BLAS thread:
+        # parallel batteries with a full BLAS pool each oversubscribe the host
+        for var in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[var] = "1"
     try:
         p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=240, env=env)
     except subprocess.TimeoutExpired:

@@ -217,3 +217,11 @@ def test_multiple_scattering_against_adding_doubling():
     # 0.5 SE of the adding-doubling value)
     ok, detail = P.check_adding_doubling(paths=1 << 20, k=3.5)
     assert ok, detail
+
+
+def test_hero_wavelength_groups_reduce_to_the_plain_walk():
+    _assert(P.check_hero_reduces_to_the_plain_walk())
+
+
+def test_hero_wavelength_members_match_closed_forms():
+    _assert(P.check_hero_against_closed_forms())
