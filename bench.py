@@ -226,6 +226,9 @@ def main():
     ap.add_argument("--c3-plain-sets", type=int, default=512)
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-hero", action="store_true")
+    ap.add_argument("--hero-tones", type=int, default=64)
+    ap.add_argument("--hero-photons", type=int, default=1 << 16)
     ap.add_argument("--c5-targets", type=int, default=4096)
     ap.add_argument("--c5-iters", type=int, default=200)
     ap.add_argument("--c5-lut", type=int, default=800)
@@ -454,6 +457,8 @@ def main():
         out["batched_sweep"] = c3(ctx, rw, api, workloads, torch, args)
     if not args.no_c4:
         out["adjoint_sweep"] = c4(ctx, rw, workloads, torch, args)
+    if not args.no_hero:
+        out["hero_wavelengths"] = hero_leg(ctx, rw, api, workloads, torch, args)
     if not args.no_c5:
         out["inverse_fit"] = c5(torch, args)
     if not args.no_cpu_baseline:
@@ -498,6 +503,49 @@ def autotuned_leg(rw, torch, cur, run, bat, args):
             "same_vertices_as_untuned": r["vf"] == bat["vf"],
             "chosen": chosen,
             "default": {"chunk": 2048, "waves_per_wg": 4, "wgs_per_cu": "occupancy limit"}}
+
+
+def hero_leg(ctx, rw, api, workloads, torch, args):
+    """Hero wavelengths on the two-layer tones: the per-wavelength walk
+    (rw_layered_forward, N photons per wavelength) against groups of C
+    neighbouring wavelengths sharing N photons per group
+    (rw_layered_hero_forward), on the same tones.  Reported per form: the
+    launch time, the walked vertices, the median relative standard error of R,
+    and the efficiency gain, the median over wavelengths of
+    (SE^2 x time) of the per-wavelength walk over that of the hero walk."""
+    wl = workloads.layered_tones(args.hero_tones, paths=args.hero_photons)
+    L = rw.Layers.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm, wl.n_rel_bottom)
+    geom = rw.Geometry(n_media=2, n_rel=wl.n_rel, n_bins=wl.n_bins)
+    N = args.hero_photons
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        e0.record(s)
+        r = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    plain, t_plain = timed(lambda: api.layered_forward(ctx, L, geom, N, 3, stream=s))
+    se_p = (plain.R_se / plain.R).cpu().numpy()
+    res = {"workload": f"two-layer tones: {args.hero_tones} tones x 81 wavelengths, "
+                       f"{N} photons per wavelength (per-wavelength walk) or per group",
+           "per_wavelength": {"ms": t_plain, "vertices": int(plain.vertices.sum()),
+                              "median_rel_se": float(np.median(se_p))}}
+    for C in (3, 9):
+        h, t_h = timed(lambda: api.layered_hero_forward(ctx, L, geom, C, N - N % C, 3, stream=s))
+        assert rw.rw_check(ctx, h.tally.flags) == 0
+        se_h = (h.R_se / h.R).cpu().numpy()
+        gain = (se_p ** 2 * t_plain) / (se_h ** 2 * t_h)
+        res[f"hero_{C}"] = {"ms": t_h, "vertices": int(h.vertices.sum()),
+                            "median_rel_se": float(np.median(se_h)),
+                            "efficiency_gain_median": float(np.median(gain)),
+                            "efficiency_gain_p10_p90": [float(np.quantile(gain, 0.1)),
+                                                        float(np.quantile(gain, 0.9))]}
+    return res
 
 
 def c5(torch, args):

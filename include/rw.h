@@ -285,6 +285,32 @@ rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_
                              double* grad_sumsq, int64_t* vertices, int32_t* flags,
                              const rw_batch_opts* opts, void* stream);
 
+/* Hero-wavelength form of the two-layer walk (Wilkie et al. 2014's hero
+ * wavelength, named in Sec. 2; Sec. 3's simulator propagates all its
+ * wavelengths together): one path serves a group of n_hero wavelengths of one
+ * tissue.  Units come in groups of n_hero consecutive units (u = q n_hero + i,
+ * e.g. a tone's wavelengths); members of a group must share the top-layer
+ * thickness (else the group keeps zero tallies and RW_FLAG_BAD_PARAMS is
+ * raised); the indices are the call's.  Path p of group q draws Philox counter
+ * (v, p, 0, unit_base + q) and is sampled with the optics of member p mod
+ * n_hero (its flights from that member's sigma_t, its scatterings from its
+ * g); every member carries its own albedo weight, Russian roulette decides on
+ * the largest weight, and a path that leaves contributes to member i the
+ * one-sample balance-heuristic estimate n_hero x_i p_i / sum_j p_j, where
+ * p_j is the path's density under member j's optics.  With n_hero = 1 this
+ * is rw_layered_forward's walk.  n_hero: 1, 2, 3, 4, 8 or 9;
+ * paths_per_group: a multiple of n_hero in [0, 2^31] (each member then was
+ * hero of the same number of paths); every unit's estimate is a mean over its
+ * group's paths_per_group paths (finalize with that count).  Outputs per unit
+ * as rw_layered_forward's exact sums, except sum A = 0 (absorbed weight is
+ * not estimated) and vertices[u] = the vertices of the paths unit u was hero
+ * of.  A device workspace of 8 n_hero (2 n_bins + 6) bytes per work item of
+ * 2048 paths (grown so that it stays within 1 GiB). */
+rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
+                                  const rw_geometry* geom, int32_t n_hero,
+                                  int64_t paths_per_group, uint64_t seed, rw_tally* out,
+                                  void* stream);
+
 /* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
  * path count N the walk ran: with a DEVICE int32 paths_per_unit [n_units],
  * N = min(max(paths_per_unit[u], 0), paths_uniform) (the clamp of

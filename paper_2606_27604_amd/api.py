@@ -76,6 +76,15 @@ def layered_forward(ctx: Context, layers, geom: Geometry, paths: int, seed: int,
     return finalize(ctx, geom, tally, layers.n_units, paths, paths_per_unit, stream=stream)
 
 
+def layered_hero_forward(ctx: Context, layers, geom: Geometry, n_hero: int, paths: int,
+                         seed: int, stream=None) -> ForwardResult:
+    """Hero-wavelength two-layer walk (rw_layered_hero_forward) + finalize:
+    units in groups of n_hero wavelengths sharing paths, `paths` per group."""
+    tally = Tally(layers.n_units, geom.n_bins, device=layers.sigma_t.device)
+    rw.rw_layered_hero_forward(ctx, layers, geom, n_hero, paths, seed, tally, stream=stream)
+    return finalize(ctx, geom, tally, layers.n_units, paths, stream=stream)
+
+
 def layered_adjoint(ctx: Context, layers, geom: Geometry, paths: int, seed: int, cot_R=None,
                     cot_bins=None, paths_per_unit=None, use_graph: bool = True, stream=None,
                     path_mask=None):

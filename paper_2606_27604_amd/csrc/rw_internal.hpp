@@ -157,6 +157,34 @@ struct LutArgs {
 };
 hipError_t launch_lut(const LutArgs& a, int K, hipStream_t stream);
 
+// Hero-wavelength two-layer walk (rw_hero.hip): units in groups of C
+// consecutive units, group q drawing Philox counter (v, p, tag, unit_base + q)
+// with hero member p mod C; per-item slots [n_items][C][2 (n_bins + 2) + 2]
+// int64 (bins, T, vertices of the paths the member was hero of).
+struct HeroArgs {
+  const float* sigma_t;        // SoA [2][k_stride] (top, bottom)
+  const float* albedo;
+  const float* g;
+  const float* layer_d;        // [k_stride] top-layer thickness
+  int64_t k_stride;
+  uint64_t unit_base;          // counter index of group 0
+  WalkGeom geo;
+  uint32_t key0, key1, tag;
+  int64_t n_groups, group_begin;
+  int64_t paths_per_group;
+  int64_t chunk, chunks_per_group, n_items;
+  float fix_scale32, fix_cap;
+  void* slots;
+  double* out_R;               // [n_units][4]
+  double* out_bins;            // [n_units][n_bins + 2][2]
+  int64_t* out_vertices;       // [n_units]
+  int32_t* flags;
+};
+constexpr bool hero_group_supported(int C) {
+  return C == 1 || C == 2 || C == 3 || C == 4 || C == 8 || C == 9;
+}
+hipError_t launch_hero(const HeroArgs& a, int C, hipStream_t stream);
+
 // launchers (rw_kernels.hip); all asynchronous on `stream`
 hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg, int grid_wgs,
                        hipStream_t stream);

@@ -1130,6 +1130,77 @@ rw_status rw_layered_adjoint(rw_context* ctx, const rw_layers* layers, const rw_
                   true, stream);
 }
 
+rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
+                                  const rw_geometry* geom, int32_t n_hero,
+                                  int64_t paths_per_group, uint64_t seed, rw_tally* out,
+                                  void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error[0] = 0;
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  MediaView v;
+  st = check_layers(ctx, layers, geom, &v);
+  if (st != RW_OK) return st;
+  if (!hero_group_supported(n_hero))
+    return fail(ctx, RW_E_UNSUPPORTED, "hero groups of %d wavelengths are not supported "
+                "(1, 2, 3, 4, 8 or 9)", n_hero);
+  const int64_t n_units = layers->n_units;
+  if (n_units % n_hero != 0)
+    return fail(ctx, RW_E_INVALID, "n_units (%lld) is not a multiple of the group size %d",
+                (long long)n_units, n_hero);
+  if (paths_per_group < 0 || paths_per_group > (int64_t(1) << 31) || paths_per_group % n_hero)
+    return fail(ctx, RW_E_INVALID, "paths per group must be a multiple of %d in [0, 2^31]",
+                n_hero);
+  if (!out || !out->R || !out->bins || !out->vertices || !out->flags)
+    return fail(ctx, RW_E_INVALID, "tally pointers must be non-NULL");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HeroArgs a{};
+  a.sigma_t = v.sigma_t;
+  a.albedo = v.albedo;
+  a.g = v.g;
+  a.layer_d = v.layer_d;
+  a.k_stride = v.k_stride;
+  a.unit_base = uint64_t(v.unit_base);
+  a.geo = make_geom(geom);
+  set_bottom_index(a.geo, v.n_bottom);
+  a.key0 = uint32_t(seed);
+  a.key1 = uint32_t(seed >> 32);
+  a.tag = kForwardTag;
+  a.n_groups = n_units / n_hero;
+  a.group_begin = 0;
+  a.paths_per_group = paths_per_group;
+  // items of 2048 paths, grown so that the slots stay within kMaxSlotBytes
+  const int64_t words = int64_t(n_hero) * (2 * (geom->n_bins + 2) + 2);
+  int64_t chunk = 2048;
+  while (paths_per_group > chunk &&
+         a.n_groups * ((paths_per_group + chunk - 1) / chunk) * words * 8 > kMaxSlotBytes)
+    chunk *= 2;
+  a.chunk = chunk;
+  a.chunks_per_group = (paths_per_group + chunk - 1) / chunk;
+  a.n_items = a.n_groups * a.chunks_per_group;
+  // each contribution is at most C times a weight below x_max: 32-bit fixed
+  // point with s = 31 - ceil(log2(C x_max)) fraction bits
+  const double x_max = 2.0 * double(n_hero) *
+                       std::max(1.0, double(a.geo.rr_weight) * double(a.geo.rr_boost));
+  a.fix_scale32 = float(std::ldexp(1.0, 31 - int(std::ceil(std::log2(x_max)))));
+  a.fix_cap = float(x_max * (1.0 - 0x1p-20));
+  a.out_R = out->R;
+  a.out_bins = out->bins;
+  a.out_vertices = out->vertices;
+  a.flags = out->flags;
+  RW_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(out->flags), 1, 0u, s));
+  if (a.n_items > 0) {
+    st = ensure_workspace(ctx, size_t(a.n_items * words * 8));
+    if (st != RW_OK) return st;
+    a.slots = ctx->workspace;
+    RW_HIP(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(a.slots), a.n_items * words, s));
+  }
+  RW_HIP(ctx, launch_hero(a, n_hero, s));
+  return RW_OK;
+}
+
 rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
                       const int32_t* paths_per_unit, int64_t paths_uniform, const rw_tally* tally,
                       double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,

@@ -129,7 +129,7 @@ EXPORTS = [
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
     "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
     "rw_layered_adjoint", "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
-    "rw_forward_noalloc",
+    "rw_forward_noalloc", "rw_layered_hero_forward",
 ]
 
 _lib = None
@@ -160,6 +160,9 @@ def load_library(path: str = LIB_PATH):
     L.rw_forward.restype = ctypes.c_int
     L.rw_forward_noalloc.argtypes = [vp, P(RwMediaC), P(RwGeometryC), i64, u64, P(RwTallyC), vp]
     L.rw_forward_noalloc.restype = ctypes.c_int
+    L.rw_layered_hero_forward.argtypes = [vp, P(RwLayersC), P(RwGeometryC), i32, i64, u64,
+                                          P(RwTallyC), vp]
+    L.rw_layered_hero_forward.restype = ctypes.c_int
     L.rw_batch_forward.argtypes = [vp, P(RwMediaC), P(RwGeometryC), vp, i64, u64, P(RwTallyC),
                                    P(RwBatchOptsC), vp]
     L.rw_batch_forward.restype = ctypes.c_int
@@ -521,6 +524,15 @@ def rw_layered_adjoint(ctx: Context, layers: Layers, geom: Geometry, paths_per_u
         ctx.h, ctypes.byref(layers._c), ctypes.byref(g), _ptr(paths_per_unit), int(paths_uniform),
         int(seed), _ptr(cot_R), _ptr(cot_bins), _ptr(grad), _ptr(grad_sumsq), _ptr(vertices),
         _ptr(flags), ctypes.byref(o), _stream(stream)))
+
+
+def rw_layered_hero_forward(ctx: Context, layers: Layers, geom: Geometry, n_hero: int,
+                            paths_per_group: int, seed: int, out: Tally, stream=None):
+    g = geom.c()
+    ctx._check(load_library().rw_layered_hero_forward(ctx.h, ctypes.byref(layers._c),
+                                                      ctypes.byref(g), int(n_hero),
+                                                      int(paths_per_group), int(seed),
+                                                      ctypes.byref(out._c), _stream(stream)))
 
 
 def rw_debug_trace_layered(ctx: Context, layers: Layers, geom: Geometry, words, n_paths: int,

@@ -167,3 +167,22 @@ def test_noalloc_forward_checks_its_scratch_bound_on_the_host(lib):
     bad_t = rw.RwTallyC(0x5000, 0, 0x7000, 0x8000)
     assert lib.rw_forward_noalloc(ctx.h, ctypes.byref(m), ctypes.byref(g256), 16, 0,
                                   ctypes.byref(bad_t), None) == rw.RW_E_INVALID
+
+
+def test_hero_walk_argument_checks(lib):
+    """rw_layered_hero_forward rejects unsupported group sizes, unit counts
+    that are not a multiple of the group and path counts that are not a
+    multiple of it, before anything reaches a device."""
+    ctx = rw.Context(-1)
+    g = rw.Geometry(n_media=2).c()
+    t = rw.RwTallyC(0x5000, 0x6000, 0x7000, 0x8000)
+    L = rw.RwLayersC(0x1000, 0x2000, 0x3000, 0x4000, 1.4, 36, 0, 0)
+    call = lambda C, n: lib.rw_layered_hero_forward(ctx.h, ctypes.byref(L), ctypes.byref(g), C,  # noqa: E731
+                                                    n, 0, ctypes.byref(t), None)
+    assert call(5, 1000) == rw.RW_E_UNSUPPORTED
+    assert call(8, 800) == rw.RW_E_INVALID        # 36 units are not groups of 8
+    assert call(3, 1000) == rw.RW_E_INVALID       # 1000 paths are not a multiple of 3
+    assert call(9, 900) == rw.RW_E_UNSUPPORTED and "validation-only" in ctx.last_error()
+    g3 = rw.Geometry(n_media=3).c()
+    assert lib.rw_layered_hero_forward(ctx.h, ctypes.byref(L), ctypes.byref(g3), 3, 300, 0,
+                                       ctypes.byref(t), None) == rw.RW_E_INVALID
