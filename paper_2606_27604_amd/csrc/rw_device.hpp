@@ -191,6 +191,7 @@ __device__ __forceinline__ WalkGeom step_geom_in_vgprs(const WalkGeom& g) {
   r.n_rel = in_vgpr(g.n_rel);
   r.n_rel2 = in_vgpr(g.n_rel2);
   r.slab_mm = in_vgpr(g.slab_mm);
+  r.z_bottom = in_vgpr(g.z_bottom);
   r.rr_weight = in_vgpr(g.rr_weight);
   r.rr_survive = in_vgpr(g.rr_survive);
   r.rr_boost = in_vgpr(g.rr_boost);
@@ -431,12 +432,21 @@ __device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkG
 // vertex v >= 1: flight, then boundary interaction or collision.  Returns the
 // vertex event.  ADJ adds the score bookkeeping (collisions, flight length,
 // g score).
+// Does a flight from depth z along uz to the new depth zn reach the top (or,
+// for a slab, the bottom) surface?
+__device__ __forceinline__ bool reaches_top(const Path& p, float zn) {
+  return (p.uz < 0.0f) && (zn <= 0.0f);
+}
+__device__ __forceinline__ bool reaches_bottom(const Path& p, float zn, const WalkGeom& geo) {
+  return geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
+}
+
 template <bool ADJ>
 __device__ __forceinline__ int vertex_step_drawn(Path& p, const VertexDraw& d, const WalkGeom& geo) {
   const float s = d.s;
   const float zn = fmaf(s, p.uz, p.z);
-  const bool top = (p.uz < 0.0f) && (zn <= 0.0f);
-  const bool bottom = geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
+  const bool top = reaches_top(p, zn);
+  const bool bottom = reaches_bottom(p, zn, geo);
   if (top || bottom) {
     const float db = (top ? -p.z : (geo.slab_mm - p.z)) * __builtin_amdgcn_rcpf(p.uz);
     p.x = fmaf(db, p.ux, p.x);
@@ -463,8 +473,10 @@ __device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo
 // Collision at the end of a flight of length s (new depth zn): implicit
 // capture (A += W (1 - alpha), W *= alpha), roulette, Henyey-Greenstein
 // scattering.
+// The two halves of a collision around the roulette test: the move to the
+// collision point with implicit capture, then the scattering.
 template <bool ADJ>
-__device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkGeom& geo, float zn) {
+__device__ __forceinline__ void absorb_at(Path& p, const VertexDraw& d, float zn) {
   const float s = d.s;
   p.x = fmaf(s, p.ux, p.x);
   p.y = fmaf(s, p.uy, p.y);
@@ -475,6 +487,17 @@ __device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkG
   }
   p.A = fmaf(p.W, 1.0f - p.m.alb, p.A);
   p.W *= p.m.alb;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void scatter(Path& p, const VertexDraw& d) {
+  if (ADJ) p.Sg = fmaf((d.mu - p.m.g) * d.den, p.m.gq, p.Sg);
+  rotate(p.ux, p.uy, p.uz, d.mu, d.p, d.q);
+}
+
+template <bool ADJ>
+__device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkGeom& geo, float zn) {
+  absorb_at<ADJ>(p, d, zn);
   if (p.W < geo.rr_weight) {
     if (u01(d.w3) < geo.rr_survive) {
       p.W *= geo.rr_boost;
@@ -482,9 +505,23 @@ __device__ __forceinline__ int collide(Path& p, const VertexDraw& d, const WalkG
       return EV_RR_KILL;
     }
   }
-  if (ADJ) p.Sg = fmaf((d.mu - p.m.g) * d.den, p.m.gq, p.Sg);
-  rotate(p.ux, p.uy, p.uz, d.mu, d.p, d.q);
+  scatter<ADJ>(p, d);
   return EV_COLLIDE;
+}
+
+// A vertex of the mixture walk that is a plain collision: the flight ends
+// strictly between the top surface (z = 0) and z_bottom (the slab bottom, else
+// +inf), and the new weight is at or above the roulette threshold.  For such
+// a vertex vertex_step_drawn reduces to absorb_at then scatter, the same
+// operations in the same order.  The test errs only towards the general
+// step: a flight ending exactly on a surface is not taken as plain.
+__device__ __forceinline__ bool plain_collision(const Path& p, const VertexDraw& d,
+                                                const WalkGeom& geo, float& zn) {
+  zn = fmaf(d.s, p.uz, p.z);
+  // evaluated in full (no short circuit): it is tested by a ballot
+  const int in = int(zn > 0.0f) & int(zn < geo.z_bottom) &
+                 int(!(p.W * p.m.alb < geo.rr_weight));
+  return in != 0;
 }
 
 // ---------------------------------------------------------------------------

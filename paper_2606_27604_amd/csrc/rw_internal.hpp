@@ -26,6 +26,7 @@ struct WalkGeom {
   float n_rel, n_rel2;
   float entry_weight;     // 1 - F(0)
   float slab_mm;
+  float z_bottom;         // slab_mm for a slab, else +inf
   float r_min, r_max;
   float log2_rmin;        // log2(r_min)
   float bin_scale;        // n_bins / log2(r_max / r_min)

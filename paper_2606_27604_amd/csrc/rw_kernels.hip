@@ -543,10 +543,37 @@ walk_kernel(const WalkArgs a) {
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const uint32_t depth = 1u << lg;
-    for (uint32_t s = 0; s < depth; ++s) {
-      if (__ballot(sel) == 0) break;
+    // this lane's draws (a lane outside the selection reads the first ones)
+    const uint32_t base = sel ? (rank << lg) : 0u;
+    uint32_t s = 0;
+    while (s < depth && __ballot(sel) != 0) {
+      if constexpr (!LAYERED) {
+        // A long path spends nearly all its vertices colliding away from the
+        // surface above the roulette threshold.  While that holds for every
+        // selected path, one ballot per step says so and the step runs as
+        // straight-line code; the first step where it does not goes through
+        // the general step below.  The straight-line step runs on every lane:
+        // a lane outside the selection holds no running path (the tail calls
+        // this with the running lanes), so its state is free to overwrite.
+        // The vertex cap is checked once for the round.  (The next step's
+        // draw is read before this step's arithmetic, so that the LDS latency
+        // overlaps it.)
+        const bool room = __ballot(sel && v + (depth - s) > geo.max_vertices) == 0;
+        VertexDraw d = load_draw<ADJ>(dr, base + s);
+        for (; room && s < depth; ++s) {
+          float zn;
+          const bool plain = plain_collision(p, d, geo, zn);
+          if (__ballot(sel & !plain) != 0) break;
+          const VertexDraw dn = load_draw<ADJ>(dr, base + (s + 1 < depth ? s + 1 : s));
+          absorb_at<ADJ>(p, d, zn);
+          scatter<ADJ>(p, d);
+          ++v;
+          d = dn;
+        }
+        if (s == depth) break;
+      }
       if (sel) {
-        const uint32_t i = (rank << lg) + s;
+        const uint32_t i = base + s;
         int ev;
         if constexpr (LAYERED) {
           ev = step_any<ADJ, LAYERED>(p, blk[i], geo);
@@ -579,6 +606,7 @@ walk_kernel(const WalkArgs a) {
           ++v;
         }
       }
+      ++s;
     }
   };
 

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -163,6 +164,7 @@ WalkGeom make_geom(const rw_geometry* g) {
   const double F0 = ((n - 1.0) / (n + 1.0)) * ((n - 1.0) / (n + 1.0));
   w.entry_weight = float(1.0 - F0);
   w.slab_mm = g->slab_mm > 0.0f ? g->slab_mm : 0.0f;
+  w.z_bottom = w.slab ? w.slab_mm : std::numeric_limits<float>::infinity();
   w.r_min = g->r_min_mm;
   w.r_max = g->r_max_mm;
   w.log2_rmin = float(std::log2(double(g->r_min_mm)));
