@@ -122,8 +122,8 @@ def load_traffic(kernel_name: str):
 
 
 def load_counters(kernel_name: str):
-    """rocprofv3 VALU counters of the kernel (profiles/valu_counters.json): the
-    primary utilisation definition (issue-busy x active-lane fraction), used
+    """rocprofv3 VALU counters of the kernel (profiles/valu_counters.json): VALU
+    busy calibrated against a saturating FMA stream x active-lane fraction, used
     only while the kernel sources still hash to the profiled version."""
     path = os.path.join(ROOT, "profiles", "valu_counters.json")
     try:
@@ -134,8 +134,9 @@ def load_counters(kernel_name: str):
     e = t.get(kernel_name)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
-    return {k: e[k] for k in ("issue_busy", "active_lane_fraction", "exec_weighted_utilisation",
-                              "transcendental_share", "transcendental_rate_fraction")}
+    return {k: e[k] for k in ("valu_busy_vs_fma", "active_lane_fraction",
+                              "exec_weighted_utilisation", "transcendental_share",
+                              "transcendental_rate_fraction")}
 
 
 def host_cpu():
@@ -382,7 +383,8 @@ def main():
     if adj_avg >= fwd_avg:
         dom, dom_ms, dom_v = "walk_kernel<3, adjoint>", adj_avg, va_avg
     else:
-        dom, dom_ms, dom_v = "walk_kernel<3, forward>", fwd_avg, vf_avg
+        # the forward that sets the live-path mask (its own instantiation)
+        dom, dom_ms, dom_v = "walk_kernel<3, forward, marked>", fwd_avg, vf_avg
     slots = alg_slots_per_vertex(dom.endswith("adjoint>"))
     achieved = slots * dom_v / (dom_ms * 1e-3) / 1e12
     peak = ISSUE_PEAK / 1e12
@@ -430,8 +432,9 @@ def main():
                              "per second against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; traffic = "
                              "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated); "
                              "counters = rocprofv3 SQ counters of the same kernel (exec-weighted "
-                             "VALU utilisation = issue-busy x active-lane fraction; transcendental "
-                             "lane-ops/s over their measured peak)"},
+                             "VALU utilisation = VALU busy, calibrated against a saturating FMA "
+                             "stream, x active-lane fraction; transcendental lane-ops/s over "
+                             "their measured peak)"},
     }
     if plain is not None:
         for name, r in (("plain", plain), ("batched_full_replay", full)):
@@ -600,6 +603,13 @@ def c3(ctx, rw, api, workloads, torch, args):
     res = {"workload": f"batched-{wl.n_sets}x16: K=3, n=1.4, 4096 paths per unit",
            "units": n, "batched_ms": full_ms, "batched_vertices_per_s": full_v / (full_ms * 1e-3),
            "spectra_per_s": wl.n_sets / (full_ms * 1e-3)}
+    slots = alg_slots_per_vertex(False)
+    achieved = slots * full_v / (full_ms * 1e-3) / 1e12
+    key = f"walk_kernel<3, forward>@batched-{wl.n_sets}x16"
+    res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ISSUE_PEAK / 1e12,
+                       "unit": "Tslot/s", "frac": achieved / (ISSUE_PEAK / 1e12),
+                       "kernel": "walk_kernel<3, forward>", "slots_per_vertex": slots,
+                       "counters": load_counters(key), "traffic": load_traffic(key)}
     # matched shape: one plain static launch (rw_forward) over all the units,
     # same seed, same estimates
     stat = rw.Tally(n, wl.n_bins)
@@ -750,6 +760,7 @@ def lut_generation(rw, torch, args):
         "R_range": [float(table.R.min()), float(table.R.max())],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": load_traffic("walk_kernel<1, forward>"),
+                     "counters": load_counters("walk_kernel<1, forward>"),
                      "kernel": "walk_kernel<1, forward>", "slots_per_vertex": slots},
     }
     del table
@@ -806,6 +817,7 @@ def layered_tones(rw, torch, args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak,
                      "traffic": load_traffic("walk_kernel<2, forward, layered>"),
+                     "counters": load_counters("walk_kernel<2, forward, layered>"),
                      "kernel": "walk_kernel<2, forward, layered>", "slots_per_vertex": slots,
                      "note": "slot model of the mixture forward vertex (the interface adds "
                              "work only at crossing vertices)"},

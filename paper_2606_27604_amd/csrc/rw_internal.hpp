@@ -226,7 +226,9 @@ hipError_t launch_unit_order(const WalkArgs& a, int K, int32_t* bucket, uint32_t
                              int32_t* unit_order, hipStream_t stream);
 
 // kernel entry points, for graph nodes
-const void* walk_kernel_ptr(int K, bool adjoint);
+// the walk instantiation of a launch: adjoint, or forward with (mark) or
+// without the live-path mask
+const void* walk_kernel_ptr(int K, bool adjoint, bool mark);
 const void* fill_u32_kernel_ptr();
 const void* fill_u64_kernel_ptr();
 const void* unit_cost_kernel_ptr(int K);

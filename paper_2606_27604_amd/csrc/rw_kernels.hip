@@ -64,11 +64,38 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
 // live mask.  The words of a work item belong to that item alone (items span
 // whole words: their first path is a multiple of the chunk, itself a
 // multiple of 64, and every unit starts on a word), and one wave runs all of
-// an item's paths, so the OR needs no ordering beyond the workgroup; it
-// stays in the L2 of the wave's XCD and is visible to later launches.
+// an item's paths, so the OR needs no ordering beyond the workgroup.  The
+// counters show such atomics writing through to memory, one 32-byte write
+// each; the main loop therefore gathers the bits of its current item in LDS
+// (live_window below) and this direct form serves only the paths that end
+// after their wave moved on, and the tail.
 __device__ __forceinline__ void mark_live(const WalkArgs& a, uint32_t u, uint32_t path) {
   __hip_atomic_fetch_or(a.live_mask + int64_t(u) * a.mask_words + (path >> 5), 1u << (path & 31u),
                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The live bits of the first kLiveWindow mask words of the wave's current
+// work item, gathered in LDS (the part of the exit ring's area that only the
+// tail's draws use) and ORed into the mask when the wave takes another item:
+// one atomic per nonzero word instead of one per path that leaves the top.
+// Only the wave's own paths set bits here, so the OR leaves the bits of other
+// waves' items as they are.
+constexpr uint32_t kLiveWindow = kWave;
+constexpr uint32_t kNoUnit = 0xFFFFFFFFu;
+static_assert(2 * walk_ring_words(false) >= 4 * kExitRing + int(kLiveWindow),
+              "the live window must fit behind the forward exit ring");
+
+// wave-wide: lane l ORs word wb + l of unit wu into the mask and clears it
+__device__ __forceinline__ void flush_live(const WalkArgs& a, uint32_t* win, uint32_t wu,
+                                           uint32_t wb, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const uint32_t bits = win[lane];
+  const uint32_t w = wb + uint32_t(lane);
+  if (bits != 0u && wu != kNoUnit && w < uint32_t(a.mask_words))
+    __hip_atomic_fetch_or(a.live_mask + int64_t(wu) * a.mask_words + w, bits, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+  win[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 // item -> (local unit, first path, end path); pb >= pe for an empty item
@@ -134,6 +161,7 @@ struct WaveLds {
   float* media;
   ColdConst* cold;
   float4* ring;
+  uint32_t* live;   // forward: the live window, behind the exit ring
 };
 
 // Read from LDS where used: reads that a store in the loop may alias stay in
@@ -445,10 +473,13 @@ __device__ __forceinline__ VertexDraw load_draw(const float* dr, uint32_t i) {
 // The two-layer adjoint carries both layers' scores and would take 81 VGPRs,
 // i.e. 5 waves per SIMD; asking for 6 fits it in 79 without spills (7 would
 // spill in the vertex loop).  The other instantiations are left to the
-// compiler (7 waves at 63-74 VGPRs).
-template <int K, bool ADJ, bool LAYERED>
+// compiler (7 waves at 63-74 VGPRs).  MARK: a forward that sets the live-path
+// mask; its own instantiation, so that a forward without the mask carries
+// none of the marking code.
+template <int K, bool ADJ, bool LAYERED, bool MARK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ && LAYERED ? 6 : 1)))
 walk_kernel(const WalkArgs a) {
+  static_assert(!(ADJ && MARK), "only the forward marks paths");
   extern __shared__ u64 lds[];
   const int lane = lane_id();
   // the wave index is uniform; say so, or every schedule value derived from it
@@ -461,7 +492,9 @@ walk_kernel(const WalkArgs a) {
   L.media = reinterpret_cast<float*>(L.acc + a.acc_words);
   L.cold = reinterpret_cast<ColdConst*>(L.acc + a.acc_words + kMediaTableWords);
   L.ring = reinterpret_cast<float4*>(L.acc + a.acc_words + kMediaTableWords + kColdConstWords);
+  L.live = MARK ? reinterpret_cast<uint32_t*>(L.ring + kExitRing) : nullptr;
   for (int i = lane; i < a.acc_words; i += kWave) L.acc[i] = 0ull;
+  if (MARK) L.live[lane] = 0u;
   if (lane == 0) {
     float4* q = reinterpret_cast<float4*>(L.cold);
     q[0] = make_float4(a.geo.r_min, a.geo.r_max, a.geo.log2_rmin, a.geo.bin_scale);
@@ -484,6 +517,8 @@ walk_kernel(const WalkArgs a) {
   // of this visit, the ring
   int64_t u_cur = -1, cur_slot = -1;
   uint32_t cursor = 0, pend = 0, head = 0, tail = 0, iter = 0;
+  // the live window: unit and first word
+  uint32_t wu = kNoUnit, wb = 0;
   int64_t static_item = int64_t(blockIdx.x) * wpw + wid;
   bool done = false, unit_ok = false, boosted = false;
   // lane state
@@ -587,7 +622,7 @@ walk_kernel(const WalkArgs a) {
         if (ev >= EV_EXIT_TOP) {
           sel = false;
           alive = false;
-          if (!ADJ && ev == EV_EXIT_TOP && a.live_mask) mark_live(a, lunit, path);
+          if (MARK && ev == EV_EXIT_TOP) mark_live(a, lunit, path);
           if constexpr (ADJ && LAYERED) {
             exit_adjoint_layered(a, L, lslot == uint32_t(cur_slot), lslot, lunit, ev, p, v);
           } else if (lslot == uint32_t(cur_slot)) {
@@ -642,6 +677,11 @@ walk_kernel(const WalkArgs a) {
         }
         cursor = __builtin_amdgcn_readfirstlane(cursor);
         pend = __builtin_amdgcn_readfirstlane(pend);
+        if constexpr (MARK) {
+          flush_live(a, L.live, wu, wb, lane);
+          wu = done ? kNoUnit : uint32_t(u_cur);
+          wb = cursor >> 5;
+        }
       }
       if (ADJ && a.live_mask) {
         // replay only the paths the forward saw leave the top: of the next 64
@@ -737,7 +777,14 @@ walk_kernel(const WalkArgs a) {
         head += n;
       }
       if (ending) {
-        if (!ADJ && ev == EV_EXIT_TOP && a.live_mask) mark_live(a, lunit, path);
+        if (MARK && ev == EV_EXIT_TOP) {
+          const uint32_t wd = (path >> 5) - wb;
+          if (lunit == wu && wd < kLiveWindow)
+            __hip_atomic_fetch_or(L.live + wd, 1u << (path & 31u), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+          else
+            mark_live(a, lunit, path);
+        }
         if (local) {
           const uint32_t i = (tail + lane_rank(lm)) & (kExitRing - 1);
           if (!ADJ) {
@@ -752,6 +799,12 @@ walk_kernel(const WalkArgs a) {
       }
       tail += n_new;
     }
+  }
+
+  // the tail reuses the ring's area: the window goes to the mask first
+  if constexpr (MARK) {
+    flush_live(a, L.live, wu, wb, lane);
+    wu = kNoUnit;
   }
 
   // ---- tail: the paths still running after the last one was handed out ----
@@ -1149,11 +1202,14 @@ static hipError_t launch_walk_k(const WalkArgs& a, bool adjoint, int waves_per_w
                                 hipStream_t s) {
   const size_t lds = size_t(walk_lds_bytes(a, waves_per_wg));
   if (adjoint)
-    hipLaunchKernelGGL((walk_kernel<K, true, false>), dim3(grid), dim3(waves_per_wg * kWave), lds,
-                       s, a);
+    hipLaunchKernelGGL((walk_kernel<K, true, false, false>), dim3(grid),
+                       dim3(waves_per_wg * kWave), lds, s, a);
+  else if (a.live_mask)
+    hipLaunchKernelGGL((walk_kernel<K, false, false, true>), dim3(grid),
+                       dim3(waves_per_wg * kWave), lds, s, a);
   else
-    hipLaunchKernelGGL((walk_kernel<K, false, false>), dim3(grid), dim3(waves_per_wg * kWave), lds,
-                       s, a);
+    hipLaunchKernelGGL((walk_kernel<K, false, false, false>), dim3(grid),
+                       dim3(waves_per_wg * kWave), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1166,23 +1222,38 @@ hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg,
     case 4: return launch_walk_k<4>(a, adjoint, waves_per_wg, grid_wgs, stream);
     case kLayeredModel:
       if (adjoint)
-        hipLaunchKernelGGL((walk_kernel<2, true, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
-                           size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
+        hipLaunchKernelGGL((walk_kernel<2, true, true, false>), dim3(grid_wgs),
+                           dim3(waves_per_wg * kWave), size_t(walk_lds_bytes(a, waves_per_wg)),
+                           stream, a);
+      else if (a.live_mask)
+        hipLaunchKernelGGL((walk_kernel<2, false, true, true>), dim3(grid_wgs),
+                           dim3(waves_per_wg * kWave), size_t(walk_lds_bytes(a, waves_per_wg)),
+                           stream, a);
       else
-        hipLaunchKernelGGL((walk_kernel<2, false, true>), dim3(grid_wgs), dim3(waves_per_wg * kWave),
-                           size_t(walk_lds_bytes(a, waves_per_wg)), stream, a);
+        hipLaunchKernelGGL((walk_kernel<2, false, true, false>), dim3(grid_wgs),
+                           dim3(waves_per_wg * kWave), size_t(walk_lds_bytes(a, waves_per_wg)),
+                           stream, a);
       return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
 }
 
-const void* walk_kernel_ptr(int K, bool adjoint) {
+// The walk instantiation a launch uses: adjoint, or forward with (mark) or
+// without the live-path mask.
+template <int K, bool LAYERED>
+static const void* walk_ptr(bool adjoint, bool mark) {
+  if (adjoint) return reinterpret_cast<const void*>(walk_kernel<K, true, LAYERED, false>);
+  return mark ? reinterpret_cast<const void*>(walk_kernel<K, false, LAYERED, true>)
+              : reinterpret_cast<const void*>(walk_kernel<K, false, LAYERED, false>);
+}
+
+const void* walk_kernel_ptr(int K, bool adjoint, bool mark) {
   switch (K) {
-    case 1: return adjoint ? (const void*)walk_kernel<1, true, false> : (const void*)walk_kernel<1, false, false>;
-    case 2: return adjoint ? (const void*)walk_kernel<2, true, false> : (const void*)walk_kernel<2, false, false>;
-    case 3: return adjoint ? (const void*)walk_kernel<3, true, false> : (const void*)walk_kernel<3, false, false>;
-    case 4: return adjoint ? (const void*)walk_kernel<4, true, false> : (const void*)walk_kernel<4, false, false>;
-    case kLayeredModel: return adjoint ? (const void*)walk_kernel<2, true, true> : (const void*)walk_kernel<2, false, true>;
+    case 1: return walk_ptr<1, false>(adjoint, mark);
+    case 2: return walk_ptr<2, false>(adjoint, mark);
+    case 3: return walk_ptr<3, false>(adjoint, mark);
+    case 4: return walk_ptr<4, false>(adjoint, mark);
+    case kLayeredModel: return walk_ptr<2, true>(adjoint, mark);
     default: return nullptr;
   }
 }

@@ -402,7 +402,8 @@ rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_
 int occupancy_wgs(const Plan& P, int waves_per_wg) {
   int blocks = 0;
   const int lds = walk_lds_bytes(P.a, waves_per_wg);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel_ptr(P.K, P.adjoint),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel_ptr(P.K, P.adjoint,
+                                                                   P.a.live_mask != nullptr),
                                                    waves_per_wg * kWave, lds) != hipSuccess ||
       blocks < 1) {
     (void)hipGetLastError();
@@ -772,7 +773,8 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
   specs.push_back({order_scatter_kernel_ptr(), dim3(ugrid), dim3(256), 0,
                    {arg_bytes(a.map.n_units), arg_bytes(sp.bucket), arg_bytes(sp.hist),
                     arg_bytes(sp.order)}});
-  specs.push_back({walk_kernel_ptr(P.K, P.adjoint), dim3(unsigned(grid)), dim3(wpw * kWave),
+  specs.push_back({walk_kernel_ptr(P.K, P.adjoint, !P.adjoint && a.live_mask != nullptr),
+                   dim3(unsigned(grid)), dim3(wpw * kWave),
                    unsigned(walk_lds_bytes(a, wpw)), {arg_bytes(a)}});
   if (P.adjoint) {
     specs.push_back({convert_adjoint_kernel_ptr(P.K), dim3(convert_blocks(a.map.n_units)),
@@ -784,9 +786,10 @@ rw_status enqueue_graph(rw_context* ctx, Plan& P, rw_tally* out, double* grad, d
                      dim3(kConvWords * kConvGroups), 0, {arg_bytes(a)}});
   }
   char key[200];
-  std::snprintf(key, sizeof(key), "K%d adj%d grid%lld wpw%d lds%d units%lld direct%d nodes%zu",
-                P.K, int(P.adjoint), (long long)grid, wpw, walk_lds_bytes(a, wpw),
-                (long long)a.map.n_units, int(a.direct), specs.size());
+  std::snprintf(key, sizeof(key),
+                "K%d adj%d mark%d grid%lld wpw%d lds%d units%lld direct%d nodes%zu", P.K,
+                int(P.adjoint), int(!P.adjoint && a.live_mask != nullptr), (long long)grid, wpw,
+                walk_lds_bytes(a, wpw), (long long)a.map.n_units, int(a.direct), specs.size());
   return graph_launch(ctx, key, specs, s);
 }
 
