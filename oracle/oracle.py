@@ -140,12 +140,19 @@ def _bind(L):
     L.orc_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_int64, i64p, ctypes.c_uint64,
                               ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, dp, dp, i64p]
     L.orc_forward.restype = ctypes.c_int
+    L.orc_dwivedi_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_int64, i64p, ctypes.c_uint64,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double,
+                                      ctypes.c_int, dp, dp, i64p]
+    L.orc_dwivedi_forward.restype = ctypes.c_int
+    L.orc_dwivedi_nu0.argtypes = [ctypes.c_double]
+    L.orc_dwivedi_nu0.restype = ctypes.c_double
     L.orc_adjoint.argtypes = [gp, dp, dp, dp, dp, ctypes.c_int64, i64p, ctypes.c_uint64,
                               ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, dp, dp, dp, dp, dp,
                               dp]
     L.orc_adjoint.restype = ctypes.c_int
     L.orc_trace.argtypes = [gp, dp, dp, dp, dp, u32p, ctypes.c_int64, ctypes.c_int64,
-                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, dp, dp, dp]
+                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, dp, dp, dp,
+                            ctypes.c_double]
     L.orc_trace.restype = ctypes.c_int
     L.orc_layered_forward.argtypes = [gp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64, i64p,
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -238,6 +245,35 @@ def forward(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, tag: int = 0
     return tally, bins, vert
 
 
+def dwivedi_forward(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, q: float,
+                    tag: int = 0, n_threads: int | None = None, unit_base: int = 0):
+    """Raw FP64 sums per unit of the mixture walk with Dwivedi sampling
+    (technique probability q in (0, 1); see orc_dwivedi_forward).  Same layout
+    as forward()."""
+    K = geo.n_media
+    sigma_t = np.asarray(sigma_t)
+    n_units = sigma_t.size // K
+    s, a, gg, ww = (_soa(v, K, n_units) for v in (sigma_t, albedo, g, w))
+    p = _paths(paths, n_units)
+    tally = np.zeros((n_units, 8))
+    bins = np.zeros((n_units, geo.n_bins + 2, 2))
+    vert = np.zeros(n_units, dtype=np.int64)
+    cg = geo.c()
+    rc = lib().orc_dwivedi_forward(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(ww),
+                                   n_units, _i64ptr(p), seed, tag, unit_base, float(q),
+                                   n_threads or default_threads(), _dptr(tally), _dptr(bins),
+                                   _i64ptr(vert))
+    if rc != 0:
+        raise ValueError(f"orc_dwivedi_forward failed with code {rc}")
+    return tally, bins, vert
+
+
+def dwivedi_nu0(alpha: float) -> float:
+    """nu0 of the Dwivedi walk for a single-scattering albedo (clamped to
+    [0.3, 1 - 1e-7])."""
+    return float(lib().orc_dwivedi_nu0(float(alpha)))
+
+
 def adjoint(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, cot_R=None, cot_bins=None,
             tag: int = 0, n_threads: int | None = None, jacobian: bool = False,
             unit_base: int = 0):
@@ -272,9 +308,10 @@ def adjoint(geo: Geometry, sigma_t, albedo, g, w, paths, seed: int, cot_R=None, 
 
 def trace(geo: Geometry, sigma_t, albedo, g, w, words=None, n_paths: int | None = None,
           n_blocks: int = 64, seed: int = 0, unit: int = 0, tag: int = 0,
-          with_events: bool = True):
+          with_events: bool = True, dwivedi_q: float = 0.0):
     """Per-path replay of one unit.  words: uint32 [n_paths, n_blocks, 4] or None
-    (Philox).  Returns (events [n_paths, n_blocks, 8], path_out [n_paths, 8],
+    (Philox).  dwivedi_q > 0: the Dwivedi walk with that technique probability.
+    Returns (events [n_paths, n_blocks, 8], path_out [n_paths, 8],
     path_adj [n_paths, 2])."""
     K = geo.n_media
     s, a, gg, ww = (np.ascontiguousarray(np.asarray(v, np.float64).reshape(K))
@@ -289,7 +326,8 @@ def trace(geo: Geometry, sigma_t, albedo, g, w, words=None, n_paths: int | None 
     cg = geo.c()
     rc = lib().orc_trace(ctypes.byref(cg), _dptr(s), _dptr(a), _dptr(gg), _dptr(ww),
                          _u32ptr(words) if words is not None else None, n_paths, n_blocks, seed,
-                         unit, tag, _dptr(ev) if ev is not None else None, _dptr(out), _dptr(adj))
+                         unit, tag, _dptr(ev) if ev is not None else None, _dptr(out), _dptr(adj),
+                         float(dwivedi_q))
     if rc != 0:
         raise ValueError(f"orc_trace failed with code {rc}")
     return ev, out, adj

@@ -51,6 +51,12 @@
  * layer (the path density factorises over the vertices, and each factor
  * depends on one layer's parameters only).
  *
+ * Dwivedi sampling (the variance reduction the paper names beside hero
+ * wavelengths in Sec. 2; the zero-variance-based scheme of Krivanek and
+ * d'Eon, "A zero-variance-based sampling scheme for Monte Carlo subsurface
+ * scattering", SIGGRAPH 2014 Talks, after Dwivedi 1982) runs as a variant of
+ * the mixture walk: see dwivedi_nu0() and walk() for its readings.
+ *
  * Everything is FP64.  Threads split the paths of a unit into fixed ranges;
  * partial sums are merged in range order, so results do not depend on the
  * thread count.
@@ -232,12 +238,73 @@ static int bin_slot(double r, const orc_geometry* g) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Dwivedi sampling                                                            */
+/* ------------------------------------------------------------------------- */
+/* Readings (Krivanek and d'Eon 2014; the paper only names the technique):
+ *   - mu_s = -d_z, the cosine of a direction with the outward normal of the
+ *     top surface (positive towards the surface);
+ *   - nu0(alpha) > 1 is the root of alpha nu atanh(1/nu) = 1, the decay
+ *     constant of the asymptotic (diffusion-regime) solution of isotropic
+ *     transport in a half-space; computed from the single-scattering albedo
+ *     clamped to [DW_ALB_MIN, DW_ALB_MAX] (the estimator stays unbiased for
+ *     every nu0 > 1; the clamp only keeps the pdf below representable);
+ *   - Dwivedi direction pdf (per steradian) p_D = 1 / (2 pi lam (nu0 - mu_s)),
+ *     lam = ln((nu0 + 1) / (nu0 - 1)), sampled by inverting its CDF:
+ *     mu_s = nu0 - (nu0 + 1) exp(-u1 lam), azimuth 2 pi u2 about the normal;
+ *   - with it the flight is sampled against sigma' = sigma_t (1 - mu_s / nu0)
+ *     (longer flights towards the surface, shorter away from it);
+ *   - at every scattering one of two techniques is chosen: Dwivedi
+ *     (direction and flight as above) with probability q, else the plain walk
+ *     (Henyey-Greenstein direction, flight against sigma_t); the technique
+ *     uniform comes from the low 9 bits of the vertex's fourth word, which the
+ *     roulette and Fresnel uniform (its top 23 bits) does not use;
+ *   - one-sample MIS with the balance heuristic: at the end of that flight the
+ *     weight is multiplied by the true density of (direction, flight) over
+ *     the two techniques' mixture,
+ *       p_HG T / (q p_D T' + (1 - q) p_HG T),
+ *     T = sigma_t e^{-sigma_t s}, T' = sigma' e^{-sigma' s} for a collision
+ *     after s, and T = e^{-sigma_t l}, T' = e^{-sigma' l} for a flight that
+ *     reaches a surface after l; so each factor is at most 1 / (1 - q);
+ *   - the entry flight and flights after a surface reflection are plain
+ *     (their direction is not sampled) and keep their weight. */
+#define DW_ALB_MIN 0.3
+#define DW_ALB_MAX (1.0 - 1e-7)
+
+/* nu0 of the albedo, by bisection on x = 1/nu in (0, 1), where
+ * atanh(x) / x rises from 1 to infinity */
+static double dwivedi_nu0(double alpha) {
+  const double a = fmin(fmax(alpha, DW_ALB_MIN), DW_ALB_MAX);
+  double lo = 0.0, hi = 1.0;
+  for (int i = 0; i < 200; ++i) {
+    const double x = 0.5 * (lo + hi);
+    if (x <= lo || x >= hi) break;
+    const double f = atanh(x) / x;
+    if (a * f < 1.0) lo = x;
+    else hi = x;
+  }
+  return 2.0 / (lo + hi);
+}
+
+/* Henyey-Greenstein phase function per steradian at cos(theta) = c */
+static double hg_pdf(double g, double c) {
+  const double b = 1.0 + g * g - 2.0 * g * c;
+  return (1.0 - g * g) / (4.0 * M_PI * b * sqrt(b));
+}
+
+/* Dwivedi direction pdf per steradian at mu_s */
+static double dwivedi_pdf(double nu0, double lam, double mu_s) {
+  return 1.0 / (2.0 * M_PI * lam * (nu0 - mu_s));
+}
+
+/* ------------------------------------------------------------------------- */
 /* One path                                                                    */
 /* ------------------------------------------------------------------------- */
 typedef struct {
   int K;
   double sigma_t[ORC_MAX_K], albedo[ORC_MAX_K], g[ORC_MAX_K], w[ORC_MAX_K];
   double cum[ORC_MAX_K];
+  /* Dwivedi walk: nu0 of each medium and ln((nu0 + 1) / (nu0 - 1)) */
+  double nu0[ORC_MAX_K], lam[ORC_MAX_K];
 } unit_params;
 
 typedef struct {
@@ -266,8 +333,10 @@ typedef struct {
   double Sg_l[2];
 } path_result;
 
-/* fetch block v; returns 0 when an injected source has run out */
-static int get_block(const block_source* src, int64_t v, double u[4]) {
+/* fetch block v; returns 0 when an injected source has run out.  w3, when
+ * not NULL, receives the raw fourth word (its low 9 bits, which u01 drops,
+ * choose the sampling technique of the Dwivedi walk) */
+static int get_block_w(const block_source* src, int64_t v, double u[4], uint32_t* w3) {
   uint32_t w[4];
   if (v >= src->n_blocks) return 0;
   if (src->words) {
@@ -277,7 +346,12 @@ static int get_block(const block_source* src, int64_t v, double u[4]) {
     philox4x32_10(ctr, src->key, w);
   }
   for (int i = 0; i < 4; ++i) u[i] = u01(w[i]);
+  if (w3) *w3 = w[3];
   return 1;
+}
+
+static int get_block(const block_source* src, int64_t v, double u[4]) {
+  return get_block_w(src, v, u, NULL);
 }
 
 static void put_event(double* ev, int64_t max_ev, int64_t idx, int code,
@@ -317,12 +391,11 @@ static int enter(const orc_geometry* geo, double n, const double u[4], double d[
   return 0;
 }
 
-/* A collision with a medium of albedo alb and anisotropy g: absorption
- * (implicit capture with Russian roulette, or the analog survival test), then
- * Henyey-Greenstein scattering of the direction d.  Returns END_NONE when the
- * path goes on, else how it ended. */
-static int collide(const orc_geometry* geo, double alb, double g, const double u[4], double d[3],
-                   double* Wp, path_result* res) {
+/* Absorption at a collision with a medium of albedo alb: implicit capture
+ * with Russian roulette, or the analog survival test.  Returns END_NONE when
+ * the path goes on, else how it ended. */
+static int absorb(const orc_geometry* geo, double alb, const double u[4], double* Wp,
+                  path_result* res) {
   double W = *Wp;
   res->n_coll += 1;
   if (geo->analog) {
@@ -343,18 +416,69 @@ static int collide(const orc_geometry* geo, double alb, double g, const double u
     }
   }
   *Wp = W;
-  double mu = hg_cos(g, u[1]);
-  res->Sg += hg_dlog_dg(g, mu);
+  return END_NONE;
+}
+
+/* A collision with a medium of albedo alb and anisotropy g: absorption, then
+ * Henyey-Greenstein scattering of the direction d.  Returns END_NONE when the
+ * path goes on, else how it ended. */
+/* Henyey-Greenstein scattering of d by the words u1 (cosine) and u2
+ * (azimuth); returns the cosine */
+static double hg_scatter(double g, const double u[4], double d[3]) {
+  const double mu = hg_cos(g, u[1]);
   scatter_dir(d, mu, 2.0 * M_PI * u[2]);
+  return mu;
+}
+
+static int collide(const orc_geometry* geo, double alb, double g, const double u[4], double d[3],
+                   double* Wp, path_result* res) {
+  const int end = absorb(geo, alb, u, Wp, res);
+  if (end != END_NONE) return end;
+  const double mu = hg_scatter(g, u, d);
+  res->Sg += hg_dlog_dg(g, mu);
+  return END_NONE;
+}
+
+/* One path of the mixture walk.  dw_q > 0: Dwivedi sampling with technique
+ * probability dw_q (the readings above; up->nu0/lam set); dw_q = 0: the plain
+ * walk. */
+/* A collision of the Dwivedi walk: implicit capture and roulette as in
+ * collide(), then the technique choice and the new direction with the two
+ * techniques' densities of it and the flight extinction sig_d of the next
+ * flight (used when *dw). */
+static int dwivedi_collide(const orc_geometry* geo, const unit_params* up, int k, double q,
+                           const double u[4], uint32_t w3, double d[3], double* Wp,
+                           path_result* res, int* dw, double* p_hg, double* p_d, double* mu_s,
+                           double* sig_d) {
+  const double g = up->g[k], nu0 = up->nu0[k], lam = up->lam[k];
+  const int end = absorb(geo, up->albedo[k], u, Wp, res);
+  if (end != END_NONE) return end;
+  const double ut = ((double)(w3 & 0x1FFu) + 0.5) / 512.0;
+  *dw = ut < q;
+  if (*dw) {
+    const double m = nu0 - (nu0 + 1.0) * exp(-u[1] * lam);
+    const double phi = 2.0 * M_PI * u[2];
+    const double st = sqrt(fmax(0.0, 1.0 - m * m));
+    const double nd[3] = {st * cos(phi), st * sin(phi), -m};
+    const double c = nd[0] * d[0] + nd[1] * d[1] + nd[2] * d[2];
+    *p_hg = hg_pdf(g, c);
+    d[0] = nd[0]; d[1] = nd[1]; d[2] = nd[2];
+  } else {
+    *p_hg = hg_pdf(g, hg_scatter(g, u, d));
+  }
+  *mu_s = -d[2];
+  *p_d = dwivedi_pdf(nu0, lam, *mu_s);
+  *sig_d = up->sigma_t[k] * (1.0 - *mu_s / nu0);
   return END_NONE;
 }
 
 static void walk(const unit_params* up, const orc_geometry* geo,
                  const block_source* src, path_result* res,
-                 double* events, int64_t max_events) {
+                 double* events, int64_t max_events, double dw_q) {
   const double n = geo->n_rel;
   const int slab = geo->slab_mm > 0.0;
   double u[4];
+  uint32_t w3 = 0;
   memset(res, 0, sizeof(*res));
   res->slot = -1;
 
@@ -366,6 +490,11 @@ static void walk(const unit_params* up, const orc_geometry* geo,
   }
   res->k = k;
   const double sig = up->sigma_t[k], alb = up->albedo[k], g = up->g[k];
+  /* Dwivedi state of the current flight: mixed = its direction was sampled
+   * (0 for the entry and after a reflection); dw = by the Dwivedi technique;
+   * p_hg, p_d = both techniques' densities of that direction; mu_s, sig_d */
+  int mixed = 0, dw = 0;
+  double p_hg = 0.0, p_d = 0.0, mu_s = 0.0, sig_d = sig;
 
   double p[3] = {0.0, 0.0, 0.0};
   double d[3];
@@ -383,9 +512,9 @@ static void walk(const unit_params* up, const orc_geometry* geo,
       put_event(events, max_events, v, EV_CAP, p, d, W);
       return;
     }
-    if (!get_block(src, v, u)) { res->end = END_NO_BLOCKS; return; }
+    if (!get_block_w(src, v, u, &w3)) { res->end = END_NO_BLOCKS; return; }
     res->n_vert = v;
-    double s = -log(u[0]) / sig;
+    double s = -log(u[0]) / (dw ? sig_d : sig);
 
     /* boundary crossings along this flight */
     int hit = 0; /* 1 top, 2 bottom */
@@ -403,6 +532,12 @@ static void walk(const unit_params* up, const orc_geometry* geo,
       p[0] += db * d[0];
       p[1] += db * d[1];
       p[2] = (hit == 1) ? 0.0 : geo->slab_mm;
+      if (mixed) {
+        /* the flight passed db: e^{-sigma_t db} over the mixture */
+        W *= p_hg / (dw_q * p_d * exp(sig * mu_s * db / up->nu0[k]) + (1.0 - dw_q) * p_hg);
+        mixed = 0;
+        dw = 0;
+      }
       double F = fresnel(fabs(d[2]), n);
       if (u[3] < F) {
         reflect(d);
@@ -425,6 +560,23 @@ static void walk(const unit_params* up, const orc_geometry* geo,
     /* collision */
     res->L += s;
     for (int i = 0; i < 3; ++i) p[i] += s * d[i];
+    if (mixed) {
+      /* a collision after s: sigma_t e^{-sigma_t s} over the mixture */
+      W *= p_hg / (dw_q * p_d * (sig_d / sig) * exp(sig * mu_s * s / up->nu0[k]) +
+                   (1.0 - dw_q) * p_hg);
+    }
+    if (dw_q > 0.0) {
+      const int end = dwivedi_collide(geo, up, k, dw_q, u, w3, d, &W, res, &dw, &p_hg, &p_d,
+                                      &mu_s, &sig_d);
+      mixed = 1;
+      if (end != END_NONE) {
+        res->end = end;
+        put_event(events, max_events, v, EV_RR_KILL, p, d, 0.0);
+        return;
+      }
+      put_event(events, max_events, v, EV_COLLIDE, p, d, W);
+      continue;
+    }
     const int end = collide(geo, alb, g, u, d, &W, res);
     if (end != END_NONE) {
       res->end = end;
@@ -673,6 +825,8 @@ typedef struct {
   /* hero-wavelength walk: groups of `hero` consecutive units (0: off); the
    * task table then runs over groups */
   int hero;
+  /* Dwivedi walk: technique probability q (0: the plain walk) */
+  double dwivedi;
   /* adjoint inputs (NULL for the forward) */
   int adjoint;
   const double* cot_R;
@@ -707,6 +861,10 @@ static int load_unit(const job_t* job, int64_t u, unit_params* up) {
     if (!(up->sigma_t[k] > 0.0) || !(up->albedo[k] >= 0.0) || !(up->albedo[k] <= 1.0) ||
         !(fabs(up->g[k]) < 1.0) || !(up->w[k] >= 0.0))
       return -1;
+    if (job->dwivedi > 0.0) {
+      up->nu0[k] = dwivedi_nu0(up->albedo[k]);
+      up->lam[k] = log((up->nu0[k] + 1.0) / (up->nu0[k] - 1.0));
+    }
   }
   if (!(fabs(acc - 1.0) <= 1e-5)) return -1;
   return 0;
@@ -765,7 +923,7 @@ static void run_task(job_t* job, int64_t t) {
     path_result r;
     src.path = (uint32_t)pth;
     if (job->layered) walk_layers(&lp, geo, &src, &r, NULL, 0, NULL);
-    else walk(&up, geo, &src, &r, NULL, 0);
+    else walk(&up, geo, &src, &r, NULL, 0, job->dwivedi);
     int tallied_top = (r.end == END_EXIT_TOP) &&
                       (geo->order_filter <= 0 || r.n_coll == geo->order_filter);
     if (!job->adjoint) {
@@ -993,6 +1151,46 @@ int orc_forward(const orc_geometry* geo, const double* sigma_t, const double* al
   return rc;
 }
 
+/* The forward of the mixture walk with Dwivedi sampling (technique
+ * probability 0 < q < 1; see the readings above dwivedi_nu0).  Same tallies
+ * and layout as orc_forward; the weights of the exiting paths now vary from
+ * path to path.  Normal incidence, implicit capture only (no analog mode).
+ * Returns as orc_forward. */
+int orc_dwivedi_forward(const orc_geometry* geo, const double* sigma_t, const double* albedo,
+                        const double* g, const double* w, int64_t n_units, const int64_t* paths,
+                        uint64_t seed, uint32_t tag, uint32_t unit_base, double q, int n_threads,
+                        double* tally, double* bins, int64_t* vertices) {
+  if (check_geometry(geo) || geo->analog || geo->incidence != 0 || !(q > 0.0) || !(q <= 1.0) ||
+      !sigma_t || !albedo || !g || !w || !paths || n_units < 0 || !tally || !bins || !vertices)
+    return -1;
+  const int nb = geo->n_bins;
+  job_t job;
+  memset(&job, 0, sizeof(job));
+  job.geo = geo; job.K = geo->n_media;
+  job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
+  job.n_units = n_units; job.paths = paths; job.seed = seed; job.tag = tag;
+  job.unit_base = unit_base;
+  job.dwivedi = q;
+  job.part_len = T_NSLOTS + (int64_t)(nb + 2) * 2 + 1;
+  int rc = run_job(&job, n_threads);
+  if (rc == -1 || rc == -2) return rc;
+  memset(tally, 0, sizeof(double) * (size_t)n_units * T_NSLOTS);
+  memset(bins, 0, sizeof(double) * (size_t)n_units * (size_t)(nb + 2) * 2);
+  for (int64_t u = 0; u < n_units; ++u) vertices[u] = 0;
+  for (int64_t t = 0; t < job.n_tasks; ++t) {
+    int64_t u = job.task_unit[t];
+    const double* part = job.part + t * job.part_len;
+    for (int i = 0; i < T_NSLOTS; ++i) tally[u * T_NSLOTS + i] += part[i];
+    for (int i = 0; i < (nb + 2) * 2; ++i) bins[u * (nb + 2) * 2 + i] += part[T_NSLOTS + i];
+    vertices[u] += (int64_t)part[T_NSLOTS + (nb + 2) * 2];
+  }
+  free_job(&job);
+  return rc;
+}
+
+/* nu0 of an albedo (the Dwivedi walk's constant), for tests */
+double orc_dwivedi_nu0(double alpha) { return dwivedi_nu0(alpha); }
+
 /* Score-function gradient of the cotangent-weighted top tallies:
  *   grad[u][j] = sum over paths of x * (cot_R[u] + cot_bins[u][slot]) * score_j
  * with score layout [sigma_t(K) | albedo(K) | g(K) | logits(K)] (logits of a
@@ -1056,14 +1254,16 @@ int orc_adjoint(const orc_geometry* geo, const double* sigma_t, const double* al
 int orc_trace(const orc_geometry* geo, const double* sigma_t, const double* albedo,
               const double* g, const double* w, const uint32_t* words, int64_t n_paths,
               int64_t n_blocks, uint64_t seed, uint32_t unit, uint32_t tag, double* events,
-              double* path_out, double* path_adj) {
+              double* path_out, double* path_adj, double dw_q) {
   if (check_geometry(geo) || !sigma_t || !albedo || !g || !w || n_paths < 0 ||
-      n_blocks < 1 || !path_out)
+      n_blocks < 1 || !path_out || !(dw_q >= 0.0) || !(dw_q <= 1.0) ||
+      (dw_q > 0.0 && (geo->analog || geo->incidence != 0)))
     return -1;
   job_t job;
   memset(&job, 0, sizeof(job));
   job.K = geo->n_media; job.n_units = 1;
   job.sigma_t = sigma_t; job.albedo = albedo; job.g = g; job.w = w;
+  job.dwivedi = dw_q;
   unit_params up;
   if (load_unit(&job, 0, &up) != 0) return -3;
   if (events) memset(events, 0, sizeof(double) * (size_t)n_paths * (size_t)n_blocks * 8);
@@ -1078,7 +1278,7 @@ int orc_trace(const orc_geometry* geo, const double* sigma_t, const double* albe
     src.n_blocks = n_blocks;
     if (words) src.words = words + p * n_blocks * 4;
     path_result r;
-    walk(&up, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks);
+    walk(&up, geo, &src, &r, events ? events + p * n_blocks * 8 : NULL, n_blocks, dw_q);
     double* o = path_out + p * 8;
     o[0] = r.end; o[1] = r.k; o[2] = r.slot; o[3] = r.x; o[4] = r.r;
     o[5] = (double)r.n_vert; o[6] = (double)r.n_coll; o[7] = r.absorbed;

@@ -53,6 +53,7 @@ ORDER = ["energy", "special", "plane", "beer", "mixture", "single_scatter", "ana
          "analog_cosine", "layers_trace", "layers_beer", "layers_plane", "layers_absorbing_top",
          "layers_adj_absorbing_top",
          "layers_stack", "layers_analog", "hero_reductions", "hero_closed_forms",
+         "dwivedi_nu0", "dwivedi_telescope", "dwivedi_vs_plain", "dwivedi_closed_forms",
          "adding_doubling"]
 
 

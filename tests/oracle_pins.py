@@ -36,6 +36,15 @@ What pins what:
                      cosine incidence, with and without total internal
                      reflection at the interface); analog and weighted agree;
                      traces obey Snell's law at every crossing
+  Dwivedi walk     - nu0 against a library root finder and its diffusion
+                     limit; in isotropic index-matched media with technique
+                     probability 1 every exit weight equals its closed form
+                     alpha e^(-sigma_t z1 / nu0) lam (nu0 - mu_exit) / 2 (the
+                     weights telescope); R against Chandrasekhar's closed
+                     form (probabilities 1 and 0.5) and, with anisotropy and
+                     a Fresnel surface, against adding-doubling; an isotropic
+                     three-medium mixture agrees with the plain walk in R and
+                     the radial histogram
 """
 from __future__ import annotations
 
@@ -733,6 +742,94 @@ def check_adding_doubling(paths=1 << 18, seed=30, k=3.0):
     return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
 
 
+def check_dwivedi_nu0():
+    """nu0 (root > 1 of alpha nu atanh(1/nu) = 1) against scipy's brentq on the
+    same equation, its diffusion limit nu0 sqrt(3 (1 - alpha)) -> 1, and the
+    clamp of the albedo to [0.3, 1 - 1e-7]."""
+    from scipy import optimize
+
+    errs = []
+    for al in (0.3, 0.5, 0.7, 0.9, 0.99, 0.999):
+        ref = optimize.brentq(lambda v: al * v * math.atanh(1.0 / v) - 1.0, 1.0 + 1e-14, 1e7,
+                              xtol=1e-15, rtol=1e-15)
+        errs.append(abs(O.dwivedi_nu0(al) / ref - 1.0))
+    lim = O.dwivedi_nu0(0.99999) * math.sqrt(3 * 1e-5)
+    clamp = O.dwivedi_nu0(0.1) == O.dwivedi_nu0(0.3)
+    ok = max(errs) < 1e-12 and abs(lim - 1.0) < 1e-3 and clamp
+    return _r(ok, f"rel errs {max(errs):.1e} limit {lim:.6f} clamp {clamp}")
+
+
+def check_dwivedi_weights_telescope(n_paths=1500, seed=31):
+    """Isotropic, index-matched, technique probability 1: the weight factor of
+    a collision is alpha lam nu0 / 2 e^(sigma_t dz / nu0) = e^(sigma_t dz / nu0)
+    (nu0's equation), so an exiting path carries exactly
+    alpha e^(-sigma_t z1 / nu0) lam (nu0 - mu_exit) / 2, z1 the depth of its
+    first collision (the entry flight is plain), mu_exit the cosine of its exit
+    direction with the outward normal."""
+    worst, n_exit = 0.0, 0
+    for al, sig in ((0.99, 2.0), (0.8, 0.7)):
+        nu = O.dwivedi_nu0(al)
+        lam = math.log((nu + 1.0) / (nu - 1.0))
+        geo = O.Geometry(n_media=1, n_rel=1.0)
+        ev, out, _ = O.trace(geo, [sig], [al], [0.0], [1.0], n_paths=n_paths, n_blocks=2048,
+                             seed=seed, dwivedi_q=1.0)
+        for p in np.where(out[:, 0] == 1)[0]:
+            nv = int(out[p, 5])
+            if nv < 2:
+                continue
+            pred = al * math.exp(-sig * ev[p, 1, 3] / nu) * lam * (nu + ev[p, nv, 6]) / 2.0
+            worst = max(worst, abs(out[p, 3] / pred - 1.0))
+            n_exit += 1
+    return _r(worst < 1e-10 and n_exit > n_paths, f"worst rel {worst:.1e} over {n_exit} exits")
+
+
+def check_dwivedi_closed_forms(paths=1 << 17, seed=32, k=3.5):
+    """The Dwivedi walk is unbiased: (i) isotropic index-matched half-spaces
+    against Chandrasekhar's 1 - H(1) sqrt(1 - alpha), technique probability 1
+    and 0.5; (ii) anisotropic media, some with a Fresnel surface, against
+    adding-doubling (probabilities 0.3-1)."""
+    from oracle import adding_doubling as AD
+
+    zs = []
+    geo = O.Geometry(n_media=1, n_rel=1.0)
+    al = np.array([0.5, 0.9, 0.99])
+    for q in (1.0, 0.5):
+        tal, _, _ = O.dwivedi_forward(geo, np.ones(3), al, np.zeros(3), np.ones(3), paths, seed, q)
+        m, se = mean_se(tal[:, 0], tal[:, 1], paths)
+        zs += list((m - np.array([cf.R_plane(a) for a in al])) / se)
+    for a, g, n, q in ((0.7, 0.5, 1.4, 0.5), (0.9, 0.3, 1.4, 0.3), (0.6, -0.3, 1.0, 1.0)):
+        geo = O.Geometry(n_media=1, n_rel=n)
+        tal, _, _ = O.dwivedi_forward(geo, [2.0], [a], [g], [1.0], paths, seed + 1, q)
+        m, se = mean_se(tal[0, 0], tal[0, 1], paths)
+        zs.append((m - AD.R_semi_infinite(a, g, n, "normal")) / se)
+    return _r(all(abs(z) <= k for z in zs), f"z={np.round(zs, 2)}")
+
+
+def check_dwivedi_vs_plain(paths=1 << 17, seed=33, k=3.5):
+    """An isotropic three-medium mixture under a Fresnel surface (n = 1.4):
+    the Dwivedi walk (probability 1) and the plain walk estimate the same R and
+    radial histogram (independent streams; combined standard errors)."""
+    K = 3
+    geo = O.Geometry(n_media=K, n_rel=1.4, n_bins=32, r_min_mm=1e-2, r_max_mm=20.0)
+    s = np.array([[0.5, 3.0], [4.0, 1.0], [20.0, 8.0]])
+    a = np.array([[0.95, 0.7], [0.999, 0.9], [0.6, 0.99]])
+    g = np.zeros((K, 2))
+    w = np.array([[0.2, 0.5], [0.5, 0.3], [0.3, 0.2]])
+    td, bd, _ = O.dwivedi_forward(geo, s, a, g, w, paths, seed, 1.0)
+    tp, bp, _ = O.forward(geo, s, a, g, w, paths, seed + 1)
+    md, sd = mean_se(td[:, 0], td[:, 1], paths)
+    mp, sp = mean_se(tp[:, 0], tp[:, 1], paths)
+    z = (md - mp) / np.hypot(sd, sp)
+    ok = bool(np.all(np.abs(z) <= k))
+    for u in range(2):
+        m1, s1 = mean_se(bd[u, :, 0], bd[u, :, 1], paths)
+        m2, s2 = mean_se(bp[u, :, 0], bp[u, :, 1], paths)
+        zb = histogram_z(m1, s1, m2, s2, mask=(m1 > 0) & (m2 > 0))
+        hok, chi2, lim = accept_histogram(zb)
+        ok = ok and hok
+    return _r(ok, f"z={np.round(z, 2)}")
+
+
 BATTERY_SMALL = [
     ("plane", lambda: check_plane_albedo(alphas=(0.5, 0.9), paths=1 << 16, k=4.0)),
     ("second_moment", lambda: check_second_moment(paths=1 << 16, k=4.0)),
@@ -761,4 +858,8 @@ BATTERY_SMALL = [
     ("adding_doubling", lambda: check_adding_doubling(paths=1 << 16, k=4.0)),
     ("hero_reductions", lambda: check_hero_reduces_to_the_plain_walk(paths=1 << 11)),
     ("hero_closed_forms", lambda: check_hero_against_closed_forms(paths=1 << 16, k=4.0)),
+    ("dwivedi_nu0", check_dwivedi_nu0),
+    ("dwivedi_telescope", lambda: check_dwivedi_weights_telescope(n_paths=300)),
+    ("dwivedi_closed_forms", lambda: check_dwivedi_closed_forms(paths=1 << 15, k=4.0)),
+    ("dwivedi_vs_plain", lambda: check_dwivedi_vs_plain(paths=1 << 15, k=4.0)),
 ]

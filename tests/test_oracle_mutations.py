@@ -32,7 +32,8 @@ MUTATIONS = [
      "return 3.0 * (mu - g)"),
     ("frame_sign", "t2[2] = -d[1];", "t2[2] = d[1];"),
     ("azimuth_sin_cos", "b = st * sin(phi);", "b = st * cos(phi);"),
-    ("free_flight_scale", "double s = -log(u[0]) / sig;", "double s = -log(u[0]) * sig;"),
+    ("free_flight_scale", "double s = -log(u[0]) / (dw ? sig_d : sig);",
+     "double s = -log(u[0]) * (dw ? sig_d : sig);"),
     ("boundary_distance_sign", "db = -p[2] / d[2];", "db = p[2] / d[2];"),
     ("no_absorption", "W *= alb;", "W *= 1.0;"),
     ("absorbed_after_update", "res->absorbed += W * (1.0 - alb);\n    W *= alb;",
@@ -82,6 +83,20 @@ MUTATIONS = [
     ("hero_weight_with_hero_albedo", "hw->x[i] *= hw->lps[i].albedo[layer];",
      "hw->x[i] *= hw->lps[hw->hero].albedo[layer];"),
     ("hero_never_rotates", "const int hero = (int)(pth % C);", "const int hero = 0;"),
+    ("dwivedi_flight_sign", "*sig_d = up->sigma_t[k] * (1.0 - *mu_s / nu0);",
+     "*sig_d = up->sigma_t[k] * (1.0 + *mu_s / nu0);"),
+    ("dwivedi_pdf_no_2pi", "return 1.0 / (2.0 * M_PI * lam * (nu0 - mu_s));",
+     "return 1.0 / (lam * (nu0 - mu_s));"),
+    ("dwivedi_flight_density_inverted", "(sig_d / sig)", "(sig / sig_d)"),
+    ("dwivedi_surface_exp_sign", "exp(sig * mu_s * db / up->nu0[k])",
+     "exp(-sig * mu_s * db / up->nu0[k])"),
+    ("dwivedi_surface_weight_dropped", "W *= p_hg / (dw_q * p_d * exp(sig * mu_s * db",
+     "W = W + 0.0 * p_hg / (dw_q * p_d * exp(sig * mu_s * db"),
+    ("dwivedi_inverse_cdf", "const double m = nu0 - (nu0 + 1.0) * exp(-u[1] * lam);",
+     "const double m = nu0 - (nu0 - 1.0) * exp(-u[1] * lam);"),
+    ("dwivedi_hg_cosine_wrong", "const double c = nd[0] * d[0] + nd[1] * d[1] + nd[2] * d[2];",
+     "const double c = nd[2];"),
+    ("dwivedi_nu0_bisection", "if (a * f < 1.0) lo = x;", "if (a * f > 1.0) lo = x;"),
 ]
 
 

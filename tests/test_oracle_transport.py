@@ -225,3 +225,19 @@ def test_hero_wavelength_groups_reduce_to_the_plain_walk():
 
 def test_hero_wavelength_members_match_closed_forms():
     _assert(P.check_hero_against_closed_forms())
+
+
+def test_dwivedi_nu0_against_a_root_finder_and_its_limit():
+    _assert(P.check_dwivedi_nu0())
+
+
+def test_dwivedi_exit_weights_telescope_in_isotropic_media():
+    _assert(P.check_dwivedi_weights_telescope())
+
+
+def test_dwivedi_walk_matches_closed_forms():
+    _assert(P.check_dwivedi_closed_forms())
+
+
+def test_dwivedi_walk_agrees_with_the_plain_walk():
+    _assert(P.check_dwivedi_vs_plain())
