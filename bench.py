@@ -27,7 +27,10 @@ at 4,096 paths (one persistent launch) against one plain static launch over
 the same units, and its per-set plain launches timed on a subset of sets; the
 adjoint sweep (1,024 sets x 81 wavelengths x 2^14 paths, random bin
 cotangents); the inverse fit (4,096 targets x 81 wavelengths, 200 Adam steps
-at 2^12 paths, by the adjoint and by the LUT route); the autotuned step; the roofline of the dominant kernel (ALU-bound: VALU issue
+at 2^12 paths, by the adjoint and by the LUT route); hero wavelengths on the
+two-layer tones and Dwivedi sampling (on the tiny workload's isotropic media
+and on the 81-wavelength mixture), each as an efficiency gain over the plain
+walk; the autotuned step; the roofline of the dominant kernel (ALU-bound: VALU issue
 slots per vertex x vertices / measured kernel time, against the issue peak of
 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
@@ -228,6 +231,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-hero", action="store_true")
+    ap.add_argument("--no-dwivedi", action="store_true")
+    ap.add_argument("--dwivedi-paths", type=int, default=1 << 20)
     ap.add_argument("--hero-tones", type=int, default=64)
     ap.add_argument("--hero-photons", type=int, default=1 << 16)
     ap.add_argument("--c5-targets", type=int, default=4096)
@@ -462,6 +467,8 @@ def main():
         out["adjoint_sweep"] = c4(ctx, rw, workloads, torch, args)
     if not args.no_hero:
         out["hero_wavelengths"] = hero_leg(ctx, rw, api, workloads, torch, args)
+    if not args.no_dwivedi:
+        out["dwivedi"] = dwivedi_leg(ctx, rw, api, workloads, torch, args)
     if not args.no_c5:
         out["inverse_fit"] = c5(torch, args)
     if not args.no_cpu_baseline:
@@ -548,6 +555,53 @@ def hero_leg(ctx, rw, api, workloads, torch, args):
                             "efficiency_gain_median": float(np.median(gain)),
                             "efficiency_gain_p10_p90": [float(np.quantile(gain, 0.1)),
                                                         float(np.quantile(gain, 0.9))]}
+    return res
+
+
+def dwivedi_leg(ctx, rw, api, workloads, torch, args):
+    """Dwivedi sampling (rw_dwivedi_forward) against the plain batched walk at
+    the same paths per unit: on the tiny workload's isotropic, index-matched
+    half-spaces (16 albedos in [0.5, 0.99], sigma_t = 1) with technique
+    probability 1, and on the 81-wavelength mixture (anisotropic, Fresnel
+    n = 1.4) with probability 0.2.  Per form: the launch time, the walked
+    vertices, per unit the efficiency gain (SE^2 x time of the plain walk over
+    that of the Dwivedi walk), median and 10-90 % range, and the z-scores of
+    the two estimates of R (heavy-tailed weights show as a low bias there: the
+    sample SE then understates the error)."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        e0.record(s)
+        r = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    res = {}
+    for name, wl, q in (("isotropic_half_spaces", workloads.config1(paths=args.dwivedi_paths), 1.0),
+                        ("mixture3_81wl", workloads.config2(paths=args.dwivedi_paths), 0.2)):
+        m = rw.Media.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.weight, wl.n_units, 1)
+        geom = rw.Geometry(n_media=wl.n_media, n_rel=wl.n_rel, n_bins=wl.n_bins)
+        N = wl.paths_per_unit
+        plain, t_p = timed(lambda: api.forward(ctx, m, geom, N, 21, stream=s))
+        dw, t_d = timed(lambda: api.dwivedi_forward(ctx, m, geom, N, 21, q, stream=s))
+        assert rw.rw_check(ctx, dw.tally.flags) == 0
+        se_p = plain.R_se.cpu().numpy()
+        se_d = dw.R_se.cpu().numpy()
+        gain = (se_p ** 2 * t_p) / (se_d ** 2 * t_d)
+        z = (dw.R - plain.R).cpu().numpy() / np.hypot(se_p, se_d)
+        res[name] = {"units": wl.n_units, "paths_per_unit": N, "q": q,
+                     "plain_ms": t_p, "dwivedi_ms": t_d,
+                     "plain_vertices": int(plain.vertices.sum()),
+                     "dwivedi_vertices": int(dw.vertices.sum()),
+                     "efficiency_gain_median": float(np.median(gain)),
+                     "efficiency_gain_p10_p90": [float(np.quantile(gain, 0.1)),
+                                                 float(np.quantile(gain, 0.9))],
+                     "R_z_vs_plain_median_abs": float(np.median(np.abs(z))),
+                     "R_z_vs_plain_max_abs": float(np.max(np.abs(z)))}
     return res
 
 

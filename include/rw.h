@@ -69,6 +69,8 @@ typedef enum {
                                   a negative weight, weights not summing to 1 (+-1e-5)
                                   or a NaN; that unit is left with zero tallies */
 #define RW_FLAG_VERTEX_CAP 2   /* some path hit max_vertices; it scored 0 */
+#define RW_FLAG_WEIGHT_CAP 4   /* rw_dwivedi_forward: a path's weight exceeded 2^64 (FP32
+                                  range guard); it was ended and scored 0 */
 
 typedef struct rw_context rw_context;
 
@@ -310,6 +312,34 @@ rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
                                   const rw_geometry* geom, int32_t n_hero,
                                   int64_t paths_per_group, uint64_t seed, rw_tally* out,
                                   void* stream);
+
+/* Dwivedi sampling in the mixture walk (the second variance reduction named in
+ * Sec. 2; the zero-variance-based scheme of Krivanek and d'Eon 2014, after
+ * Dwivedi 1982).  The walk of rw_forward (same media, geometry, Philox
+ * counters (v, p, 0, unit_base + u) and tally layout), except that at every
+ * scattering it takes, with probability q (0 < q <= 1), the Dwivedi
+ * technique: a direction of density 1 / (2 pi lam (nu0 - mu_s)) in the cosine
+ * mu_s with the top surface's outward normal and a flight against
+ * sigma_t (1 - mu_s / nu0), with nu0 > 1 the root of a nu atanh(1/nu) = 1 for
+ * the medium's albedo a clamped to [0.3, 1 - 1e-7] and
+ * lam = ln((nu0 + 1) / (nu0 - 1)); otherwise the plain technique.  The flight's
+ * end multiplies the weight by the true density of the sampled direction and
+ * flight over the two techniques' mixture (one-sample MIS, balance heuristic),
+ * so the estimate stays unbiased; the technique uniform is the low 9 bits of
+ * the vertex's fourth Philox word.  Exit weights vary from path to path and
+ * may exceed 1: the sums are FP64 (per work item, then added in item order),
+ * and R[u] = (sum x, sum x^2, T, A) and bins as rw_forward's.  With q = 1 in
+ * an isotropic medium the weights telescope (every exit weight depends only on
+ * the first collision's depth and the exit cosine); with strongly forward
+ * scattering media the weights become heavy-tailed and the plain walk is the
+ * better estimator.  A path whose weight exceeds 2^64 ends with score 0 and
+ * raises RW_FLAG_WEIGHT_CAP.  Normal incidence only (RW_E_UNSUPPORTED otherwise); no
+ * adjoint.  A device workspace of 8 (2 n_bins + 9) bytes per work item of up
+ * to 2048 paths (grown so that it stays within 1 GiB) plus 16 K bytes per unit.
+ * Asynchronous on `stream`. */
+rw_status rw_dwivedi_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                             int64_t paths_per_unit, uint64_t seed, float q, rw_tally* out,
+                             void* stream);
 
 /* Finalize (eq. radsss): per unit, from the raw sums of a forward tally and the
  * path count N the walk ran: with a DEVICE int32 paths_per_unit [n_units],

@@ -85,6 +85,15 @@ def layered_hero_forward(ctx: Context, layers, geom: Geometry, n_hero: int, path
     return finalize(ctx, geom, tally, layers.n_units, paths, stream=stream)
 
 
+def dwivedi_forward(ctx: Context, media: Media, geom: Geometry, paths: int, seed: int,
+                    q: float = 1.0, stream=None) -> ForwardResult:
+    """Mixture walk with Dwivedi sampling (rw_dwivedi_forward, technique
+    probability q) + finalize."""
+    tally = Tally(media.n_units, geom.n_bins, device=media.sigma_t.device)
+    rw.rw_dwivedi_forward(ctx, media, geom, paths, seed, q, tally, stream=stream)
+    return finalize(ctx, geom, tally, media.n_units, paths, stream=stream)
+
+
 def layered_adjoint(ctx: Context, layers, geom: Geometry, paths: int, seed: int, cot_R=None,
                     cot_bins=None, paths_per_unit=None, use_graph: bool = True, stream=None,
                     path_mask=None):

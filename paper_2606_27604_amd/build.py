@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librw.so")
 MICRO_LIB = os.path.join(PKG, "librw_micro.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["rw_kernels.hip", "rw_lut.hip", "rw_hero.hip", "rw_runtime.hip"]
+SOURCES = ["rw_kernels.hip", "rw_lut.hip", "rw_hero.hip", "rw_dwivedi.hip", "rw_runtime.hip"]
 MICRO_SOURCES = ["rw_micro.hip"]
 HEADERS = ["rw_device.hpp", "rw_internal.hpp"]
 

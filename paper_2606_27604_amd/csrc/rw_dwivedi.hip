@@ -1,0 +1,388 @@
+// Dwivedi sampling in the mixture walk for gfx950: the zero-variance-based
+// scheme of Krivanek and d'Eon ("A zero-variance-based sampling scheme for
+// Monte Carlo subsurface scattering", SIGGRAPH 2014 Talks, after Dwivedi 1982),
+// one of the two variance reductions the paper names beside its random walk
+// (Sec. 2).
+//
+// At every scattering the walk picks, with probability q, the Dwivedi
+// technique: a direction with density 1 / (2 pi lam (nu0 - mu_s)) in the
+// cosine mu_s with the outward normal of the top surface, and a flight against
+// sigma' = sigma_t (1 - mu_s / nu0), which favour flights back to the
+// surface; otherwise the plain technique (Henyey-Greenstein direction, flight
+// against sigma_t).  nu0 > 1 is the root of alpha nu atanh(1/nu) = 1, the
+// decay constant of the diffusion mode of a half-space, lam =
+// ln((nu0 + 1) / (nu0 - 1)).  One-sample MIS with the balance heuristic: the
+// flight's end multiplies the weight by the true density of (direction,
+// flight) over the two techniques' mixture, at most 1 / (1 - q).  With q = 1 in
+// an isotropic medium the factors telescope and every exit weight is a
+// function of the first collision's depth and the exit cosine alone.
+//
+// Work: one wavefront per work item (unit, chunk of paths), lanes taking the
+// item's paths in turn; the weights vary from path to path (they can exceed
+// 1), so the sums are FP64, gathered per wave in LDS and stored to the item's
+// slot, then added up per unit in item order by the convert kernel.
+#include <hip/hip_runtime.h>
+
+#include "../../include/rw.h"
+#include "rw_device.hpp"
+#include "rw_internal.hpp"
+
+namespace rw {
+
+// LDS table per medium (12 floats):
+// {flight = ln2 / sigma_t, albedo, g, hq}, {sigma_t, nu0, lam log2(e), hgk},
+// {1 / nu0, 1 / (2 pi lam), cumulative weight, (1 - g)^2}
+constexpr int kDwFloats = 12;
+
+// nu0 of an albedo clamped to [0.3, 1 - 1e-7]: bisection on x = 1/nu in
+// (0, 1), where atanh(x) / x rises from 1 to infinity, in FP64.
+__device__ double dwivedi_nu0(double alpha) {
+  const double a = fmin(fmax(alpha, 0.3), 1.0 - 1e-7);
+  double lo = 0.0, hi = 1.0;
+  for (int i = 0; i < 200; ++i) {
+    const double x = 0.5 * (lo + hi);
+    if (x <= lo || x >= hi) break;
+    const double f = atanh(x) / x;
+    if (a * f < 1.0) lo = x;
+    else hi = x;
+  }
+  return 2.0 / (lo + hi);
+}
+
+struct DwPath {
+  float x, y, z, ux, uy, uz, W, A;
+  int k;
+  bool mixed;  // the current flight's direction was sampled (not the entry, not a reflection)
+  bool dw;     // ... by the Dwivedi technique
+  float p_hg, p_d, mu_s, sig_d;
+};
+
+// Load and check unit u's media into the wave's LDS table (lane k stages
+// medium k).  Returns false (and raises the flag) for an invalid unit.
+template <int K>
+__device__ __forceinline__ bool stage_dwivedi(const DwivediArgs& a, int64_t u, float* tab,
+                                              int lane) {
+  const UnitParams<K> up = load_unit<K>(a.w, u);
+  if (lane < K) {
+    float s = up.sigma_t[0], al = up.alb[0], g = up.g[0], c = up.cum[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j) {
+      s = (lane == j) ? up.sigma_t[j] : s;
+      al = (lane == j) ? up.alb[j] : al;
+      g = (lane == j) ? up.g[j] : g;
+      c = (lane == j) ? up.cum[j] : c;
+    }
+    const Medium m = make_medium(s, al, g);
+    // nu0 and its derived constants, computed once per unit and medium
+    const float4 dn = reinterpret_cast<const float4*>(a.nu)[u * K + lane];
+    float* e = tab + lane * kDwFloats;
+    e[0] = m.flight; e[1] = al; e[2] = g; e[3] = m.hq;
+    e[4] = s;
+    e[5] = dn.x;
+    e[6] = dn.y;
+    e[7] = (1.0f - g * g) * 0.07957747154594767f;  // (1 - g^2) / (4 pi)
+    e[8] = dn.z;
+    e[9] = dn.w;
+    e[10] = c;
+    e[11] = (1.0f - g) * (1.0f - g);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (!up.ok && lane == 0) atomicOr(a.w.flags, RW_FLAG_BAD_PARAMS);
+  return up.ok;
+}
+
+// Per unit and medium: (nu0, lam log2(e), 1 / nu0, 1 / (2 pi lam)) of its
+// albedo, [n_units][K] float4 (an invalid albedo gets the clamp's value; the
+// walk kernel flags the unit)
+template <int K>
+__global__ void __launch_bounds__(256) dwivedi_nu_kernel(const DwivediArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n_units * K) return;
+  const int64_t u = i / K;
+  const int k = int(i - u * K);
+  const float al = a.w.albedo[k * a.w.k_stride + u];
+  const double nu = dwivedi_nu0(al == al ? double(al) : 0.5);
+  const double lam = log((nu + 1.0) / (nu - 1.0));
+  reinterpret_cast<float4*>(a.nu)[i] =
+      make_float4(float(nu), float(lam * 1.4426950408889634), float(1.0 / nu),
+                  float(1.0 / (2.0 * 3.141592653589793 * lam)));
+}
+
+// Henyey-Greenstein density per steradian from b = 1 + g^2 - 2 g cos(theta)
+__device__ __forceinline__ float hg_density(float hgk, float b) {
+  return hgk * __builtin_amdgcn_rcpf(b * __builtin_amdgcn_sqrtf(b));
+}
+
+// A path whose weight leaves [0, 2^64] (the FP32 range guard of the product of
+// MIS factors, each at most 1 / (1 - q)) ends here and scores 0
+constexpr int EV_WEIGHT_CAP = EV_CAP + 1;
+constexpr float kDwWeightCap = 1.8446744e19f;
+
+// One vertex (v >= 1) of a Dwivedi path.  Returns the vertex event.
+__device__ __forceinline__ int dwivedi_step(DwPath& p, uint4 w, const float* tab, float q,
+                                            const WalkGeom& geo) {
+  const float* e = tab + p.k * kDwFloats;
+  const float sig = e[4], nu0 = e[5], inv_nu0 = e[8];
+  // flight: -ln(u0) / sigma (sigma' after a Dwivedi direction)
+  const float fl = p.dw ? 0.69314718055994531f * __builtin_amdgcn_rcpf(p.sig_d) : e[0];
+  const float s = -__builtin_amdgcn_logf(u01(w.x)) * fl;
+  const float zn = fmaf(s, p.uz, p.z);
+  const bool top = (p.uz < 0.0f) && (zn <= 0.0f);
+  const bool bottom = geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
+  // the MIS factor of a flight of length l: true density over the mixture,
+  // divided through by the plain technique's e^{-sigma l} (times sigma for a
+  // collision): p_hg / (q p_d f e^{sigma mu_s l / nu0} + (1 - q) p_hg)
+  if (top || bottom) {
+    const float db = (top ? -p.z : (geo.slab_mm - p.z)) * __builtin_amdgcn_rcpf(p.uz);
+    p.x = fmaf(db, p.ux, p.x);
+    p.y = fmaf(db, p.uy, p.y);
+    p.z = top ? 0.0f : geo.slab_mm;
+    if (p.mixed) {
+      const float ex = __builtin_amdgcn_exp2f(sig * p.mu_s * db * inv_nu0 * 1.4426950408889634f);
+      p.W *= p.p_hg * __builtin_amdgcn_rcpf(fmaf(q * p.p_d, ex, (1.0f - q) * p.p_hg));
+      p.mixed = false;
+      p.dw = false;
+      if (!(p.W <= kDwWeightCap)) return EV_WEIGHT_CAP;
+    }
+    if (!geo.index_matched) {
+      const float F = fresnel(fabsf(p.uz), geo.n_rel, geo.n_rel2);
+      if (u01(w.w) < F) {
+        p.uz = -p.uz;
+        return EV_REFLECT;
+      }
+    }
+    return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
+  }
+  p.x = fmaf(s, p.ux, p.x);
+  p.y = fmaf(s, p.uy, p.y);
+  p.z = zn;
+  if (p.mixed) {
+    const float ex = __builtin_amdgcn_exp2f(sig * p.mu_s * s * inv_nu0 * 1.4426950408889634f);
+    const float f = p.sig_d * __builtin_amdgcn_rcpf(sig);
+    p.W *= p.p_hg * __builtin_amdgcn_rcpf(fmaf(q * p.p_d * f, ex, (1.0f - q) * p.p_hg));
+    if (!(p.W <= kDwWeightCap)) return EV_WEIGHT_CAP;
+  }
+  const float alb = e[1];
+  p.A = fmaf(p.W, 1.0f - alb, p.A);
+  p.W *= alb;
+  if (p.W < geo.rr_weight) {
+    if (u01(w.w) < geo.rr_survive) p.W *= geo.rr_boost;
+    else return EV_RR_KILL;
+  }
+  // the technique of the next flight: the low 9 bits of the fourth word (the
+  // roulette and Fresnel uniform uses its top 23)
+  const float ut = (float(w.w & 0x1FFu) + 0.5f) * 0.001953125f;
+  p.dw = ut < q;
+  const float g = e[2];
+  if (p.dw) {
+    const float m = nu0 - (nu0 + 1.0f) * __builtin_amdgcn_exp2f(-u01(w.y) * e[6]);
+    const float u2 = u01(w.z);
+    const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-m, m, 1.0f)));
+    const float nx = st * __builtin_amdgcn_cosf(u2), ny = st * __builtin_amdgcn_sinf(u2);
+    const float nz = -m;
+    const float c = fmaf(nx, p.ux, fmaf(ny, p.uy, nz * p.uz));
+    p.p_hg = hg_density(e[7], fmaf(-2.0f * g, c, fmaf(g, g, 1.0f)));
+    p.ux = nx;
+    p.uy = ny;
+    p.uz = nz;
+  } else {
+    float den;
+    const float omm = hg_omm(g, e[3], u01(w.y), den);
+    const float st = __builtin_amdgcn_sqrtf(omm * (2.0f - omm));
+    const float u2 = u01(w.z);
+    // 1 + g^2 - 2 g mu = (1 - g)^2 + 2 g (1 - mu): no cancellation near mu = 1
+    p.p_hg = hg_density(e[7], fmaf(2.0f * g, omm, e[11]));
+    rotate(p.ux, p.uy, p.uz, 1.0f - omm, st * __builtin_amdgcn_cosf(u2),
+           st * __builtin_amdgcn_sinf(u2));
+  }
+  p.mu_s = -p.uz;
+  p.p_d = e[9] * __builtin_amdgcn_rcpf(nu0 - p.mu_s);
+  p.sig_d = sig * fmaf(-p.mu_s, inv_nu0, 1.0f);
+  p.mixed = true;
+  return EV_COLLIDE;
+}
+
+__device__ __forceinline__ void lds_addd(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// per-wave LDS: the medium table (K x 12 floats, padded to 8-byte words), then
+// the sums [bins (n_bins+2) x (sum x, sum x^2) | sum x, sum x^2, T, A]
+inline __host__ __device__ int dwivedi_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
+constexpr int kDwTableWords = kMaxMedia * kDwFloats / 2;
+
+template <int K>
+__global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) {
+  extern __shared__ double dw_lds[];
+  const int lane = __lane_id();
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t item = int64_t(blockIdx.x) * (blockDim.x / kWave) + wid;
+  if (item >= a.n_items) return;  // whole waves
+  const int nb = a.w.geo.n_bins;
+  const int acc_words = dwivedi_acc_words(nb);
+  double* base = dw_lds + int64_t(wid) * (kDwTableWords + acc_words);
+  float* tab = reinterpret_cast<float*>(base);
+  double* acc = base + kDwTableWords;
+  const int64_t ul = item / a.chunks_per_unit;
+  const int64_t c = item - ul * a.chunks_per_unit;
+  const int64_t u = ul;  // the call's units start at 0 of the media view
+  const uint32_t pb = uint32_t(c * a.chunk);
+  const uint32_t pe = uint32_t(min(int64_t(pb) + a.chunk, a.w.map.paths_uniform));
+  for (int i = lane; i < acc_words; i += kWave) acc[i] = 0.0;
+  double* slot = a.slots + item * int64_t(acc_words + 1);
+  if (!stage_dwivedi<K>(a, u, tab, lane)) {
+    for (int i = lane; i <= acc_words; i += kWave) slot[i] = 0.0;
+    return;  // an invalid unit keeps zero tallies
+  }
+  const PhiloxKey ks = philox_schedule(a.w.key0, a.w.key1);
+  const uint32_t ctr3 = uint32_t(uint64_t(a.w.unit_base) + uint64_t(u));
+  const WalkGeom geo = a.w.geo;
+  const float q = a.q;
+  double* bins = acc;
+
+  DwPath p;
+  bool alive = false, capped = false, wcapped = false;
+  uint32_t path = 0, v = 0, cursor = pb;
+  uint64_t verts = 0;
+  // per-lane sums of the item (x, x^2 of top exits, T, A); the radial bins
+  // go to LDS (spread over the bins, so few lanes meet on one word)
+  double rx = 0.0, rx2 = 0.0, rt = 0.0, ra = 0.0;
+  for (;;) {
+    const uint64_t idle = __ballot(!alive);
+    if (idle != 0 && cursor < pe) {
+      if (!alive) {
+        const uint32_t cand = cursor + __builtin_amdgcn_mbcnt_hi(
+                                           uint32_t(idle >> 32),
+                                           __builtin_amdgcn_mbcnt_lo(uint32_t(idle), 0u));
+        if (cand < pe) {
+          path = cand;
+          v = 0;
+          alive = true;
+        }
+      }
+      const uint32_t next = cursor + uint32_t(__popcll(idle));
+      cursor = next < pe ? next : pe;
+    }
+    if (__ballot(alive) == 0) break;
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      if (alive) {
+        const uint4 w = philox(v, path, a.w.tag, ctr3, ks);
+        if (v == 0) {
+          // medium by the cumulative weights; pencil beam entering at r = 0
+          const float u0 = u01(w.x);
+          int k = 0;
+#pragma unroll
+          for (int j = 0; j < K - 1; ++j) k += (u0 >= tab[j * kDwFloats + 10]) ? 1 : 0;
+          p.k = k;
+          p.x = 0.0f; p.y = 0.0f; p.z = 0.0f;
+          p.ux = 0.0f; p.uy = 0.0f; p.uz = 1.0f;
+          p.W = geo.entry_weight;
+          p.A = 0.0f;
+          p.mixed = false;
+          p.dw = false;
+          p.p_hg = 0.0f; p.p_d = 0.0f; p.mu_s = 0.0f; p.sig_d = 0.0f;
+          v = 1;
+        } else {
+          int ev = dwivedi_step(p, w, tab, q, geo);
+          if (ev < EV_EXIT_TOP && v >= geo.max_vertices) {
+            ev = EV_CAP;
+            capped = true;
+          }
+          if (ev >= EV_EXIT_TOP) {
+            alive = false;
+            verts += v;
+            wcapped |= ev == EV_WEIGHT_CAP;
+            if (ev == EV_EXIT_TOP) {
+              const int b = radial_slot(p.x, p.y, geo);
+              const double x = double(p.W);
+              lds_addd(&bins[2 * b], x);
+              lds_addd(&bins[2 * b + 1], x * x);
+              rx += x;
+              rx2 += x * x;
+            } else if (ev == EV_EXIT_BOTTOM) {
+              rt += double(p.W);
+            }
+            ra += double(p.A);
+          } else {
+            ++v;
+          }
+        }
+      }
+    }
+  }
+  // the item's sums to its slot (the lanes' sums reduced in a fixed order); the
+  // vertex count after them
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int i = lane; i < 2 * (nb + 2); i += kWave) slot[i] = bins[i];
+  uint64_t tv = verts;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    tv += __shfl_xor(tv, off, kWave);
+    rx += __shfl_xor(rx, off, kWave);
+    rx2 += __shfl_xor(rx2, off, kWave);
+    rt += __shfl_xor(rt, off, kWave);
+    ra += __shfl_xor(ra, off, kWave);
+  }
+  if (lane == 0) {
+    slot[2 * (nb + 2)] = rx;
+    slot[2 * (nb + 2) + 1] = rx2;
+    slot[2 * (nb + 2) + 2] = rt;
+    slot[2 * (nb + 2) + 3] = ra;
+    slot[acc_words] = double(tv);
+  }
+  if (__any(capped) && lane == 0) atomicOr(a.w.flags, RW_FLAG_VERTEX_CAP);
+  if (__any(wcapped) && lane == 0) atomicOr(a.w.flags, RW_FLAG_WEIGHT_CAP);
+}
+
+// Per unit: its items' slots added in item order; R = (sum x, sum x^2, T, A),
+// bins, vertices.  One block per unit (grid stride).
+__global__ void __launch_bounds__(256) dwivedi_convert_kernel(const DwivediArgs a) {
+  const int nb2 = 2 * (a.w.geo.n_bins + 2);
+  const int acc_words = nb2 + 4;
+  for (int64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+    for (int wd = threadIdx.x; wd <= acc_words; wd += blockDim.x) {
+      double s = 0.0;
+      for (int64_t c = 0; c < a.chunks_per_unit; ++c)
+        s += a.slots[(u * a.chunks_per_unit + c) * int64_t(acc_words + 1) + wd];
+      if (wd < nb2) a.w.out_bins[u * nb2 + wd] = s;
+      else if (wd < acc_words) a.w.out_R[u * 4 + (wd - nb2)] = s;
+      else a.w.out_vertices[u] = int64_t(s);
+    }
+  }
+}
+
+int dwivedi_lds_bytes(int n_bins, int waves_per_wg) {
+  return waves_per_wg * (kDwTableWords + dwivedi_acc_words(n_bins)) * int(sizeof(double));
+}
+
+int64_t dwivedi_slot_words(int n_bins) { return dwivedi_acc_words(n_bins) + 1; }
+
+template <int K>
+static hipError_t launch_dwivedi_k(const DwivediArgs& a, int wpw, hipStream_t s) {
+  const int64_t blocks = (a.n_items + wpw - 1) / wpw;
+  const size_t lds = size_t(dwivedi_lds_bytes(a.w.geo.n_bins, wpw));
+  if (a.n_units > 0)
+    hipLaunchKernelGGL(dwivedi_nu_kernel<K>, dim3(unsigned((a.n_units * K + 255) / 256)),
+                       dim3(256), 0, s, a);
+  if (blocks > 0)
+    hipLaunchKernelGGL(dwivedi_walk_kernel<K>, dim3(unsigned(blocks)), dim3(wpw * kWave), lds, s,
+                       a);
+  if (a.n_units > 0) {
+    const unsigned g = unsigned(a.n_units < (int64_t(1) << 20) ? a.n_units : (int64_t(1) << 20));
+    hipLaunchKernelGGL(dwivedi_convert_kernel, dim3(g), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dwivedi(const DwivediArgs& a, int K, int waves_per_wg, hipStream_t s) {
+  switch (K) {
+    case 1: return launch_dwivedi_k<1>(a, waves_per_wg, s);
+    case 2: return launch_dwivedi_k<2>(a, waves_per_wg, s);
+    case 3: return launch_dwivedi_k<3>(a, waves_per_wg, s);
+    case 4: return launch_dwivedi_k<4>(a, waves_per_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rw

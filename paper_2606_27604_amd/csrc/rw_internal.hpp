@@ -186,6 +186,22 @@ constexpr bool hero_group_supported(int C) {
 }
 hipError_t launch_hero(const HeroArgs& a, int C, hipStream_t stream);
 
+// Dwivedi walk (rw_dwivedi.hip): the mixture walk's arguments plus the
+// technique probability, the work items (unit, chunk of paths), their FP64
+// slots [n_items][2 (n_bins + 2) + 4 sums + vertex count] and the per unit
+// and medium constants of nu0 [n_units][K] x 4 floats
+struct DwivediArgs {
+  WalkArgs w;                  // media, geometry, keys, tag, unit_base, outputs, flags;
+                               // w.map.paths_uniform = paths per unit
+  float q;                     // probability of the Dwivedi technique, (0, 1]
+  int64_t n_units, chunk, chunks_per_unit, n_items;
+  double* slots;
+  float* nu;
+};
+hipError_t launch_dwivedi(const DwivediArgs& a, int K, int waves_per_wg, hipStream_t stream);
+int dwivedi_lds_bytes(int n_bins, int waves_per_wg);
+int64_t dwivedi_slot_words(int n_bins);
+
 // launchers (rw_kernels.hip); all asynchronous on `stream`
 hipError_t launch_walk(const WalkArgs& a, int K, bool adjoint, int waves_per_wg, int grid_wgs,
                        hipStream_t stream);

@@ -1206,6 +1206,77 @@ rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
   return RW_OK;
 }
 
+rw_status rw_dwivedi_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
+                             int64_t paths_per_unit, uint64_t seed, float q, rw_tally* out,
+                             void* stream) {
+  if (!ctx) return RW_E_INVALID;
+  ctx->last_error[0] = 0;
+  rw_status st = check_geom(ctx, geom);
+  if (st != RW_OK) return st;
+  int64_t n_units = 0;
+  st = check_media(ctx, media, &n_units);
+  if (st != RW_OK) return st;
+  if (!(q > 0.0f) || !(q <= 1.0f))
+    return fail(ctx, RW_E_INVALID, "the Dwivedi technique probability q must be in (0, 1]");
+  if (geom->incidence != RW_INCIDENCE_NORMAL)
+    return fail(ctx, RW_E_UNSUPPORTED, "the Dwivedi walk supports normal incidence only");
+  if (paths_per_unit < 0 || paths_per_unit > (int64_t(1) << 31))
+    return fail(ctx, RW_E_INVALID, "path count must be in [0, 2^31] (got %lld)",
+                (long long)paths_per_unit);
+  if (!out || !out->R || !out->bins || !out->vertices || !out->flags)
+    return fail(ctx, RW_E_INVALID, "tally pointers must be non-NULL");
+  st = need_device(ctx);
+  if (st != RW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const MediaView v = view_of(media, geom, n_units);
+  DwivediArgs a{};
+  a.w.sigma_t = v.sigma_t;
+  a.w.albedo = v.albedo;
+  a.w.g = v.g;
+  a.w.weight = v.weight;
+  a.w.weights_are_logits = v.logits;
+  a.w.k_stride = v.k_stride;
+  a.w.unit_base = uint32_t(v.unit_base);
+  a.w.n_units_total = n_units;
+  a.w.geo = make_geom(geom);
+  a.w.map.paths_uniform = paths_per_unit;
+  a.w.key0 = uint32_t(seed);
+  a.w.key1 = uint32_t(seed >> 32);
+  a.w.tag = kForwardTag;
+  a.w.out_R = out->R;
+  a.w.out_bins = out->bins;
+  a.w.out_vertices = out->vertices;
+  a.w.flags = out->flags;
+  a.q = q;
+  a.n_units = n_units;
+  // items of 2048 paths, grown so that the slots stay within kMaxSlotBytes
+  const int64_t words = dwivedi_slot_words(geom->n_bins);
+  int64_t chunk = 2048;
+  while (paths_per_unit > chunk &&
+         n_units * ((paths_per_unit + chunk - 1) / chunk) * words * 8 > kMaxSlotBytes)
+    chunk *= 2;
+  a.chunk = chunk;
+  a.chunks_per_unit = paths_per_unit > 0 ? (paths_per_unit + chunk - 1) / chunk : 0;
+  a.n_items = n_units * a.chunks_per_unit;
+  RW_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(out->flags), 1, 0u, s));
+  if (a.n_items > 0) {
+    const size_t slot_bytes = (size_t(a.n_items * words * 8) + 15) & ~size_t(15);
+    st = ensure_workspace(ctx, slot_bytes + size_t(n_units) * geom->n_media * 16);
+    if (st != RW_OK) return st;
+    a.slots = reinterpret_cast<double*>(ctx->workspace);
+    a.nu = reinterpret_cast<float*>(reinterpret_cast<char*>(ctx->workspace) + slot_bytes);
+  } else if (n_units > 0) {
+    // no paths: zero tallies
+    RW_HIP(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(out->R), n_units * 4, s));
+    RW_HIP(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(out->bins),
+                                n_units * 2 * (geom->n_bins + 2), s));
+    RW_HIP(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(out->vertices), n_units, s));
+    return RW_OK;
+  }
+  RW_HIP(ctx, launch_dwivedi(a, geom->n_media, 4, s));
+  return RW_OK;
+}
+
 rw_status rw_finalize(rw_context* ctx, const rw_geometry* geom, int64_t n_units,
                       const int32_t* paths_per_unit, int64_t paths_uniform, const rw_tally* tally,
                       double* R_mean, double* R_se, double* Rr, double* Rr_se, double* Pd,

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_PKG, "librw.so")
 RW_OK, RW_E_INVALID, RW_E_HIP, RW_E_NOMEM, RW_E_UNSUPPORTED, RW_E_DEVICE_FLAG = range(6)
 RW_FLAG_BAD_PARAMS = 1
 RW_FLAG_VERTEX_CAP = 2
+RW_FLAG_WEIGHT_CAP = 4
 
 
 class RwError(RuntimeError):
@@ -129,7 +130,7 @@ EXPORTS = [
     "rw_batch_forward", "rw_adjoint", "rw_batch_adjoint", "rw_finalize", "rw_check",
     "rw_debug_trace", "rw_debug_philox", "rw_version", "rw_layered_forward",
     "rw_layered_adjoint", "rw_debug_trace_layered", "rw_lut_loss_grad", "rw_lut_fit_step",
-    "rw_forward_noalloc", "rw_layered_hero_forward",
+    "rw_forward_noalloc", "rw_layered_hero_forward", "rw_dwivedi_forward",
 ]
 
 _lib = None
@@ -163,6 +164,9 @@ def load_library(path: str = LIB_PATH):
     L.rw_layered_hero_forward.argtypes = [vp, P(RwLayersC), P(RwGeometryC), i32, i64, u64,
                                           P(RwTallyC), vp]
     L.rw_layered_hero_forward.restype = ctypes.c_int
+    L.rw_dwivedi_forward.argtypes = [vp, P(RwMediaC), P(RwGeometryC), i64, u64, ctypes.c_float,
+                                     P(RwTallyC), vp]
+    L.rw_dwivedi_forward.restype = ctypes.c_int
     L.rw_batch_forward.argtypes = [vp, P(RwMediaC), P(RwGeometryC), vp, i64, u64, P(RwTallyC),
                                    P(RwBatchOptsC), vp]
     L.rw_batch_forward.restype = ctypes.c_int
@@ -533,6 +537,14 @@ def rw_layered_hero_forward(ctx: Context, layers: Layers, geom: Geometry, n_hero
                                                       ctypes.byref(g), int(n_hero),
                                                       int(paths_per_group), int(seed),
                                                       ctypes.byref(out._c), _stream(stream)))
+
+
+def rw_dwivedi_forward(ctx: Context, media: Media, geom: Geometry, paths_per_unit: int, seed: int,
+                       q: float, out: Tally, stream=None):
+    g = geom.c()
+    ctx._check(load_library().rw_dwivedi_forward(ctx.h, ctypes.byref(media._c), ctypes.byref(g),
+                                                 int(paths_per_unit), int(seed), float(q),
+                                                 ctypes.byref(out._c), _stream(stream)))
 
 
 def rw_debug_trace_layered(ctx: Context, layers: Layers, geom: Geometry, words, n_paths: int,

@@ -186,3 +186,21 @@ def test_hero_walk_argument_checks(lib):
     g3 = rw.Geometry(n_media=3).c()
     assert lib.rw_layered_hero_forward(ctx.h, ctypes.byref(L), ctypes.byref(g3), 3, 300, 0,
                                        ctypes.byref(t), None) == rw.RW_E_INVALID
+
+
+def test_dwivedi_walk_argument_checks(lib):
+    """rw_dwivedi_forward rejects technique probabilities outside (0, 1],
+    cosine incidence and bad path counts before anything reaches a device."""
+    ctx = rw.Context(-1)
+    g = rw.Geometry(n_media=3).c()
+    gc = rw.Geometry(n_media=3, incidence=1).c()
+    t = rw.RwTallyC(0x5000, 0x6000, 0x7000, 0x8000)
+    m = rw.RwMediaC(0x1000, 0x2000, 0x3000, 0x4000, 0, 1, 4, None, 0)
+    call = lambda geo, n, q: lib.rw_dwivedi_forward(ctx.h, ctypes.byref(m), ctypes.byref(geo),  # noqa: E731
+                                                    n, 0, q, ctypes.byref(t), None)
+    assert call(g, 1000, 0.0) == rw.RW_E_INVALID
+    assert call(g, 1000, 1.5) == rw.RW_E_INVALID
+    assert call(g, 1000, float("nan")) == rw.RW_E_INVALID
+    assert call(gc, 1000, 0.5) == rw.RW_E_UNSUPPORTED
+    assert call(g, -1, 0.5) == rw.RW_E_INVALID
+    assert call(g, 1000, 1.0) == rw.RW_E_UNSUPPORTED and "validation-only" in ctx.last_error()
