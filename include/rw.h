@@ -327,7 +327,7 @@ rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
  * flight over the two techniques' mixture (one-sample MIS, balance heuristic),
  * so the estimate stays unbiased; the technique uniform is the low 9 bits of
  * the vertex's fourth Philox word.  Exit weights vary from path to path and
- * may exceed 1: the sums are FP64 (per work item, then added in item order),
+ * may exceed 1: the sums are FP64 (per work item, then added in a fixed order),
  * and R[u] = (sum x, sum x^2, T, A) and bins as rw_forward's.  With q = 1 in
  * an isotropic medium the weights telescope (every exit weight depends only on
  * the first collision's depth and the exit cosine); with strongly forward

@@ -20,7 +20,7 @@
 // Work: one wavefront per work item (unit, chunk of paths), lanes taking the
 // item's paths in turn; the weights vary from path to path (they can exceed
 // 1), so the sums are FP64, gathered per wave in LDS and stored to the item's
-// slot, then added up per unit in item order by the convert kernel.
+// slot, then added up per unit in a fixed order by the convert kernel.
 #include <hip/hip_runtime.h>
 
 #include "../../include/rw.h"
@@ -174,27 +174,39 @@ __device__ __forceinline__ int dwivedi_step(DwPath& p, uint4 w, const float* tab
   const float ut = (float(w.w & 0x1FFu) + 0.5f) * 0.001953125f;
   p.dw = ut < q;
   const float g = e[2];
+  // Both techniques turn a reference direction by a polar cosine mu and an
+  // azimuth: Henyey-Greenstein about the old direction, Dwivedi about the
+  // outward normal (0, 0, -1) with cosine m = mu_s (there the frame of rotate
+  // has the tangents (1, 0, 0) and (0, -1, 0), so the sine term changes sign
+  // to give (st cos, st sin, -m)).  Only the cosine differs per technique; the
+  // square root, the azimuth's sine and cosine, the turn and the
+  // Henyey-Greenstein density are shared, so a wave with lanes of both
+  // techniques evaluates them once.
+  float mu, st2, omm = 0.0f;
   if (p.dw) {
-    const float m = nu0 - (nu0 + 1.0f) * __builtin_amdgcn_exp2f(-u01(w.y) * e[6]);
-    const float u2 = u01(w.z);
-    const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-m, m, 1.0f)));
-    const float nx = st * __builtin_amdgcn_cosf(u2), ny = st * __builtin_amdgcn_sinf(u2);
-    const float nz = -m;
-    const float c = fmaf(nx, p.ux, fmaf(ny, p.uy, nz * p.uz));
-    p.p_hg = hg_density(e[7], fmaf(-2.0f * g, c, fmaf(g, g, 1.0f)));
-    p.ux = nx;
-    p.uy = ny;
-    p.uz = nz;
+    mu = nu0 - (nu0 + 1.0f) * __builtin_amdgcn_exp2f(-u01(w.y) * e[6]);
+    st2 = fmaxf(0.0f, fmaf(-mu, mu, 1.0f));
   } else {
     float den;
-    const float omm = hg_omm(g, e[3], u01(w.y), den);
-    const float st = __builtin_amdgcn_sqrtf(omm * (2.0f - omm));
-    const float u2 = u01(w.z);
-    // 1 + g^2 - 2 g mu = (1 - g)^2 + 2 g (1 - mu): no cancellation near mu = 1
-    p.p_hg = hg_density(e[7], fmaf(2.0f * g, omm, e[11]));
-    rotate(p.ux, p.uy, p.uz, 1.0f - omm, st * __builtin_amdgcn_cosf(u2),
-           st * __builtin_amdgcn_sinf(u2));
+    omm = hg_omm(g, e[3], u01(w.y), den);
+    mu = 1.0f - omm;
+    st2 = omm * (2.0f - omm);
   }
+  const float st = __builtin_amdgcn_sqrtf(st2);
+  const float u2 = u01(w.z);
+  const float sp = st * __builtin_amdgcn_cosf(u2), sq = st * __builtin_amdgcn_sinf(u2);
+  const float ox = p.ux, oy = p.uy, oz = p.uz;
+  float nx = p.dw ? 0.0f : ox, ny = p.dw ? 0.0f : oy, nz = p.dw ? -1.0f : oz;
+  rotate(nx, ny, nz, mu, sp, p.dw ? -sq : sq);
+  // 1 + g^2 - 2 g cos(theta): from the turn's cosine for Henyey-Greenstein,
+  // as (1 - g)^2 + 2 g (1 - mu) (no cancellation near mu = 1); from the cosine
+  // between the old and the new direction for Dwivedi
+  const float c = fmaf(nx, ox, fmaf(ny, oy, nz * oz));
+  const float b = p.dw ? fmaf(-2.0f * g, c, fmaf(g, g, 1.0f)) : fmaf(2.0f * g, omm, e[11]);
+  p.p_hg = hg_density(e[7], b);
+  p.ux = nx;
+  p.uy = ny;
+  p.uz = nz;
   p.mu_s = -p.uz;
   p.p_d = e[9] * __builtin_amdgcn_rcpf(nu0 - p.mu_s);
   p.sig_d = sig * fmaf(-p.mu_s, inv_nu0, 1.0f);
@@ -335,20 +347,52 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
   if (__any(wcapped) && lane == 0) atomicOr(a.w.flags, RW_FLAG_WEIGHT_CAP);
 }
 
-// Per unit: its items' slots added in item order; R = (sum x, sum x^2, T, A),
-// bins, vertices.  One block per unit (grid stride).
-__global__ void __launch_bounds__(256) dwivedi_convert_kernel(const DwivediArgs a) {
+// Per unit: its items' slots added in a fixed order; R = (sum x, sum x^2, T,
+// A), bins, vertices.  A block takes kDwConvWords words of one unit: thread
+// (j, i) adds the unit's items c = i, i + kDwConvParts, ... for word j (loads of
+// kDwConvWords consecutive words per item), and the kDwConvParts partial sums of a
+// word are then added in i order.  Grid stride over (unit, word group).
+constexpr int kDwConvWords = 32;
+constexpr int kDwConvParts = 8;
+
+__global__ void __launch_bounds__(kDwConvWords * kDwConvParts)
+    dwivedi_convert_kernel(const DwivediArgs a) {
+  __shared__ double part[kDwConvParts][kDwConvWords];
   const int nb2 = 2 * (a.w.geo.n_bins + 2);
   const int acc_words = nb2 + 4;
-  for (int64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
-    for (int wd = threadIdx.x; wd <= acc_words; wd += blockDim.x) {
-      double s = 0.0;
-      for (int64_t c = 0; c < a.chunks_per_unit; ++c)
-        s += a.slots[(u * a.chunks_per_unit + c) * int64_t(acc_words + 1) + wd];
-      if (wd < nb2) a.w.out_bins[u * nb2 + wd] = s;
-      else if (wd < acc_words) a.w.out_R[u * 4 + (wd - nb2)] = s;
-      else a.w.out_vertices[u] = int64_t(s);
+  const int64_t stride = acc_words + 1;
+  const int64_t groups = (stride + kDwConvWords - 1) / kDwConvWords;
+  const int j = threadIdx.x % kDwConvWords, i = threadIdx.x / kDwConvWords;
+  for (int64_t bg = blockIdx.x; bg < a.n_units * groups; bg += gridDim.x) {
+    const int64_t u = bg / groups;
+    const int64_t wd = (bg - u * groups) * kDwConvWords + j;
+    double s = 0.0;
+    if (wd < stride) {
+      const double* col = a.slots + u * a.chunks_per_unit * stride + wd;
+      int64_t c = i;
+      // four independent loads in flight, added in c order
+      for (; c + 3 * kDwConvParts < a.chunks_per_unit; c += 4 * kDwConvParts) {
+        const double x0 = col[c * stride], x1 = col[(c + kDwConvParts) * stride];
+        const double x2 = col[(c + 2 * kDwConvParts) * stride];
+        const double x3 = col[(c + 3 * kDwConvParts) * stride];
+        s += x0;
+        s += x1;
+        s += x2;
+        s += x3;
+      }
+      for (; c < a.chunks_per_unit; c += kDwConvParts) s += col[c * stride];
     }
+    part[i][j] = s;
+    __syncthreads();
+    if (i == 0 && wd < stride) {
+      double t = part[0][j];
+#pragma unroll
+      for (int k = 1; k < kDwConvParts; ++k) t += part[k][j];
+      if (wd < nb2) a.w.out_bins[u * nb2 + wd] = t;
+      else if (wd < acc_words) a.w.out_R[u * 4 + (wd - nb2)] = t;
+      else a.w.out_vertices[u] = int64_t(t);
+    }
+    __syncthreads();
   }
 }
 
@@ -369,8 +413,10 @@ static hipError_t launch_dwivedi_k(const DwivediArgs& a, int wpw, hipStream_t s)
     hipLaunchKernelGGL(dwivedi_walk_kernel<K>, dim3(unsigned(blocks)), dim3(wpw * kWave), lds, s,
                        a);
   if (a.n_units > 0) {
-    const unsigned g = unsigned(a.n_units < (int64_t(1) << 20) ? a.n_units : (int64_t(1) << 20));
-    hipLaunchKernelGGL(dwivedi_convert_kernel, dim3(g), dim3(256), 0, s, a);
+    const int64_t groups = (dwivedi_slot_words(a.w.geo.n_bins) + kDwConvWords - 1) / kDwConvWords;
+    const int64_t n = a.n_units * groups;
+    const unsigned g = unsigned(n < (int64_t(1) << 20) ? n : (int64_t(1) << 20));
+    hipLaunchKernelGGL(dwivedi_convert_kernel, dim3(g), dim3(kDwConvWords * kDwConvParts), 0, s, a);
   }
   return hipGetLastError();
 }
