@@ -457,6 +457,16 @@ __device__ __forceinline__ bool stage_any(const WalkArgs& a, int64_t u, float* t
   }
 }
 
+// An empty asm statement that takes a draw's fields as register inputs: the
+// draw's reads must have completed there.
+template <bool ADJ>
+__device__ __forceinline__ void hold_draw(const VertexDraw& d) {
+  if constexpr (ADJ)
+    asm volatile("" ::"v"(d.s), "v"(d.mu), "v"(d.p), "v"(d.q), "v"(d.w3), "v"(d.den));
+  else
+    asm volatile("" ::"v"(d.s), "v"(d.mu), "v"(d.p), "v"(d.q), "v"(d.w3));
+}
+
 // Draw i of the tail's LDS arrays (field f at dr[f * kWave + i]).
 template <bool ADJ>
 __device__ __forceinline__ VertexDraw load_draw(const float* dr, uint32_t i) {
@@ -595,15 +605,26 @@ walk_kernel(const WalkArgs a) {
         // overlaps it.)
         const bool room = __ballot(sel && v + (depth - s) > geo.max_vertices) == 0;
         VertexDraw d = load_draw<ADJ>(dr, base + s);
-        for (; room && s < depth; ++s) {
+        // two steps per pass, the draws alternating between d and d1, so that
+        // no draw is copied from one variable to the other; each next draw is
+        // held in registers by the end of the step it overlaps (else the
+        // compiler defers the reads past the next test and exposes them)
+        while (room && s < depth) {
           float zn;
-          const bool plain = plain_collision(p, d, geo, zn);
-          if (__ballot(sel & !plain) != 0) break;
-          const VertexDraw dn = load_draw<ADJ>(dr, base + (s + 1 < depth ? s + 1 : s));
+          if (__ballot(sel & !plain_collision(p, d, geo, zn)) != 0) break;
+          const VertexDraw d1 = load_draw<ADJ>(dr, base + (s + 1 < depth ? s + 1 : s));
           absorb_at<ADJ>(p, d, zn);
           scatter<ADJ>(p, d);
           ++v;
-          d = dn;
+          hold_draw<ADJ>(d1);
+          if (++s == depth) break;
+          if (__ballot(sel & !plain_collision(p, d1, geo, zn)) != 0) break;
+          d = load_draw<ADJ>(dr, base + (s + 1 < depth ? s + 1 : s));
+          absorb_at<ADJ>(p, d1, zn);
+          scatter<ADJ>(p, d1);
+          ++v;
+          ++s;
+          hold_draw<ADJ>(d);
         }
         if (s == depth) break;
       }
