@@ -127,8 +127,12 @@ inline int adjoint_acc_words(int K) { return 8 * K + 2; }
 // media of the adjoint sums: K for the mixture, the two layers for the
 // two-layer walk
 inline int adjoint_media(int model) { return model == kLayeredModel ? 2 : model; }
+// the masked adjoint's pick table (kWave lane indices) and window of kWave
+// mask words, behind the exit ring
+constexpr int kAdjExtraWords = kWave;
 inline int walk_lds_words_per_wave(int acc_words, bool adjoint) {
-  return acc_words + kMediaTableWords + kColdConstWords + walk_ring_words(adjoint);
+  return acc_words + kMediaTableWords + kColdConstWords + walk_ring_words(adjoint) +
+         (adjoint ? kAdjExtraWords : 0);
 }
 
 // Lookup-table fit (rw_lut.hip): tables, targets, raw parameters [4K-1][n_units]

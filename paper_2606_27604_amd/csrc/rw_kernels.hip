@@ -48,18 +48,6 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
 }
 
-// Position of the r-th set bit (r counted from 0) of b, for r < popcount(b):
-// the largest p with popcount(b & (2^p - 1)) <= r, by binary search.
-__device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
-  uint32_t p = 0;
-#pragma unroll
-  for (uint32_t step = 32; step > 0; step >>= 1) {
-    const uint64_t below = b & ((uint64_t(1) << (p + step)) - 1);
-    if (uint32_t(__popcll(below)) <= r) p += step;
-  }
-  return p;
-}
-
 // Forward: a path of unit u that left the top surface sets its bit of the
 // live mask.  The words of a work item belong to that item alone (items span
 // whole words: their first path is a multiple of the chunk, itself a
@@ -162,6 +150,8 @@ struct WaveLds {
   ColdConst* cold;
   float4* ring;
   uint32_t* live;   // forward: the live window, behind the exit ring
+  uint32_t* pick;   // adjoint: lanes of the live candidates in rank order
+  uint32_t* mwin;   // adjoint: kWave consecutive words of the live mask
 };
 
 // Read from LDS where used: reads that a store in the loop may alias stay in
@@ -503,6 +493,10 @@ walk_kernel(const WalkArgs a) {
   L.cold = reinterpret_cast<ColdConst*>(L.acc + a.acc_words + kMediaTableWords);
   L.ring = reinterpret_cast<float4*>(L.acc + a.acc_words + kMediaTableWords + kColdConstWords);
   L.live = MARK ? reinterpret_cast<uint32_t*>(L.ring + kExitRing) : nullptr;
+  L.pick = ADJ ? reinterpret_cast<uint32_t*>(L.acc + a.acc_words + kMediaTableWords +
+                                             kColdConstWords + walk_ring_words(true))
+               : nullptr;
+  L.mwin = ADJ ? L.pick + kWave : nullptr;
   for (int i = lane; i < a.acc_words; i += kWave) L.acc[i] = 0ull;
   if (MARK) L.live[lane] = 0u;
   if (lane == 0) {
@@ -529,6 +523,8 @@ walk_kernel(const WalkArgs a) {
   uint32_t cursor = 0, pend = 0, head = 0, tail = 0, iter = 0;
   // the live window: unit and first word
   uint32_t wu = kNoUnit, wb = 0;
+  // the masked adjoint's window of mask words: unit and first word
+  uint32_t mu = kNoUnit, mw = 0;
   int64_t static_item = int64_t(blockIdx.x) * wpw + wid;
   bool done = false, unit_ok = false, boosted = false;
   // lane state
@@ -708,17 +704,30 @@ walk_kernel(const WalkArgs a) {
         // replay only the paths the forward saw leave the top: of the next 64
         // path indices, the r-th idle lane takes the r-th live one, and the
         // cursor moves past the last one taken (or past all 64)
+        // the candidates' mask words from an LDS window of kWave words, read
+        // from memory once per kWave words (an item of 2 048 paths: once)
+        const uint32_t cw = cursor >> 5;
+        if (uint32_t(u_cur) != mu || cw < mw || cw + 2u >= mw + uint32_t(kWave)) {
+          mu = uint32_t(u_cur);
+          mw = cw;
+          const uint32_t w = mw + uint32_t(lane);
+          L.mwin[lane] = int64_t(w) < a.mask_words ? a.live_mask[u_cur * a.mask_words + w] : 0u;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
         const uint32_t c = cursor + uint32_t(lane);
         bool live = false;
-        if (c < pend)
-          live = (a.live_mask[u_cur * a.mask_words + (c >> 5)] >> (c & 31u)) & 1u;
+        if (c < pend) live = (L.mwin[(c >> 5) - mw] >> (c & 31u)) & 1u;
         const uint64_t lb = __ballot(live);
         const uint32_t n_live = uint32_t(__popcll(lb));
         const uint32_t n_idle = uint32_t(__popcll(idle));
+        // the live candidates' lanes in rank order, so that the r-th idle lane
+        // reads the r-th live one instead of searching the ballot's bits
+        if (live) L.pick[lane_rank(lb)] = uint32_t(lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (!alive) {
           const uint32_t r = lane_rank(idle);
           if (r < n_live) {
-            path = cursor + nth_set_bit(lb, r);
+            path = cursor + L.pick[r];
             v = 0;
             alive = true;
             lunit = uint32_t(u_cur);
@@ -726,7 +735,9 @@ walk_kernel(const WalkArgs a) {
             lctr = a.unit_base + lunit;
           }
         }
-        const uint32_t next = n_live > n_idle ? cursor + nth_set_bit(lb, n_idle) : cursor + 64u;
+        const uint32_t next =
+            n_live > n_idle ? cursor + __builtin_amdgcn_readfirstlane(L.pick[n_idle]) : cursor + 64u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         cursor = next < pend ? next : pend;
       } else {
         if (!alive) {
