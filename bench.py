@@ -335,6 +335,10 @@ def main():
     def run(batched, seed0, skip=True):
         for i in range(args.warmup):
             step(seed0 + 1000 + i, batched, skip=skip)
+        # the per-step vertex sums below, once untimed: torch loads its
+        # reduction kernel on first use (about 25 ms, which would stall the
+        # first timed step's launch)
+        tally.vertices.sum(), avert.sum()
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         verts = []
