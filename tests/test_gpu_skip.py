@@ -128,6 +128,31 @@ def test_masked_adjoint_with_uneven_counts_window_and_small_units():
     assert _close(G[1000:3000], full[0][1000:3000])
 
 
+@pytest.mark.parametrize("chunk", [1024, 8192])
+def test_masked_adjoint_with_other_item_sizes(tmp_path, monkeypatch, chunk):
+    """Items of 1 024 and 8 192 paths (set through the tune cache): an item of
+    8 192 paths spans 256 mask words, so the replay refills its LDS window of
+    64 words four times per item.  Vertex counts equal the default shape's
+    and the gradient its value to FP64 rounding."""
+    wl = workloads.config2(paths=1 << 15)
+    sub = wl.subset(np.arange(12))
+    m = media(sub.sigma_t, sub.albedo, sub.g, sub.weight)
+    g, _ = geoms(3, sub.n_rel)
+    N, n = sub.paths_per_unit, sub.n_units
+    rng = np.random.default_rng(31)
+    cR = torch.ones(n, dtype=torch.float32, device="cuda")
+    cB = torch.from_numpy(rng.standard_normal((n, g.n_bins + 2)).astype(np.float32)).cuda()
+    res, mask, full, skip = _skip_vs_full(m, g, N, 41, cR, cB, n)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"gfx950 K3 adj persistent nb{g.n_bins} p{N} m1|{chunk} 4 0\n")
+    monkeypatch.setenv("RW_AUTOTUNE_CACHE", str(cache))
+    c2 = rw.Context(0)  # reads the cache at its first batched call
+    other = api.adjoint(c2, m, g, N, 41, cot_R=cR, cot_bins=cB, path_mask=mask)
+    assert rw.rw_check(c2, other[3]) == 0
+    assert torch.equal(other[2], skip[2])
+    assert _close(other[0], skip[0]) and _close(other[1], skip[1])
+
+
 def test_masked_layered_adjoint_equals_full_replay():
     wl = workloads.layered_tones(8, paths=1 << 14)
     L = rw.Layers.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm, wl.n_rel_bottom)
