@@ -706,8 +706,9 @@ walk_kernel(const WalkArgs a) {
         // cursor moves past the last one taken (or past all 64)
         // the candidates' mask words from an LDS window of kWave words, read
         // from memory once per kWave words (an item of 2 048 paths: once)
+        // (a wave that never took an item has u_cur = -1 and no candidates)
         const uint32_t cw = cursor >> 5;
-        if (uint32_t(u_cur) != mu || cw < mw || cw + 2u >= mw + uint32_t(kWave)) {
+        if (u_cur >= 0 && (uint32_t(u_cur) != mu || cw < mw || cw + 2u >= mw + uint32_t(kWave))) {
           mu = uint32_t(u_cur);
           mw = cw;
           const uint32_t w = mw + uint32_t(lane);

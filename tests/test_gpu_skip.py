@@ -153,6 +153,19 @@ def test_masked_adjoint_with_other_item_sizes(tmp_path, monkeypatch, chunk):
     assert _close(other[0], skip[0]) and _close(other[1], skip[1])
 
 
+def test_masked_adjoint_of_one_small_unit():
+    """One unit of 100 paths: one work item for a workgroup of four waves, so
+    three waves take no item at all."""
+    m = media(np.full((3, 1), 2.0), np.full((3, 1), 0.9), np.full((3, 1), 0.5),
+              np.full((3, 1), 1.0 / 3))
+    g, _ = geoms(3, 1.4)
+    cR = torch.ones(1, dtype=torch.float32, device="cuda")
+    cB = torch.ones((1, g.n_bins + 2), dtype=torch.float32, device="cuda")
+    res, mask, full, skip = _skip_vs_full(m, g, 100, 3, cR, cB, 1)
+    assert _close(skip[0], full[0]) and _close(skip[1], full[1])
+    assert 0 < int(_popcount(mask)[0]) <= 100
+
+
 def test_masked_layered_adjoint_equals_full_replay():
     wl = workloads.layered_tones(8, paths=1 << 14)
     L = rw.Layers.from_numpy(wl.sigma_t, wl.albedo, wl.g, wl.thickness_mm, wl.n_rel_bottom)
