@@ -73,6 +73,24 @@ def test_dwivedi_walk_matches_the_oracle_on_the_same_streams(q, gmax, n_rel, sla
     assert np.all(np.abs(v - ov) <= 2e-3 * ov + 50), np.abs(v - ov).max()
 
 
+@pytest.mark.parametrize("K", [2, 4])
+def test_dwivedi_walk_with_two_and_four_media(K):
+    """The launch for K = 2 and 4 media against the oracle on the same
+    streams (R, vertex counts)."""
+    rng = np.random.default_rng(40 + K)
+    s, a, g, w = _mixture(rng, 6, K=K, gmax=0.3)
+    N = 1 << 14
+    t, flags, tal, bins, vert = _run_both(s, a, g, w, 1.4, N, 9, 0.6)
+    assert flags == 0
+    R = np64(t.R)
+    m, se = mean_se(R[:, 0], R[:, 1], N)
+    om, ose = mean_se(tal[:, 0], tal[:, 1], N)
+    z = (m - om) / np.hypot(se, ose)
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
+    v, ov = np64(t.vertices), vert.astype(np.float64)
+    assert np.all(np.abs(v - ov) <= 2e-3 * ov + 50), np.abs(v - ov).max()
+
+
 def test_dwivedi_walk_matches_chandrasekhar_and_beats_the_plain_walk():
     """Isotropic, index-matched half-spaces, probability 1: R within 3.5 SE of
     1 - H(1) sqrt(1 - alpha); at alpha = 0.99 the variance x vertices is at
