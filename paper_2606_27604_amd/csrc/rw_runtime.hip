@@ -35,6 +35,9 @@ struct TuneCfg {
   int chunk = 2048;        // paths per work item (multiple of 64)
   int waves_per_wg = 4;    // workgroup = waves_per_wg wavefronts
   int wgs_per_cu = 0;      // persistent grid: workgroups per CU (0: occupancy limit)
+  // the default shape of a batched call: items shrink for calls with few of
+  // them (a shape from the tuner or its cache is kept as it is)
+  bool adapt = false;
 };
 
 // One instantiation of a captured launch sequence and the event recorded after
@@ -355,6 +358,16 @@ rw_status build_plan(rw_context* ctx, Plan& P, const MediaView& media, const rw_
   // max_chunk paths).
   int chunk = cfg.chunk;
   if (paths_uniform > 0 && paths_uniform < chunk) chunk = std::max(64, round_up(paths_uniform, 64));
+  if (cfg.adapt) {
+    // fewer items than about twice the device's resident waves (7 per SIMD):
+    // halve them, down to 512 paths, so that waves done early take more work
+    // instead of the last ones carrying the launch (16 units x 2^20 paths:
+    // 2.57 -> 1.75 ms)
+    const int64_t want = 2 * int64_t(ctx->n_cu) * 28;
+    while (chunk >= 1024 && (chunk / 2) % 64 == 0 &&
+           double(ue - ub) * double((paths_uniform + chunk - 1) / chunk) < double(want))
+      chunk /= 2;
+  }
   if (!adjoint && paths_uniform > chunk) {
     const double slot_bytes = double(forward_slot_words(geom->n_bins)) * 8.0;
     while (paths_uniform > chunk &&
@@ -591,6 +604,7 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
   RW_HIP(ctx, hipEventCreate(&e1));
   float best_ms = 1e30f;
   *best = base.cfg;
+  best->adapt = false;
   for (int chunk : chunks) {
     for (int wpw : wpws) {
      for (int oq : occ_quarters) {
@@ -626,6 +640,7 @@ rw_status autotune(rw_context* ctx, Plan base, bool persistent, rw_tally* out, d
       if (ok && ms_sum < best_ms) {
         best_ms = ms_sum;
         *best = P.cfg;
+        best->adapt = false;  // a measured shape is kept as it is
       }
      }
     }
@@ -835,6 +850,7 @@ rw_status run_walk(rw_context* ctx, const MediaView& media, int64_t n_units,
 
   Plan P;
   TuneCfg cfg;
+  cfg.adapt = batched;
   std::string key;
   if (batched) {
     load_tune_cache(ctx);
