@@ -178,7 +178,10 @@ rw_status rw_forward_noalloc(rw_context* ctx, const rw_media* media, const rw_ge
  * parameter sets x wavelengths with uneven work): a persistent grid pulls
  * (unit, chunk) work items from a device queue, units with the longest
  * estimated paths first, and wavefronts move on to further items without
- * waiting for an item's slowest path.  `paths_per_unit` is a DEVICE int32
+ * waiting for an item's slowest path.  Items hold 2048 paths, or the shape the
+ * autotuner chose; without a tuned shape, a call with fewer items than about
+ * twice the device's resident wavefronts halves them (down to 512 paths) so
+ * that the device stays busy.  `paths_per_unit` is a DEVICE int32
  * array [n_units] (uneven counts allowed, 0 allowed; entries above
  * paths_uniform are clamped to it) or NULL, in which case every unit runs
  * `paths_uniform` paths.  Same random numbers per path as rw_forward, hence
@@ -335,7 +338,8 @@ rw_status rw_layered_hero_forward(rw_context* ctx, const rw_layers* layers,
  * better estimator.  A path whose weight exceeds 2^64 ends with score 0 and
  * raises RW_FLAG_WEIGHT_CAP.  Normal incidence only (RW_E_UNSUPPORTED otherwise); no
  * adjoint.  A device workspace of 8 (2 n_bins + 9) bytes per work item of up
- * to 2048 paths (grown so that it stays within 1 GiB) plus 16 K bytes per unit.
+ * to 2048 paths (512-2048, smaller when the call has few items; grown so that
+ * it stays within 1 GiB) plus 16 K bytes per unit.
  * Asynchronous on `stream`. */
 rw_status rw_dwivedi_forward(rw_context* ctx, const rw_media* media, const rw_geometry* geom,
                              int64_t paths_per_unit, uint64_t seed, float q, rw_tally* out,
