@@ -219,9 +219,11 @@ __device__ __forceinline__ void lds_addd(double* p, double v) {
 }
 
 // per-wave LDS: the medium table (K x 12 floats, padded to 8-byte words), then
-// the sums [bins (n_bins+2) x (sum x, sum x^2) | sum x, sum x^2, T, A]
+// the sums [bins (n_bins+2) x (sum x, sum x^2) | sum x, sum x^2, T, A], then a
+// ring of kDwRing top exits (radius, weight) tallied kWave at a time
 inline __host__ __device__ int dwivedi_acc_words(int n_bins) { return 2 * (n_bins + 2) + 4; }
 constexpr int kDwTableWords = kMaxMedia * kDwFloats / 2;
+constexpr int kDwRing = kWave;
 
 template <int K>
 __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) {
@@ -232,9 +234,10 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
   if (item >= a.n_items) return;  // whole waves
   const int nb = a.w.geo.n_bins;
   const int acc_words = dwivedi_acc_words(nb);
-  double* base = dw_lds + int64_t(wid) * (kDwTableWords + acc_words);
+  double* base = dw_lds + int64_t(wid) * (kDwTableWords + acc_words + kDwRing);
   float* tab = reinterpret_cast<float*>(base);
   double* acc = base + kDwTableWords;
+  float2* ring = reinterpret_cast<float2*>(acc + acc_words);
   const int64_t ul = item / a.chunks_per_unit;
   const int64_t c = item - ul * a.chunks_per_unit;
   const int64_t u = ul;  // the call's units start at 0 of the media view
@@ -259,6 +262,24 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
   // per-lane sums of the item (x, x^2 of top exits, T, A); the radial bins
   // go to LDS (spread over the bins, so few lanes meet on one word)
   double rx = 0.0, rx2 = 0.0, rt = 0.0, ra = 0.0;
+  // top exits wait in the ring and are tallied a full wave at a time: the
+  // bin's logarithm and the FP64 sums then run on all lanes instead of on the
+  // few that leave in a given step
+  uint32_t rn = 0;
+  auto flush_ring = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (uint32_t(lane) < rn) {
+      const float2 r = ring[lane];
+      const int b = radial_slot_r(r.x, geo);
+      const double x = double(r.y);
+      lds_addd(&bins[2 * b], x);
+      lds_addd(&bins[2 * b + 1], x * x);
+      rx += x;
+      rx2 += x * x;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    rn = 0;
+  };
   for (;;) {
     const uint64_t idle = __ballot(!alive);
     if (idle != 0 && cursor < pe) {
@@ -276,6 +297,8 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
       cursor = next < pe ? next : pe;
     }
     if (__ballot(alive) == 0) break;
+    bool top_end = false;
+    float top_r = 0.0f, top_w = 0.0f;
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
       if (alive) {
@@ -306,12 +329,9 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
             verts += v;
             wcapped |= ev == EV_WEIGHT_CAP;
             if (ev == EV_EXIT_TOP) {
-              const int b = radial_slot(p.x, p.y, geo);
-              const double x = double(p.W);
-              lds_addd(&bins[2 * b], x);
-              lds_addd(&bins[2 * b + 1], x * x);
-              rx += x;
-              rx2 += x * x;
+              top_end = true;
+              top_r = exit_radius(p.x, p.y);
+              top_w = p.W;
             } else if (ev == EV_EXIT_BOTTOM) {
               rt += double(p.W);
             }
@@ -322,7 +342,18 @@ __global__ void __launch_bounds__(256) dwivedi_walk_kernel(const DwivediArgs a) 
         }
       }
     }
+    const uint64_t tm = __ballot(top_end);
+    if (tm != 0) {
+      const uint32_t nt = uint32_t(__popcll(tm));
+      if (rn + nt > uint32_t(kDwRing)) flush_ring();
+      if (top_end)
+        ring[rn + __builtin_amdgcn_mbcnt_hi(uint32_t(tm >> 32),
+                                            __builtin_amdgcn_mbcnt_lo(uint32_t(tm), 0u))] =
+            make_float2(top_r, top_w);
+      rn += nt;
+    }
   }
+  flush_ring();
   // the item's sums to its slot (the lanes' sums reduced in a fixed order); the
   // vertex count after them
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -397,7 +428,8 @@ __global__ void __launch_bounds__(kDwConvWords * kDwConvParts)
 }
 
 int dwivedi_lds_bytes(int n_bins, int waves_per_wg) {
-  return waves_per_wg * (kDwTableWords + dwivedi_acc_words(n_bins)) * int(sizeof(double));
+  return waves_per_wg * (kDwTableWords + dwivedi_acc_words(n_bins) + kDwRing) *
+         int(sizeof(double));
 }
 
 int64_t dwivedi_slot_words(int n_bins) { return dwivedi_acc_words(n_bins) + 1; }
