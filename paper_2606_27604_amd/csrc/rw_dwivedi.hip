@@ -129,21 +129,27 @@ __device__ __forceinline__ int dwivedi_step(DwPath& p, uint4 w, const float* tab
   const float zn = fmaf(s, p.uz, p.z);
   const bool top = (p.uz < 0.0f) && (zn <= 0.0f);
   const bool bottom = geo.slab && (p.uz > 0.0f) && (zn >= geo.slab_mm);
-  // the MIS factor of a flight of length l: true density over the mixture,
-  // divided through by the plain technique's e^{-sigma l} (times sigma for a
-  // collision): p_hg / (q p_d f e^{sigma mu_s l / nu0} + (1 - q) p_hg)
-  if (top || bottom) {
-    const float db = (top ? -p.z : (geo.slab_mm - p.z)) * __builtin_amdgcn_rcpf(p.uz);
-    p.x = fmaf(db, p.ux, p.x);
-    p.y = fmaf(db, p.uy, p.y);
-    p.z = top ? 0.0f : geo.slab_mm;
-    if (p.mixed) {
-      const float ex = __builtin_amdgcn_exp2f(sig * p.mu_s * db * inv_nu0 * 1.4426950408889634f);
-      p.W *= p.p_hg * __builtin_amdgcn_rcpf(fmaf(q * p.p_d, ex, (1.0f - q) * p.p_hg));
-      p.mixed = false;
-      p.dw = false;
-      if (!(p.W <= kDwWeightCap)) return EV_WEIGHT_CAP;
-    }
+  const bool hit = top || bottom;
+  // The move and the MIS factor are the same arithmetic for a flight that
+  // reaches a surface after l = db and one that collides after l = s, so all
+  // lanes evaluate them together: true density over the mixture, divided
+  // through by the plain technique's e^{-sigma l} (times sigma for a
+  // collision), p_hg / (q p_d f e^{sigma mu_s l / nu0} + (1 - q) p_hg) with
+  // f = sigma' / sigma after a collision and 1 at a surface
+  const float zs = top ? 0.0f : geo.slab_mm;
+  const float l = hit ? (zs - p.z) * __builtin_amdgcn_rcpf(p.uz) : s;
+  p.x = fmaf(l, p.ux, p.x);
+  p.y = fmaf(l, p.uy, p.y);
+  p.z = hit ? zs : zn;
+  if (p.mixed) {
+    const float ex = __builtin_amdgcn_exp2f(sig * p.mu_s * l * inv_nu0 * 1.4426950408889634f);
+    const float f = hit ? 1.0f : p.sig_d * __builtin_amdgcn_rcpf(sig);
+    p.W *= p.p_hg * __builtin_amdgcn_rcpf(fmaf(q * p.p_d * f, ex, (1.0f - q) * p.p_hg));
+    if (!(p.W <= kDwWeightCap)) return EV_WEIGHT_CAP;
+  }
+  if (hit) {
+    p.mixed = false;
+    p.dw = false;
     if (!geo.index_matched) {
       const float F = fresnel(fabsf(p.uz), geo.n_rel, geo.n_rel2);
       if (u01(w.w) < F) {
@@ -152,15 +158,6 @@ __device__ __forceinline__ int dwivedi_step(DwPath& p, uint4 w, const float* tab
       }
     }
     return top ? EV_EXIT_TOP : EV_EXIT_BOTTOM;
-  }
-  p.x = fmaf(s, p.ux, p.x);
-  p.y = fmaf(s, p.uy, p.y);
-  p.z = zn;
-  if (p.mixed) {
-    const float ex = __builtin_amdgcn_exp2f(sig * p.mu_s * s * inv_nu0 * 1.4426950408889634f);
-    const float f = p.sig_d * __builtin_amdgcn_rcpf(sig);
-    p.W *= p.p_hg * __builtin_amdgcn_rcpf(fmaf(q * p.p_d * f, ex, (1.0f - q) * p.p_hg));
-    if (!(p.W <= kDwWeightCap)) return EV_WEIGHT_CAP;
   }
   const float alb = e[1];
   p.A = fmaf(p.W, 1.0f - alb, p.A);
