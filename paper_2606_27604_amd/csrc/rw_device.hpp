@@ -475,18 +475,24 @@ __device__ __forceinline__ int vertex_step(Path& p, uint4 w, const WalkGeom& geo
 // scattering.
 // The two halves of a collision around the roulette test: the move to the
 // collision point with implicit capture, then the scattering.
+// implicit capture at a collision after a flight of length s (the move made)
 template <bool ADJ>
-__device__ __forceinline__ void absorb_at(Path& p, const VertexDraw& d, float zn) {
-  const float s = d.s;
-  p.x = fmaf(s, p.ux, p.x);
-  p.y = fmaf(s, p.uy, p.y);
-  p.z = zn;
+__device__ __forceinline__ void capture(Path& p, float s) {
   if (ADJ) {
     p.D += p.m.inv_sig - s;
     p.ncoll += 1;
   }
   p.A = fmaf(p.W, 1.0f - p.m.alb, p.A);
   p.W *= p.m.alb;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void absorb_at(Path& p, const VertexDraw& d, float zn) {
+  const float s = d.s;
+  p.x = fmaf(s, p.ux, p.x);
+  p.y = fmaf(s, p.uy, p.y);
+  p.z = zn;
+  capture<ADJ>(p, s);
 }
 
 template <bool ADJ>
@@ -620,13 +626,26 @@ __device__ __forceinline__ int vertex_step_layered(Path& p, uint4 w, const WalkG
     if (p.uz < 0.0f && zn <= p.d) face = 2;
     else if (geo.slab && p.uz > 0.0f && zn >= geo.slab_mm) face = 3;
   }
-  if (face == 0) return collide<ADJ>(p, d, geo, zn);
+  // the move is the same arithmetic for a flight that reaches a face after
+  // l = db and one that collides after l = s, so all lanes make it together
   const float zf = face == 1 ? 0.0f : (face == 2 ? p.d : geo.slab_mm);
-  const float db = (zf - p.z) * __builtin_amdgcn_rcpf(p.uz);
-  p.x = fmaf(db, p.ux, p.x);
-  p.y = fmaf(db, p.uy, p.y);
-  p.z = zf;
-  if (ADJ) p.D -= db;
+  const float l = face != 0 ? (zf - p.z) * __builtin_amdgcn_rcpf(p.uz) : s;
+  p.x = fmaf(l, p.ux, p.x);
+  p.y = fmaf(l, p.uy, p.y);
+  p.z = face != 0 ? zf : zn;
+  if (face == 0) {
+    capture<ADJ>(p, s);
+    if (p.W < geo.rr_weight) {
+      if (u01(d.w3) < geo.rr_survive) {
+        p.W *= geo.rr_boost;
+      } else {
+        return EV_RR_KILL;
+      }
+    }
+    scatter<ADJ>(p, d);
+    return EV_COLLIDE;
+  }
+  if (ADJ) p.D -= l;
   if (face == 2) {
     if (!geo.interface_matched) {
       const float rel = top_layer ? geo.rel_down : geo.rel_up;

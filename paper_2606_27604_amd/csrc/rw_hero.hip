@@ -108,13 +108,15 @@ __device__ __forceinline__ int hero_step(HeroPath<C>& p, uint4 w, const float* t
     if (p.uz < 0.0f && zn <= d) face = 2;
     else if (geo.slab && p.uz > 0.0f && zn >= geo.slab_mm) face = 3;
   }
+  // the move is the same arithmetic for a flight that reaches a face after
+  // l = db and one that collides after l = s, so all lanes make it together
+  const float zf = face == 1 ? 0.0f : (face == 2 ? d : geo.slab_mm);
+  const float l = face != 0 ? (zf - p.z) * __builtin_amdgcn_rcpf(p.uz) : s;
+  p.x = fmaf(l, p.ux, p.x);
+  p.y = fmaf(l, p.uy, p.y);
+  p.z = face != 0 ? zf : zn;
+  if (top_layer) p.L0 += l; else p.L1 += l;
   if (face != 0) {
-    const float zf = face == 1 ? 0.0f : (face == 2 ? d : geo.slab_mm);
-    const float db = (zf - p.z) * __builtin_amdgcn_rcpf(p.uz);
-    p.x = fmaf(db, p.ux, p.x);
-    p.y = fmaf(db, p.uy, p.y);
-    p.z = zf;
-    if (top_layer) p.L0 += db; else p.L1 += db;
     if (face == 2) {
       if (!geo.interface_matched) {
         const float rel = top_layer ? geo.rel_down : geo.rel_up;
@@ -145,10 +147,7 @@ __device__ __forceinline__ int hero_step(HeroPath<C>& p, uint4 w, const float* t
   }
   // collision: every member's weight times its albedo, roulette on the
   // largest, the hero's scattering and every member's phase density of it
-  p.x = fmaf(s, p.ux, p.x);
-  p.y = fmaf(s, p.uy, p.y);
-  p.z = zn;
-  if (top_layer) { p.L0 += s; ++p.nc0; } else { p.L1 += s; ++p.nc1; }
+  if (top_layer) ++p.nc0; else ++p.nc1;
   float wmax = 0.0f;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
