@@ -62,22 +62,26 @@ ISSUE_PEAK = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ  # lane-slots / s
 # Algorithmic work of one vertex (what the method computes, not loop control),
 # in VALU lane-slots: each op weighted by its issue cost relative to a full-rate
 # FP32 FMA, as measured by `bench.py --micro` on the MI355X
-# (profiles/issue_rates_micro.md).
+# (profiles/issue_rates_micro.md).  The counts are those of the compiled
+# plain-collision vertex (its draw, then the straight-line step), without
+# register moves, draw addressing or the ballot:
 #   random numbers: one Philox4x32-10 block = 10 rounds x (2 32x32->64
-#     multiply-adds + 2 three-input XORs, one v_bitop3_b32 each); 4 word->float
-#     conversions (2 ops each);
-#   free flight: log, 1 mul, 1 fma; surface test: 2 compares;
-#   collision: position 2 fma, absorbed-weight fma + sub, weight mul, roulette
-#     compare; Henyey-Greenstein inversion ~12 ops + rcp; scattering frame and
-#     rotation ~30 ops + sqrt, sin, cos and the frame's rcp, renormalised by one
-#     Newton fma;
-#   surface hit (about 1 vertex in 20): distance rcp + 3 ops, Fresnel ~15 ops +
-#     sqrt + rcp.
+#     multiply-adds + 2 three-input XORs, one v_bitop3_b32 each);
+#   the draw (26): 4 word->float conversions (shift, or, subtract, ~10 ops),
+#     the flight's scale, the Henyey-Greenstein inversion (~10 ops), sin(theta)
+#     from (1 - mu)(1 + mu) (2), the in-plane components (2); with log, rcp,
+#     sqrt, sin and cos;
+#   the step (35): flight end depth and the surface and roulette tests (5),
+#     position (2), implicit capture (1; the weight product is the roulette
+#     test's), the Duff et al. frame and rotation (~20) with the frame's rcp,
+#     the renormalisation by one Newton step (7);
+#   a surface hit (about 1 vertex in 20): distance rcp + 3 ops, Fresnel ~15 ops
+#     + sqrt + rcp.
 # The adjoint adds the score bookkeeping: flight-length sum (2), collision
 # count (1), g-score fma chain (2).
 ALG_MAD64_PER_VERTEX = 20
 ALG_XOR3_PER_VERTEX = 20
-ALG_FP32_PER_VERTEX = 66          # add/mul/fma/compare/select/convert, incl. word->float
+ALG_FP32_PER_VERTEX = 62          # 26 + 35 + 1/20 of a surface hit's 18
 ALG_FP32_ADJ_EXTRA = 5
 ALG_TRANS_PER_VERTEX = 6.15       # log, 2 rcp, sqrt, sin, cos + 1/20 x (3 at a surface hit)
 # measured issue costs (FMA = 1); a transcendental is priced amid FMA work
@@ -877,8 +881,9 @@ def layered_tones(rw, torch, args):
                      "traffic": load_traffic("walk_kernel<2, forward, layered>"),
                      "counters": load_counters("walk_kernel<2, forward, layered>"),
                      "kernel": "walk_kernel<2, forward, layered>", "slots_per_vertex": slots,
-                     "note": "slot model of the mixture forward vertex (the interface adds "
-                             "work only at crossing vertices)"},
+                     "note": "slot model of the mixture forward vertex; the ~1 % of vertices "
+                             "that cross the interface, reflect or leave are priced as "
+                             "collisions"},
     }
     # the adjoint replay of the same walk (rw_layered_adjoint), R and bin cotangents
     n = wl.n_units
