@@ -787,7 +787,8 @@ def check_dwivedi_closed_forms(paths=1 << 17, seed=32, k=3.5):
     """The Dwivedi walk is unbiased: (i) isotropic index-matched half-spaces
     against Chandrasekhar's 1 - H(1) sqrt(1 - alpha), technique probability 1
     and 0.5; (ii) anisotropic media, some with a Fresnel surface, against
-    adding-doubling (probabilities 0.3-1)."""
+    adding-doubling (probabilities 0.2-1), forward-peaked ones (g = 0.9) among
+    them at albedos where the weights' variance stays finite."""
     from oracle import adding_doubling as AD
 
     zs = []
@@ -797,7 +798,8 @@ def check_dwivedi_closed_forms(paths=1 << 17, seed=32, k=3.5):
         tal, _, _ = O.dwivedi_forward(geo, np.ones(3), al, np.zeros(3), np.ones(3), paths, seed, q)
         m, se = mean_se(tal[:, 0], tal[:, 1], paths)
         zs += list((m - np.array([cf.R_plane(a) for a in al])) / se)
-    for a, g, n, q in ((0.7, 0.5, 1.4, 0.5), (0.9, 0.3, 1.4, 0.3), (0.6, -0.3, 1.0, 1.0)):
+    for a, g, n, q in ((0.7, 0.5, 1.4, 0.5), (0.9, 0.3, 1.4, 0.3), (0.6, -0.3, 1.0, 1.0),
+                       (0.9, 0.9, 1.4, 0.2), (0.95, 0.9, 1.0, 0.2)):
         geo = O.Geometry(n_media=1, n_rel=n)
         tal, _, _ = O.dwivedi_forward(geo, [2.0], [a], [g], [1.0], paths, seed + 1, q)
         m, se = mean_se(tal[0, 0], tal[0, 1], paths)
