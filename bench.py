@@ -575,7 +575,9 @@ def dwivedi_leg(ctx, rw, api, workloads, torch, args):
     vertices, per unit the efficiency gain (SE^2 x time of the plain walk over
     that of the Dwivedi walk), median and 10-90 % range, and the z-scores of
     the two estimates of R (heavy-tailed weights show as a low bias there: the
-    sample SE then understates the error)."""
+    sample SE then understates the error), and per unit the weight balance
+    (R + T + A) / (paths x (1 - F(0))), which is 1 in expectation and falls
+    short when the sample misses the weights' tail."""
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -601,6 +603,9 @@ def dwivedi_leg(ctx, rw, api, workloads, torch, args):
         se_d = dw.R_se.cpu().numpy()
         gain = (se_p ** 2 * t_p) / (se_d ** 2 * t_d)
         z = (dw.R - plain.R).cpu().numpy() / np.hypot(se_p, se_d)
+        f0 = ((wl.n_rel - 1.0) / (wl.n_rel + 1.0)) ** 2
+        sums = dw.tally.R.cpu().numpy()
+        balance = (sums[:, 0] + sums[:, 2] + sums[:, 3]) / (N * (1.0 - f0))
         res[name] = {"units": wl.n_units, "paths_per_unit": N, "q": q,
                      "plain_ms": t_p, "dwivedi_ms": t_d,
                      "plain_vertices": int(plain.vertices.sum()),
@@ -609,7 +614,9 @@ def dwivedi_leg(ctx, rw, api, workloads, torch, args):
                      "efficiency_gain_p10_p90": [float(np.quantile(gain, 0.1)),
                                                  float(np.quantile(gain, 0.9))],
                      "R_z_vs_plain_median_abs": float(np.median(np.abs(z))),
-                     "R_z_vs_plain_max_abs": float(np.max(np.abs(z)))}
+                     "R_z_vs_plain_max_abs": float(np.max(np.abs(z))),
+                     "weight_balance_median": float(np.median(balance)),
+                     "weight_balance_min": float(np.min(balance))}
     return res
 
 
