@@ -73,6 +73,34 @@ def test_dwivedi_walk_matches_the_oracle_on_the_same_streams(q, gmax, n_rel, sla
     assert np.all(np.abs(v - ov) <= 2e-3 * ov + 50), np.abs(v - ov).max()
 
 
+def test_dwivedi_walk_in_forward_peaked_media():
+    """Forward-peaked media (g 0.8-0.9) at albedos where the weights' variance
+    stays finite (0.85-0.95), technique probability 0.2, a Fresnel surface:
+    R and the vertex counts against the oracle on the same streams, and the
+    weight balance R + A of each unit within 6 % of 1 - F(0) (about three of
+    its standard errors at 2^14 paths; a run that misses the weights' tail
+    falls far below, as at alpha = 0.999, g = 0.9)."""
+    rng = np.random.default_rng(91)
+    n, K = 8, 3
+    s = rng.uniform(2.0, 20.0, (K, n))
+    a = rng.uniform(0.85, 0.95, (K, n))
+    g = rng.uniform(0.8, 0.9, (K, n))
+    w = rng.dirichlet(np.ones(K), n).T
+    N = 1 << 14
+    t, flags, tal, bins, vert = _run_both(s, a, g, w, 1.4, N, 13, 0.2)
+    assert flags == 0
+    R = np64(t.R)
+    m, se = mean_se(R[:, 0], R[:, 1], N)
+    om, ose = mean_se(tal[:, 0], tal[:, 1], N)
+    z = (m - om) / np.hypot(se, ose)
+    assert np.all(np.abs(z) <= SAME_STREAM_Z), np.abs(z).max()
+    v, ov = np64(t.vertices), vert.astype(np.float64)
+    assert np.all(np.abs(v - ov) <= 2e-3 * ov + 50), np.abs(v - ov).max()
+    f0 = (0.4 / 2.4) ** 2
+    balance = (R[:, 0] + R[:, 3]) / (N * (1.0 - f0))
+    assert np.all(np.abs(balance - 1.0) <= 0.06), balance
+
+
 @pytest.mark.parametrize("K", [2, 4])
 def test_dwivedi_walk_with_two_and_four_media(K):
     """The launch for K = 2 and 4 media against the oracle on the same
