@@ -263,8 +263,8 @@ def main():
     ap.add_argument("--layers-photons", type=int, default=1 << 16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the walk shards by unit with no communication, and "
-              "this build runs on a single MI355X; --gpus above 1 is not supported.",
+        print("bench.py measures one MI355X: the walk would shard by unit with no "
+              "communication, but no multi-GPU path is built; --gpus above 1 is not supported.",
               file=sys.stderr)
         sys.exit(2)
 
