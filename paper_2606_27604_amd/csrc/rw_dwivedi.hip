@@ -436,6 +436,8 @@ int64_t dwivedi_slot_words(int n_bins) { return dwivedi_acc_words(n_bins) + 1; }
 
 template <int K>
 static hipError_t launch_dwivedi_k(const DwivediArgs& a, int wpw, hipStream_t s) {
+  // the walk kernel is built for at most 256 threads per workgroup
+  if (wpw < 1 || wpw * kWave > 256) return hipErrorInvalidValue;
   const int64_t blocks = (a.n_items + wpw - 1) / wpw;
   const size_t lds = size_t(dwivedi_lds_bytes(a.w.geo.n_bins, wpw));
   if (a.n_units > 0)

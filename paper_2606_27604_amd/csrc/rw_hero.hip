@@ -365,6 +365,7 @@ __global__ void __launch_bounds__(256) hero_convert_kernel(const HeroArgs a) {
 template <int C>
 static hipError_t launch_hero_c(const HeroArgs& a, hipStream_t s) {
   constexpr int wpw = 4;
+  static_assert(wpw * kWave <= 256, "hero_walk_kernel is built for at most 256 threads");
   const int64_t blocks = (a.n_items + wpw - 1) / wpw;
   const size_t lds = size_t(wpw) * C * 2 * kHeroFloats * sizeof(float);
   if (blocks > 0)
